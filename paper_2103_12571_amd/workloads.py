@@ -1,0 +1,136 @@
+"""Seeded synthetic workloads shaped like the paper's test problems.
+
+This module holds inputs only - grid sizes, PDE coefficients, step counts and
+seeded initial data - and none of the method's arithmetic.  It is the one
+module shared by the HIP path's callers (tests, bench) and the CPU oracle.
+
+The paper's own problems are periodic heat and advection equations on the unit
+square (Sec. 5, eqs. (heat), (advection)); the workloads below keep that
+structure (periodic constant-coefficient stencils, Radau IIA with M = 3, L a
+power of two) at the sizes used for measurement.
+"""
+from dataclasses import dataclass, field, replace
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    kind: str            # heat1d | heat2d | adv1d_c4 | advdiff2d
+    nx: int
+    ny: int
+    L: int
+    M: int
+    dt: float
+    nu: float = 0.0
+    vel: tuple = (0.0, 0.0)
+    batch: int = 1
+    init: str = "modes"  # sine | modes | gauss
+    alpha: float = 0.0   # fixed alpha (0 -> adaptive rule of Alg. 2)
+    stop: str = "laststep"   # laststep | residual
+    tol: float = 1e-12
+    inner: str = "cocg"      # cocg | bicgstab | fft
+    inner_tol: float = 1e-12
+    precision: str = "fp64"  # fp64 | mixed
+    seed: int = 2103
+    target_seed: int = 12103
+
+    @property
+    def N(self):
+        return self.nx * self.ny
+
+    @property
+    def dof(self):
+        return self.batch * self.L * self.M * self.N
+
+    def with_(self, **kw):
+        return replace(self, **kw)
+
+
+WORKLOADS = {
+    # 1D heat nu=0.1, N=64, L=4, dt=0.01, u0 = sin(2 pi x), fixed alpha 1e-3,
+    # Richardson until the relative residual is 1e-12.
+    "heat1d_64": Workload("heat1d_64", "heat1d", 64, 1, 4, 3, 0.01, nu=0.1, init="sine",
+                          alpha=1e-3, stop="residual", tol=1e-12),
+    # 2D heat nu=1e-2 on 256^2, L=64, dt=1e-3, 16 seeded Fourier modes, adaptive alpha, COCG.
+    "heat2d_256": Workload("heat2d_256", "heat2d", 256, 256, 64, 3, 1e-3, nu=1e-2, init="modes",
+                           tol=1e-11, inner="cocg"),
+    # 1D advection c=1, N=4096, 4th-order central, L=128, dt=1e-3, Gaussian + noise.
+    "adv1d_4096": Workload("adv1d_4096", "adv1d_c4", 4096, 1, 128, 3, 1e-3, vel=(1.0, 0.0),
+                           init="gauss", tol=1e-11, inner="bicgstab"),
+    # 2D heat nu=1e-2 on 1024^2, L=32, dt=1e-3; complex64 inner solves.
+    "heat2d_1024_mixed": Workload("heat2d_1024_mixed", "heat2d", 1024, 1024, 32, 3, 1e-3, nu=1e-2,
+                                  init="modes", tol=1e-10, inner="cocg", precision="mixed",
+                                  inner_tol=1e-6),
+    # 2D advection-diffusion nu=5e-3, v=(1, 0.5) on 512^2, L=64, B=8; adjoint.
+    "advdiff2d_512_adj": Workload("advdiff2d_512_adj", "advdiff2d", 512, 512, 64, 3, 1e-3, nu=5e-3,
+                                  vel=(1.0, 0.5), batch=8, init="modes", tol=1e-10,
+                                  inner="bicgstab", precision="mixed", inner_tol=1e-6),
+}
+
+
+def grid(w):
+    x = np.arange(w.nx) / w.nx
+    y = np.arange(w.ny) / w.ny
+    return x, y
+
+
+def fourier_modes(nx, ny, seed, nmodes=16, kmax=8):
+    """sum_j a_j cos(2 pi (kx_j x + ky_j y) + phi_j); per mode draw kx, ky, a, phi.
+
+    (kx, ky) uniform integers in [-kmax, kmax]^2 without (0, 0) (redrawn),
+    a ~ N(0, 1), phi ~ U[0, 2 pi), numpy default_rng(seed).  For ny = 1 the
+    ky draw is kept (and ignored) so the stream layout does not depend on ny.
+    """
+    rng = np.random.default_rng(seed)
+    x = np.arange(nx) / nx
+    y = np.arange(ny) / ny
+    X, Y = np.meshgrid(x, y)
+    u = np.zeros((ny, nx))
+    for _ in range(nmodes):
+        while True:
+            kx, ky = (int(v) for v in rng.integers(-kmax, kmax + 1, size=2))
+            if ny == 1:
+                ky = 0
+            if kx != 0 or ky != 0:
+                break
+        a = rng.normal()
+        phi = rng.uniform(0.0, 2.0 * np.pi)
+        u += a * np.cos(2.0 * np.pi * (kx * X + ky * Y) + phi)
+    return u.reshape(-1)
+
+
+def initial_condition(w, b=0):
+    """u0 for instance b (seed w.seed + b)."""
+    x, _ = grid(w)
+    if w.init == "sine":
+        return np.sin(2.0 * np.pi * x).astype(np.float64)
+    if w.init == "gauss":
+        rng = np.random.default_rng(w.seed + b)
+        return np.exp(-(x - 0.5) ** 2 / (2 * 0.05 ** 2)) + 1e-3 * rng.standard_normal(w.nx)
+    if w.init == "modes":
+        return fourier_modes(w.nx, w.ny, w.seed + b)
+    raise ValueError(w.init)
+
+
+def initial_batch(w):
+    return np.stack([initial_condition(w, b) for b in range(w.batch)])
+
+
+def target_batch(w):
+    """u_target for the adjoint loss: a seeded Fourier-mode field per instance."""
+    return np.stack([fourier_modes(w.nx, w.ny, w.target_seed + b) for b in range(w.batch)])
+
+
+def small(w, nx=None, ny=None, L=None, batch=None):
+    """A reduced copy of a workload (same structure) for parity tests."""
+    kw = {}
+    if nx is not None:
+        kw["nx"] = nx
+    if ny is not None:
+        kw["ny"] = ny
+    if L is not None:
+        kw["L"] = L
+    if batch is not None:
+        kw["batch"] = batch
+    return replace(w, **kw)
