@@ -1,0 +1,235 @@
+/*
+ * aao.h - C ABI of libaao.so: the alpha-circulant preconditioned Richardson
+ * sweep for the all-at-once collocation system of a linear IVP u' = A u, on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Caklovic, Speck, Frank, "A parallel-in-time collocation method using
+ * diagonalization: theory and implementation for linear problems",
+ * arXiv 2103.12571.
+ *
+ *   C u = w,  C = I_L (x) C_coll + E (x) H          (Sec. 2.1, eq. (globalsys))
+ *   C_coll = I_MN - dT Q (x) A,  H = H_M (x) I_N     (Sec. 2.1, eq. (Hm))
+ *   C_alpha = I_L (x) C_coll + E_alpha (x) H         (Sec. 2.2, eq. (prec))
+ *   u <- u + C_alpha^{-1} (w - C u)                  (eq. (Riteration), defect-
+ *                                                     correction form)
+ *
+ * C_alpha^{-1} is applied as in Alg. 1: scale by J^{-1}, DFT over the L steps
+ * (Lemma 1), per step the M x M eigenbasis S_l^{-1} of Q G_l^{-1} (Sec. 2.3,
+ * eq. (QGL)), L*M decoupled complex-shifted spatial solves
+ * (I - dT d_lm A) x2 = x1 (eq. (innerdiag)), then S_l, G_l^{-1}, inverse DFT
+ * and J.  Only the L/2+1 non-redundant frequencies are solved: for real data
+ * frequency L-j is the complex conjugate of frequency j.
+ *
+ * Conventions
+ *  - Every array argument named *_dev is a DEVICE pointer, owned by the
+ *    caller, FP64, contiguous, C order.  u, r, lambda are [B][L][M][N];
+ *    u0, g_last, grad_u0 are [B][N]; grad_nu is [B].  n = y*nx + x.
+ *  - Host pointers (struct members, alphas, info) are read during the call
+ *    only; the library keeps copies of what it needs.
+ *  - All device work is enqueued on the stream given to aao_setup (or
+ *    aao_set_stream).  Calls that return norms or status synchronise that
+ *    stream before returning.
+ *  - Device memory: the library allocates only a small table block (per-plan
+ *    coefficient tables, a few KB per alpha) and pinned host staging.  All
+ *    large scratch (inner-solve vectors, partial sums) lives in a caller-
+ *    provided workspace (aao_workspace_size / aao_set_workspace).
+ *  - Errors: every call returns an aao_status; AAO_OK is 0, errors are
+ *    negative.  No call aborts or throws across the ABI.  On error
+ *    aao_last_error() returns a thread-local message.  Argument checks run
+ *    before any launch, so an EINVAL/EWORKSPACE/ENODIAG return leaves device
+ *    memory untouched.
+ *  - A plan is not thread-safe; distinct plans may be used concurrently on
+ *    distinct streams.
+ */
+#ifndef AAO_H
+#define AAO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct aao_plan* aao_plan_t;
+
+typedef enum {
+  AAO_OK = 0,
+  AAO_EINVAL = -1,      /* invalid argument (sizes, pointers, alpha outside (0,1)) */
+  AAO_EHIP = -2,        /* a HIP runtime call failed */
+  AAO_ENODIAG = -3,     /* Q G_l^{-1} not (well) diagonalisable for this alpha
+                           (Sec. 2.3: eigenvalues coalesce, Examples 1-2) */
+  AAO_ENOCONV = -4,     /* aao_solve / adjoint: max_iter sweeps without meeting tol */
+  AAO_ESTAGNATE = -5,   /* reserved */
+  AAO_EWORKSPACE = -6,  /* no workspace set, or smaller than aao_workspace_size */
+  AAO_ENAN = -7,        /* a norm became NaN or Inf */
+  AAO_ESTATE = -8       /* call order violated (e.g. sweep before aao_set_u0) */
+} aao_status;
+
+enum { AAO_FP64 = 0,   /* every step in FP64 / complex128 */
+       AAO_MIXED = 1   /* inner solves stored and computed in complex64; residual,
+                          alpha scaling, DFT over L, M x M transforms and the
+                          update of u stay FP64 (Theorem 2: round-off grows like
+                          alpha^{-(l-1)/L}) */ };
+
+enum { AAO_INNER_COCG = 0,      /* batched COCG: needs A = A^T (complex-symmetric
+                                   shifted systems) */
+       AAO_INNER_BICGSTAB = 1,  /* batched BiCGStab: any A */
+       AAO_INNER_FFT = 2        /* spatial-FFT direct solve (exact for periodic
+                                   constant-coefficient A); nx, ny powers of two */ };
+
+enum { AAO_STOP_LASTSTEP = 0,   /* ||u_L^{k+1} - u_L^k||_inf <= tol (Sec. 3.2, Alg. 2) */
+       AAO_STOP_RESIDUAL = 1    /* ||w - C u||_2 / ||w||_2 <= tol */ };
+
+/* A periodic constant-coefficient stencil:
+ *   (A v)[x, y] = sum_t coef[t] * v[(x + dx[t]) mod nx, (y + dy[t]) mod ny].
+ * ndim 1 uses ny = 1 and ignores dy.  |dx|, |dy| <= 4, ntaps <= 32.
+ * dcoef_dnu (nullable) holds dA/dnu with the same taps, used by aao_grad. */
+typedef struct {
+  int ndim;
+  int64_t nx, ny;
+  int ntaps;
+  const int32_t* dx;
+  const int32_t* dy;          /* nullable when ndim == 1 */
+  const double* coef;
+  const double* dcoef_dnu;    /* nullable */
+} aao_stencil;
+
+typedef struct {
+  int M;                /* collocation nodes per step, 1..8 */
+  const double* nodes;  /* NULL: Radau-right nodes (Sec. 2.1, Sec. 2.3); else M
+                           increasing nodes in (0, 1] with nodes[M-1] == 1 */
+  int L;                /* steps solved at once; power of two, 1..1024 */
+  double dt;            /* step size dT > 0 */
+  int batch;            /* B >= 1 independent instances sharing A */
+  int precision;        /* AAO_FP64 | AAO_MIXED */
+  int inner;            /* AAO_INNER_* */
+  double inner_tol;     /* relative residual per shifted system (tau) */
+  int inner_maxit;      /* iteration cap per shifted system (Krylov) */
+} aao_config;
+
+#define AAO_MAX_HIST 64
+typedef struct {
+  int iterations;                    /* sweeps performed */
+  int converged;                     /* 1 if the stop rule was met */
+  double gamma, m0;                  /* Alg. 2 quantities actually used */
+  double alpha[AAO_MAX_HIST];        /* alpha_k of sweep k */
+  double m[AAO_MAX_HIST];            /* m_k bound of Alg. 2 after sweep k */
+  double res_rel[AAO_MAX_HIST];      /* ||w - C u^k||_2 / ||w||_2 before sweep k */
+  double dlast_inf[AAO_MAX_HIST];    /* ||u_L^{k+1} - u_L^k||_inf of sweep k */
+  double inner_mean[AAO_MAX_HIST];   /* mean Krylov iterations per system, sweep k */
+  int inner_max[AAO_MAX_HIST];       /* max Krylov iterations over systems, sweep k */
+} aao_solve_info;
+
+/* Per kernel class: launches, elements processed, event-timed milliseconds and
+ * algorithmic bytes moved.  Timing is collected only while enabled by
+ * aao_set_timing(plan, 1).  Classes: see aao_kernel_name(). */
+#define AAO_NUM_KERNELS 12
+typedef struct {
+  int64_t launches[AAO_NUM_KERNELS];
+  double elements[AAO_NUM_KERNELS];
+  double bytes[AAO_NUM_KERNELS];
+  double ms[AAO_NUM_KERNELS];
+} aao_kernel_stats;
+
+/* Create a plan for the composite collocation problem of Sec. 2.1 with
+ * stencil A, nodes/Q, L steps of size dt (eq. (globalsys)).
+ * Computes nodes and Q (eq. (collocation)) on the host, uploads the stencil and
+ * the DFT twiddles.  hip_stream: a hipStream_t (NULL = default stream).
+ * Errors: EINVAL for bad sizes/pointers, COCG with a non-symmetric stencil,
+ * FFT inner solve with non-power-of-two nx/ny; EHIP. */
+aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stream,
+                     aao_plan_t* out);
+
+/* Rebind the plan to another stream. */
+aao_status aao_set_stream(aao_plan_t plan, void* hip_stream);
+
+/* Bytes of device workspace the plan needs (256-byte aligned pointer). */
+aao_status aao_workspace_size(aao_plan_t plan, size_t* bytes);
+
+/* Hand the plan a device workspace of at least aao_workspace_size bytes.  The
+ * caller keeps ownership and must keep it alive while the plan uses it. */
+aao_status aao_set_workspace(aao_plan_t plan, void* dev_ptr, size_t bytes);
+
+/* Set the initial value u0_dev [B][N]; defines w = (1_M (x) u0, 0, ..., 0)
+ * (eq. (globalsys) with b = 0).  The pointer is kept (not copied): u0 must stay
+ * valid and unchanged while the plan uses it. */
+aao_status aao_set_u0(aao_plan_t plan, const double* u0_dev);
+
+/* Row a1: r = w - C u (eq. (globalsys)), r_dev [B][L][M][N].  res_norm
+ * (nullable host out) = ||r||_2 / ||w||_2. */
+aao_status aao_residual(aao_plan_t plan, const double* u_dev, double* r_dev, double* res_norm);
+
+/* Rows a2-a4: delta = C_alpha^{-1} r via Alg. 1's diagonalised steps
+ * (Lemma 1; eqs. (s123), (innercoll), (innerdiag), (QGL)).  r_dev and
+ * delta_dev are [B][L][M][N]; they may alias.  alpha in (0, 1).
+ * Errors: EINVAL, ENODIAG, EWORKSPACE, ESTATE. */
+aao_status aao_precond(aao_plan_t plan, const double* r_dev, double* delta_dev, double alpha);
+
+/* One sweep of eq. (Riteration) in defect-correction form on u_dev (in place):
+ * u <- u + C_alpha^{-1}(w - C u).  res_rel (nullable host out): relative
+ * residual of u BEFORE the sweep; dlast_inf (nullable host out):
+ * ||u_L^{new} - u_L^{old}||_inf over all M nodes of the last step. */
+aao_status aao_sweep(aao_plan_t plan, double* u_dev, double alpha, double* res_rel,
+                     double* dlast_inf);
+
+/* Alg. 2 (or a given alpha list): initialise u = (u0, ..., u0) (Sec. 5),
+ * then sweep until the stop rule holds or max_iter sweeps are done.
+ * alphas == NULL: adaptive alpha_{k+1} = sqrt(gamma/m_k), m_{k+1} =
+ * 2 sqrt(m_k gamma), gamma = L (3 eps + tau) ||w||_inf (Sec. 3.3), clamped to
+ * alpha <= 1/2; m0 <= 0 selects m0 = L dT ||A||_inf ||u0||_inf (Sec. 3.3).
+ * With AAO_MIXED the same balance is taken for the defect-correction form,
+ * whose round-off is relative to the current residual: alpha = min(1/2,
+ * sqrt(L (3 eps + tau))) with eps = 2^-24 (eq. (minimeq) on a relative model).
+ * alphas != NULL: sweep k uses alphas[min(k, n_alphas-1)].
+ * Returns ENOCONV (info filled) when max_iter is reached. */
+aao_status aao_solve(aao_plan_t plan, double* u_dev, const double* alphas, int n_alphas,
+                     double m0, double tol, int stop_rule, int max_iter, aao_solve_info* info);
+
+/* Adjoint: solve C^T lambda = g, g = e_{L,M} (x) g_last, by the same
+ * alpha-circulant machinery transposed (E_alpha^T = V^{-T} D_alpha V^T, Lemma
+ * 1 transposed): per sweep lambda <- lambda + C_alpha^{-T}(g - C^T lambda).
+ * g_last_dev [B][N], lambda_dev [B][L][M][N] (output; initialised to zero).
+ * Stop rule: ||lambda_1^{k+1} - lambda_1^k||_inf <= tol (the first step carries
+ * the largest round-off in the transposed sweep) or max_iter. Alpha rule as
+ * in aao_solve with ||g||_inf in gamma. */
+aao_status aao_adjoint_solve(aao_plan_t plan, const double* g_last_dev, double* lambda_dev,
+                             const double* alphas, int n_alphas, double m0, double tol,
+                             int max_iter, aao_solve_info* info);
+
+/* Gradients of J = 1/2 ||u_{L,M} - u_target||^2 given the forward solution
+ * u_dev and the adjoint lambda_dev: grad_u0 = sum_m lambda_{1,m} [B][N];
+ * grad_nu[b] = dT sum_l lambda_l^T (Q (x) dA/dnu) u_l [B] (needs dcoef_dnu). */
+aao_status aao_grad(aao_plan_t plan, const double* u_dev, const double* lambda_dev,
+                    double* grad_u0_dev, double* grad_nu_dev);
+
+/* Row a3 alone: solve (I - shift_s A) x_s = b_s for S systems of length N in
+ * the plan's inner solver and precision.  shifts: host, 2*S doubles (re, im);
+ * b_dev, x_dev: device complex128, [S][N] interleaved (re, im).  S must not
+ * exceed B*(L/2+1)*M.  iters (nullable host out, S ints): iterations used. */
+aao_status aao_shifted_solve(aao_plan_t plan, int S, const double* shifts, const double* b_dev,
+                             double* x_dev, int* iters);
+
+/* Kernel statistics (cumulative since the last reset) and event timing. */
+aao_status aao_set_timing(aao_plan_t plan, int on);
+aao_status aao_get_stats(aao_plan_t plan, aao_kernel_stats* out);
+aao_status aao_reset_stats(aao_plan_t plan);
+const char* aao_kernel_name(int kernel_class);
+
+/* Per-alpha host tables for inspection: d_j, r_j (eq. (QGL)) and the
+ * eigenvalues d_jm of Q G_j^{-1} for the L/2+1 frequencies j, plus the largest
+ * condition number of S_j.  d, r: 2*(L/2+1) doubles; djm: 2*(L/2+1)*M doubles.
+ * Any output may be NULL. */
+aao_status aao_tables(aao_plan_t plan, double alpha, double* d, double* r, double* djm,
+                      double* cond_max);
+
+/* Collocation nodes and Q (row-major M x M) the plan uses. */
+aao_status aao_collocation(aao_plan_t plan, double* nodes, double* Q);
+
+const char* aao_last_error(void);
+void aao_destroy(aao_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AAO_H */

@@ -1,0 +1,907 @@
+// C ABI of libaao.so (declared in include/aao.h): plans, workspace, the
+// per-alpha host tables, the sweep (rows a1-a4), Alg. 2 (row a5), the
+// transposed sweep and the gradients.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "aao.h"
+#include "aao_host.hpp"
+#include "aao_kernels.hpp"
+
+using aao::cd;
+
+namespace {
+
+thread_local std::string g_err;
+
+aao_status fail(aao_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(AAO_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2(int64_t v) {
+  int l = 0;
+  while ((int64_t(1) << l) < v) ++l;
+  return l;
+}
+
+constexpr int kWorkSlots = 32;     // [class] for k > 0, [16 + class] for k == 0
+constexpr int kCheckEvery = 8;     // Krylov iterations between host convergence checks
+constexpr int kNormBlocks = 256;
+
+struct Timed {
+  int cls;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct aao_plan {
+  // problem
+  int ndim = 1, nx = 0, ny = 1, N = 0, M = 0, L = 0, logL = 0, Lh = 0, B = 1;
+  int precision = AAO_FP64, inner = AAO_INNER_COCG, inner_maxit = 1000;
+  double dt = 0, inner_tol = 1e-12;
+  std::vector<double> t, Q, QT;
+  aao::Taps taps{}, tapsT{}, dtaps{};
+  bool has_dnu = false, symmetric = false;
+  double Anorm_inf = 0;
+  hipStream_t stream = nullptr;
+  // transforms over l
+  int TN = 2, logTN = 1, ntiles = 0;
+  // inner solves
+  int S = 0, wps = 1, chunk = 256, nvec = 0;
+  bool f32 = false;
+  size_t csize = 16;
+  // library-owned device tables and pinned staging
+  char* dtab = nullptr;
+  size_t off_tw = 0, off_sf = 0, off_sb = 0, off_m1 = 0, off_m2 = 0, off_sh = 0, off_q = 0,
+         off_hostend = 0, tab_bytes = 0;
+  char* htab = nullptr;      // pinned mirror of the alpha-dependent tables
+  char* hread = nullptr;     // pinned readback area
+  size_t hread_bytes = 0;
+  double cached_alpha = -1;
+  int cached_adj = -1;
+  // caller workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0, ws_need = 0;
+  size_t off_vec = 0, off_part = 0, off_st = 0, off_fb = 0, off_norms = 0, off_cnt = 0,
+         off_work = 0, off_gpart = 0, off_npart = 0;
+  int fb_slots = 0, grad_blocks = 0;
+  // state
+  const double* u0 = nullptr;
+  double w2 = 0, winf = 0;
+  // stats
+  bool timing = false;
+  aao_kernel_stats stats{};
+  std::vector<Timed> pending;
+  std::vector<hipEvent_t> pool;
+  unsigned long long work_seen[kWorkSlots] = {};
+
+  void* vec(int i) const { return ws + off_vec + (size_t)i * S * N * csize; }
+  double* part() const { return reinterpret_cast<double*>(ws + off_part); }
+  aao::SysState* st() const { return reinterpret_cast<aao::SysState*>(ws + off_st); }
+  double* fb() const { return reinterpret_cast<double*>(ws + off_fb); }
+  double* norms() const { return reinterpret_cast<double*>(ws + off_norms); }
+  int* cnt() const { return reinterpret_cast<int*>(ws + off_cnt); }
+  unsigned long long* work() const { return reinterpret_cast<unsigned long long*>(ws + off_work); }
+  double* gpart() const { return reinterpret_cast<double*>(ws + off_gpart); }
+  double* npart() const { return reinterpret_cast<double*>(ws + off_npart); }
+  double2* d_tw() const { return reinterpret_cast<double2*>(dtab + off_tw); }
+  double* d_sf() const { return reinterpret_cast<double*>(dtab + off_sf); }
+  double* d_sb() const { return reinterpret_cast<double*>(dtab + off_sb); }
+  double2* d_m1() const { return reinterpret_cast<double2*>(dtab + off_m1); }
+  double2* d_m2() const { return reinterpret_cast<double2*>(dtab + off_m2); }
+  double2* d_sh() const { return reinterpret_cast<double2*>(dtab + off_sh); }
+  double* d_q() const { return reinterpret_cast<double*>(dtab + off_q); }
+};
+
+namespace {
+
+// ------------------------------------------------------------------ timing
+hipEvent_t get_event(aao_plan* p) {
+  if (!p->pool.empty()) {
+    hipEvent_t e = p->pool.back();
+    p->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+template <typename F>
+hipError_t timed(aao_plan* p, int cls, F&& launch) {
+  p->stats.launches[cls] += 1;
+  if (!p->timing) return launch();
+  hipEvent_t a = get_event(p), b = get_event(p);
+  if (!a || !b) return launch();
+  hipEventRecord(a, p->stream);
+  hipError_t e = launch();
+  hipEventRecord(b, p->stream);
+  p->pending.push_back({cls, a, b});
+  return e;
+}
+
+// Call after the stream has been synchronised.
+void collect_timing(aao_plan* p) {
+  for (auto& t : p->pending) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) p->stats.ms[t.cls] += ms;
+    p->pool.push_back(t.a);
+    p->pool.push_back(t.b);
+  }
+  p->pending.clear();
+}
+
+// ------------------------------------------------------------------ tables
+// alpha-dependent tables for the primal (adj = 0) or transposed (adj = 1)
+// sweep: scale before/after the DFT over l, the node transforms of each
+// frequency and the shifts dT d_jm of the inner systems.
+aao_status upload_tables(aao_plan* p, double alpha, int adj) {
+  if (!(alpha > 0.0 && alpha < 1.0))
+    return fail(AAO_EINVAL, "alpha must lie in (0, 1), got " + std::to_string(alpha));
+  if (alpha == p->cached_alpha && adj == p->cached_adj) return AAO_OK;
+  const int M = p->M, L = p->L, Lh = p->Lh;
+  double* sf = reinterpret_cast<double*>(p->htab + (p->off_sf - p->off_sf));
+  double* sb = reinterpret_cast<double*>(p->htab + (p->off_sb - p->off_sf));
+  cd* m1 = reinterpret_cast<cd*>(p->htab + (p->off_m1 - p->off_sf));
+  cd* m2 = reinterpret_cast<cd*>(p->htab + (p->off_m2 - p->off_sf));
+  cd* sh = reinterpret_cast<cd*>(p->htab + (p->off_sh - p->off_sf));
+  // Lemma 1: J^{-1} = diag(alpha^{(l-1)/L}) before the DFT, J and the 1/L of the
+  // inverse DFT after it.  Transposed (V^T = (1/L) F J, V^{-T} = J^{-1} F^*):
+  // J and 1/L before an inverse DFT, J^{-1} after a forward DFT.
+  for (int l = 0; l < L; ++l) {
+    const double up = std::pow(alpha, (double)l / L);
+    const double dn = std::pow(alpha, -(double)l / L);
+    sf[l] = adj ? dn / L : up;
+    sb[l] = adj ? up : dn / L;
+  }
+  for (int j = 0; j < Lh; ++j) {
+    aao::FreqTable ft;
+    std::string why = aao::freq_table(p->t, p->Q, alpha, L, j, ft);
+    if (!why.empty())
+      return fail(AAO_ENODIAG, "alpha=" + std::to_string(alpha) + ", frequency " + std::to_string(j) +
+                                   ": " + why);
+    cd* A1 = m1 + (size_t)j * M * M;
+    cd* A2 = m2 + (size_t)j * M * M;
+    for (int m = 0; m < M; ++m)
+      for (int k = 0; k < M; ++k) {
+        if (!adj) {
+          // x1 = S^{-1} x (eq. (innerdiag)); y = G^{-1} S x2 with G^{-1} = I - r H_M (eq. (QGL))
+          A1[m * M + k] = ft.Sinv[m * M + k];
+          A2[m * M + k] = ft.S[m * M + k] - ft.r * ft.S[(M - 1) * M + k];
+        } else {
+          // transposed: x1 = S^T G^{-T} x, (G^{-T})[i][k] = delta_ik - r delta_{i,M-1}
+          // (G^{-T} = I - r H_M^T), so (S^T G^{-T})[m][k] = S[k][m] - r S[M-1][m];
+          // y = S^{-T} x2
+          A1[m * M + k] = ft.S[k * M + m] - ft.r * ft.S[(M - 1) * M + m];
+          A2[m * M + k] = ft.Sinv[k * M + m];
+        }
+      }
+    for (int b = 0; b < p->B; ++b)
+      for (int m = 0; m < M; ++m) sh[((size_t)b * Lh + j) * M + m] = p->dt * ft.lam[m];
+  }
+  const size_t bytes = p->off_hostend - p->off_sf;
+  HIPCHK(hipMemcpyAsync(p->dtab + p->off_sf, p->htab, bytes, hipMemcpyHostToDevice, p->stream));
+  p->cached_alpha = alpha;
+  p->cached_adj = adj;
+  return AAO_OK;
+}
+
+aao::FwdArgs fwd_args(aao_plan* p, const double* in, int adj) {
+  aao::FwdArgs a{};
+  a.u = in;
+  a.w0 = p->u0;
+  a.out = p->vec(1);  // the Krylov right-hand side / residual buffer R
+  a.scale = p->d_sf();
+  a.tw = p->d_tw();
+  a.mix = p->d_m1();
+  a.part = p->fb();
+  a.g = {p->nx, p->ny, p->N};
+  a.taps = adj ? p->tapsT : p->taps;
+  const std::vector<double>& q = adj ? p->QT : p->Q;
+  for (int i = 0; i < p->M * p->M; ++i) a.q[i] = q[i];
+  a.dt = p->dt;
+  a.L = p->L;
+  a.logL = p->logL;
+  a.Lh = p->Lh;
+  a.TN = p->TN;
+  a.logTN = p->logTN;
+  return a;
+}
+
+aao::BwdArgs bwd_args(aao_plan* p, double* u) {
+  aao::BwdArgs a{};
+  a.in = p->vec(0);  // Krylov solution X
+  a.u = u;
+  a.scale = p->d_sb();
+  a.tw = p->d_tw();
+  a.mix = p->d_m2();
+  a.part = p->fb() + p->fb_slots;
+  a.g = {p->nx, p->ny, p->N};
+  a.L = p->L;
+  a.logL = p->logL;
+  a.Lh = p->Lh;
+  a.TN = p->TN;
+  a.logTN = p->logTN;
+  return a;
+}
+
+aao::KrylovArgs krylov_args(aao_plan* p, int adj, int nsys) {
+  aao::KrylovArgs a{};
+  a.X = p->vec(0);
+  a.R = p->vec(1);
+  a.P[0] = p->vec(2);
+  a.P[1] = p->vec(3);
+  a.V[0] = p->vec(4);
+  a.V[1] = p->nvec > 5 ? p->vec(5) : nullptr;
+  a.Rh = p->nvec > 6 ? p->vec(6) : nullptr;
+  a.S = p->nvec > 7 ? p->vec(7) : nullptr;
+  a.T = p->nvec > 8 ? p->vec(8) : nullptr;
+  a.shift = p->d_sh();
+  a.st = p->st();
+  a.part = p->part();
+  a.work = p->work();
+  a.g = {p->nx, p->ny, p->N};
+  a.taps = adj ? p->tapsT : p->taps;
+  a.num_sys = nsys;
+  a.wps = p->wps;
+  a.chunk = p->chunk;
+  a.tol2 = p->inner_tol * p->inner_tol;
+  a.maxit = p->inner_maxit;
+  return a;
+}
+
+// Solve the nsys shifted systems held in R into X.  Fills the per-system
+// iteration counts into p->hread (as SysState) after the final check.
+aao_status inner_solve(aao_plan* p, int adj, int nsys) {
+  aao::KrylovArgs a = krylov_args(p, adj, nsys);
+  HIPCHK(aao::launch_krylov_init(a, p->stream));
+  int* hcnt = reinterpret_cast<int*>(p->hread);
+  for (int k = 0; k <= p->inner_maxit; ++k) {
+    if (p->inner == AAO_INNER_COCG) {
+      HIPCHK(timed(p, aao::KC_COCG_A, [&] { return aao::launch_cocg_a(p->f32, a, k, p->stream); }));
+      if (k < p->inner_maxit)
+        HIPCHK(timed(p, aao::KC_COCG_B, [&] { return aao::launch_cocg_b(p->f32, a, k, p->stream); }));
+    } else {
+      HIPCHK(timed(p, aao::KC_BICG_1, [&] { return aao::launch_bicg(1, p->f32, a, k, p->stream); }));
+      if (k < p->inner_maxit) {
+        HIPCHK(timed(p, aao::KC_BICG_2, [&] { return aao::launch_bicg(2, p->f32, a, k, p->stream); }));
+        HIPCHK(timed(p, aao::KC_BICG_3, [&] { return aao::launch_bicg(3, p->f32, a, k, p->stream); }));
+      }
+    }
+    if ((k + 1) % kCheckEvery == 0 || k == p->inner_maxit) {
+      HIPCHK(timed(p, aao::KC_MISC, [&] { return aao::launch_count_active(p->st(), nsys, p->cnt(), p->stream); }));
+      HIPCHK(hipMemcpyAsync(hcnt, p->cnt(), sizeof(int), hipMemcpyDeviceToHost, p->stream));
+      HIPCHK(hipStreamSynchronize(p->stream));
+      if (*hcnt == 0) break;
+    }
+  }
+  return AAO_OK;
+}
+
+struct SweepOut {
+  double res2 = 0, dmax = 0;
+  double inner_mean = 0;
+  int inner_max = 0, inner_fail = 0;
+};
+
+// Read norms and per-system Krylov statistics (synchronises the stream).
+aao_status read_back(aao_plan* p, int nsys, bool want_norms, SweepOut& o) {
+  double* hn = reinterpret_cast<double*>(p->hread + 64);
+  aao::SysState* hs = reinterpret_cast<aao::SysState*>(p->hread + 128);
+  if (want_norms) HIPCHK(hipMemcpyAsync(hn, p->norms(), 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  if (nsys > 0)
+    HIPCHK(hipMemcpyAsync(hs, p->st(), (size_t)nsys * sizeof(aao::SysState), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  collect_timing(p);
+  if (want_norms) {
+    o.res2 = hn[0];
+    o.dmax = hn[1];
+  }
+  double sum = 0;
+  for (int s = 0; s < nsys; ++s) {
+    sum += hs[s].iters;
+    o.inner_max = std::max(o.inner_max, hs[s].iters);
+    if (hs[s].flag != 0) o.inner_fail += 1;
+  }
+  o.inner_mean = nsys ? sum / nsys : 0;
+  return AAO_OK;
+}
+
+// Device table block, pinned staging and the static tables (twiddles, Q); done
+// once, on the first aao_set_workspace, so that aao_setup stays host-only.
+aao_status alloc_tables(aao_plan* p) {
+  if (p->dtab) return AAO_OK;
+  HIPCHK(hipMalloc(&p->dtab, p->tab_bytes));
+  HIPCHK(hipHostMalloc(&p->htab, p->tab_bytes, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc(&p->hread, p->hread_bytes, hipHostMallocDefault));
+  std::vector<double2> tw(p->L / 2 + 1);
+  for (int k = 0; k < (int)tw.size(); ++k) {
+    const double ang = -2.0 * M_PI * (double)k / (double)p->L;
+    tw[k].x = std::cos(ang);
+    tw[k].y = std::sin(ang);
+  }
+  HIPCHK(hipMemcpyAsync(p->dtab + p->off_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice,
+                        p->stream));
+  HIPCHK(hipMemcpyAsync(p->dtab + p->off_q, p->Q.data(), p->Q.size() * sizeof(double), hipMemcpyHostToDevice,
+                        p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->cached_alpha = -1;
+  return AAO_OK;
+}
+
+aao_status need_ready(aao_plan* p, bool need_u0) {
+  if (!p) return fail(AAO_EINVAL, "null plan");
+  if (!p->ws || p->ws_bytes < p->ws_need) return fail(AAO_EWORKSPACE, "workspace not set or too small");
+  if (need_u0 && !p->u0) return fail(AAO_ESTATE, "aao_set_u0 has not been called");
+  return AAO_OK;
+}
+
+// One sweep; res_stop > 0 stops before the update if ||r||/||w|| <= res_stop.
+aao_status do_sweep(aao_plan* p, double* u, double alpha, int adj, double res_stop,
+                    SweepOut& o, bool& stopped) {
+  stopped = false;
+  aao_status s = upload_tables(p, alpha, adj);
+  if (s != AAO_OK) return s;
+  aao::FwdArgs fa = fwd_args(p, u, adj);
+  const bool f32 = p->f32;
+  HIPCHK(timed(p, aao::KC_FWD, [&] { return aao::launch_fwd(p->M, adj, false, f32, fa, p->B, p->stream); }));
+  const int nt = p->ntiles * p->B;
+  if (res_stop > 0) {
+    HIPCHK(timed(p, aao::KC_MISC, [&] { return aao::launch_finalize(p->fb(), nt, p->fb(), 0, p->norms(), p->stream); }));
+    SweepOut pre;
+    s = read_back(p, 0, true, pre);
+    if (s != AAO_OK) return s;
+    o.res2 = pre.res2;
+    if (!std::isfinite(pre.res2)) return fail(AAO_ENAN, "residual norm is not finite");
+    if (std::sqrt(pre.res2) <= res_stop * std::sqrt(adj ? 0.0 : p->w2)) {
+      stopped = true;
+      return AAO_OK;
+    }
+  }
+  s = inner_solve(p, adj, p->S);
+  if (s != AAO_OK) return s;
+  aao::BwdArgs ba = bwd_args(p, u);
+  HIPCHK(timed(p, aao::KC_BWD, [&] { return aao::launch_bwd(p->M, adj, false, f32, ba, p->B, p->stream); }));
+  HIPCHK(timed(p, aao::KC_MISC, [&] {
+    return aao::launch_finalize(p->fb(), nt, p->fb() + p->fb_slots, nt, p->norms(), p->stream);
+  }));
+  double keep = o.res2;
+  s = read_back(p, p->S, true, o);
+  if (s != AAO_OK) return s;
+  if (res_stop > 0) o.res2 = keep;
+  if (!std::isfinite(o.res2) || !std::isfinite(o.dmax)) return fail(AAO_ENAN, "sweep produced a non-finite norm");
+  return AAO_OK;
+}
+
+aao_status fill_taps(aao::Taps& t, int n, const int32_t* dx, const int32_t* dy, const double* c, int ndim) {
+  t.n = n;
+  for (int i = 0; i < n; ++i) {
+    t.dx[i] = dx[i];
+    t.dy[i] = (ndim == 2 && dy) ? dy[i] : 0;
+    t.c[i] = c[i];
+  }
+  return AAO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* aao_last_error(void) { return g_err.c_str(); }
+
+const char* aao_kernel_name(int c) {
+  static const char* names[AAO_NUM_KERNELS] = {
+      "fwd_residual_dft_l", "bwd_idft_l_update", "cocg_matvec", "cocg_update",
+      "bicgstab_p_matvec", "bicgstab_s_matvec", "bicgstab_update", "fft_inner",
+      "residual", "misc", "init", "grad"};
+  return (c >= 0 && c < AAO_NUM_KERNELS) ? names[c] : "";
+}
+
+aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stream, aao_plan_t* out) {
+  if (!A || !cfg || !out) return fail(AAO_EINVAL, "null argument");
+  *out = nullptr;
+  if (A->ndim != 1 && A->ndim != 2) return fail(AAO_EINVAL, "ndim must be 1 or 2");
+  const int64_t nx = A->nx, ny = (A->ndim == 1) ? 1 : A->ny;
+  if (nx < 2 || ny < 1 || (A->ndim == 2 && ny < 2)) return fail(AAO_EINVAL, "grid too small");
+  if (nx * ny > (int64_t(1) << 28)) return fail(AAO_EINVAL, "grid too large (N <= 2^28)");
+  if (A->ntaps < 1 || A->ntaps > aao::kMaxTaps) return fail(AAO_EINVAL, "ntaps must be in 1..32");
+  if (!A->dx || !A->coef || (A->ndim == 2 && !A->dy)) return fail(AAO_EINVAL, "null stencil array");
+  for (int i = 0; i < A->ntaps; ++i) {
+    const int dxv = A->dx[i], dyv = A->ndim == 2 ? A->dy[i] : 0;
+    if (std::abs(dxv) > 4 || std::abs(dyv) > 4 || std::abs(dxv) >= nx || (A->ndim == 2 && std::abs(dyv) >= ny))
+      return fail(AAO_EINVAL, "tap offsets must satisfy |d| <= 4 and |d| < grid size");
+    if (!std::isfinite(A->coef[i])) return fail(AAO_EINVAL, "non-finite stencil coefficient");
+  }
+  if (cfg->M < 1 || cfg->M > aao::kMaxM) return fail(AAO_EINVAL, "M must be in 1..8");
+  if (!is_pow2(cfg->L) || cfg->L > 1024) return fail(AAO_EINVAL, "L must be a power of two in 1..1024");
+  if ((int64_t)cfg->L * cfg->M > 2048) return fail(AAO_EINVAL, "L*M must not exceed 2048");
+  if (!(cfg->dt > 0) || !std::isfinite(cfg->dt)) return fail(AAO_EINVAL, "dt must be positive");
+  if (cfg->batch < 1) return fail(AAO_EINVAL, "batch must be >= 1");
+  if (cfg->precision != AAO_FP64 && cfg->precision != AAO_MIXED) return fail(AAO_EINVAL, "bad precision");
+  if (cfg->inner != AAO_INNER_COCG && cfg->inner != AAO_INNER_BICGSTAB)
+    return fail(AAO_EINVAL, "inner solver not available (COCG or BiCGStab)");
+  if (!(cfg->inner_tol > 0) || cfg->inner_maxit < 1) return fail(AAO_EINVAL, "bad inner tolerance / iteration cap");
+
+  aao_plan* p = new aao_plan();
+  p->ndim = A->ndim;
+  p->nx = (int)nx;
+  p->ny = (int)ny;
+  p->N = (int)(nx * ny);
+  p->M = cfg->M;
+  p->L = cfg->L;
+  p->logL = ilog2(cfg->L);
+  p->Lh = cfg->L / 2 + 1;
+  p->B = cfg->batch;
+  p->dt = cfg->dt;
+  p->precision = cfg->precision;
+  p->inner = cfg->inner;
+  p->inner_tol = cfg->inner_tol;
+  p->inner_maxit = cfg->inner_maxit;
+  p->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  p->f32 = (cfg->precision == AAO_MIXED);
+  p->csize = p->f32 ? 8 : 16;
+
+  // nodes and Q (Sec. 2.1, eq. (collocation))
+  if (cfg->nodes) {
+    p->t.assign(cfg->nodes, cfg->nodes + cfg->M);
+    for (int m = 0; m < cfg->M; ++m)
+      if (!(p->t[m] > (m ? p->t[m - 1] : 0.0)) || p->t[m] > 1.0) {
+        delete p;
+        return fail(AAO_EINVAL, "nodes must increase in (0, 1]");
+      }
+    if (p->t[cfg->M - 1] != 1.0) {
+      delete p;
+      return fail(AAO_EINVAL, "the last node must be 1 (H_M copies the last node)");
+    }
+  } else if (!aao::radau_right_nodes(cfg->M, p->t)) {
+    delete p;
+    return fail(AAO_EINVAL, "Radau node computation failed");
+  }
+  aao::collocation_matrix(p->t, p->Q);
+  p->QT.assign(p->M * p->M, 0.0);
+  for (int m = 0; m < p->M; ++m)
+    for (int k = 0; k < p->M; ++k) p->QT[m * p->M + k] = p->Q[k * p->M + m];
+
+  fill_taps(p->taps, A->ntaps, A->dx, A->dy, A->coef, A->ndim);
+  std::vector<int32_t> rdx(A->ntaps), rdy(A->ntaps);
+  for (int i = 0; i < A->ntaps; ++i) {
+    rdx[i] = -A->dx[i];
+    rdy[i] = A->ndim == 2 ? -A->dy[i] : 0;
+  }
+  fill_taps(p->tapsT, A->ntaps, rdx.data(), rdy.data(), A->coef, A->ndim);
+  p->has_dnu = A->dcoef_dnu != nullptr;
+  if (p->has_dnu) fill_taps(p->dtaps, A->ntaps, A->dx, A->dy, A->dcoef_dnu, A->ndim);
+  // symmetry of A (needed by COCG: I - c A complex-symmetric)
+  {
+    bool sym = true;
+    for (int i = 0; i < A->ntaps && sym; ++i) {
+      double c = 0;
+      for (int k = 0; k < A->ntaps; ++k)
+        if (p->taps.dx[k] == -p->taps.dx[i] && p->taps.dy[k] == -p->taps.dy[i]) c += p->taps.c[k];
+      double ci = 0;
+      for (int k = 0; k < A->ntaps; ++k)
+        if (p->taps.dx[k] == p->taps.dx[i] && p->taps.dy[k] == p->taps.dy[i]) ci += p->taps.c[k];
+      if (std::abs(c - ci) > 1e-14 * std::max(1.0, std::abs(ci))) sym = false;
+    }
+    p->symmetric = sym;
+  }
+  if (p->inner == AAO_INNER_COCG && !p->symmetric) {
+    delete p;
+    return fail(AAO_EINVAL, "COCG needs a symmetric stencil (A = A^T); use BiCGStab");
+  }
+  for (int i = 0; i < A->ntaps; ++i) p->Anorm_inf += std::abs(A->coef[i]);
+
+  // tiling of the DFT over l: TN spatial points per workgroup, LDS <= 48 KB
+  int TN = 64;
+  while (TN > 2 && (size_t)p->L * p->M * TN * 8 > 48 * 1024) TN >>= 1;
+  p->TN = TN;
+  p->logTN = ilog2(TN);
+  p->ntiles = (p->N + TN - 1) / TN;
+
+  // batched inner solves: S systems, wps workgroups per system
+  p->S = p->B * p->Lh * p->M;
+  p->nvec = (p->inner == AAO_INNER_COCG) ? 5 : 9;
+  {
+    const int target = 4096;
+    int wps = (target + p->S - 1) / p->S;
+    wps = std::max(1, std::min(wps, (p->N + 1023) / 1024));
+    int chunk = (p->N + wps - 1) / wps;
+    chunk = ((chunk + aao::kBlock - 1) / aao::kBlock) * aao::kBlock;
+    p->chunk = chunk;
+    p->wps = (p->N + chunk - 1) / chunk;
+  }
+  p->fb_slots = std::max(p->ntiles * p->B, 1024);
+  p->grad_blocks = std::max(1, std::min(256, (p->N + aao::kBlock - 1) / aao::kBlock));
+
+  // workspace layout
+  size_t off = 0;
+  p->off_vec = off;
+  off = align256(off + (size_t)p->nvec * p->S * p->N * p->csize);
+  p->off_part = off;
+  off = align256(off + (size_t)aao::QP_COUNT * p->S * p->wps * sizeof(double));
+  p->off_st = off;
+  off = align256(off + (size_t)p->S * sizeof(aao::SysState));
+  p->off_fb = off;
+  off = align256(off + 2 * (size_t)p->fb_slots * sizeof(double));
+  p->off_norms = off;
+  off = align256(off + 8 * sizeof(double));
+  p->off_cnt = off;
+  off = align256(off + 16 * sizeof(int));
+  p->off_work = off;
+  off = align256(off + kWorkSlots * sizeof(unsigned long long));
+  p->off_gpart = off;
+  off = align256(off + (size_t)p->B * p->grad_blocks * sizeof(double));
+  p->off_npart = off;
+  off = align256(off + 2 * kNormBlocks * sizeof(double));
+  p->ws_need = off;
+
+  // library-owned tables
+  size_t t = 0;
+  p->off_tw = t;
+  t = align256(t + (size_t)(p->L / 2 + 1) * sizeof(double2));
+  p->off_q = t;
+  t = align256(t + (size_t)p->M * p->M * sizeof(double));
+  p->off_sf = t;
+  t = align256(t + (size_t)p->L * sizeof(double));
+  p->off_sb = t;
+  t = align256(t + (size_t)p->L * sizeof(double));
+  p->off_m1 = t;
+  t = align256(t + (size_t)p->Lh * p->M * p->M * sizeof(double2));
+  p->off_m2 = t;
+  t = align256(t + (size_t)p->Lh * p->M * p->M * sizeof(double2));
+  p->off_sh = t;
+  t = align256(t + (size_t)p->S * sizeof(double2));
+  p->off_hostend = t;
+  p->tab_bytes = t;
+  p->hread_bytes = 128 + (size_t)p->S * sizeof(aao::SysState) + 64;
+  *out = p;
+  return AAO_OK;
+}
+
+aao_status aao_set_stream(aao_plan_t p, void* s) {
+  if (!p) return fail(AAO_EINVAL, "null plan");
+  p->stream = reinterpret_cast<hipStream_t>(s);
+  return AAO_OK;
+}
+
+aao_status aao_workspace_size(aao_plan_t p, size_t* bytes) {
+  if (!p || !bytes) return fail(AAO_EINVAL, "null argument");
+  *bytes = p->ws_need;
+  return AAO_OK;
+}
+
+aao_status aao_set_workspace(aao_plan_t p, void* dev, size_t bytes) {
+  if (!p || !dev) return fail(AAO_EINVAL, "null argument");
+  if ((reinterpret_cast<uintptr_t>(dev) & 255) != 0) return fail(AAO_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < p->ws_need)
+    return fail(AAO_EWORKSPACE, "workspace of " + std::to_string(bytes) + " bytes < required " +
+                                    std::to_string(p->ws_need));
+  aao_status st = alloc_tables(p);
+  if (st != AAO_OK) return st;
+  p->ws = reinterpret_cast<char*>(dev);
+  p->ws_bytes = bytes;
+  HIPCHK(hipMemsetAsync(p->work(), 0, kWorkSlots * sizeof(unsigned long long), p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  std::memset(p->work_seen, 0, sizeof(p->work_seen));
+  return AAO_OK;
+}
+
+aao_status aao_set_u0(aao_plan_t p, const double* u0) {
+  aao_status s = need_ready(p, false);
+  if (s != AAO_OK) return s;
+  if (!u0) return fail(AAO_EINVAL, "null u0");
+  HIPCHK(aao::launch_norms_bn(u0, p->B, p->N, p->npart(), kNormBlocks, p->stream));
+  std::vector<double> h(2 * kNormBlocks);
+  HIPCHK(hipMemcpyAsync(h.data(), p->npart(), h.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  double s2 = 0, mx = 0;
+  for (int i = 0; i < kNormBlocks; ++i) {
+    s2 += h[2 * i];
+    mx = std::max(mx, h[2 * i + 1]);
+  }
+  if (!std::isfinite(s2)) return fail(AAO_ENAN, "u0 contains NaN or Inf");
+  p->u0 = u0;
+  p->w2 = p->M * s2;  // ||w||_2^2 = M ||u0||^2
+  p->winf = mx;
+  return AAO_OK;
+}
+
+aao_status aao_residual(aao_plan_t p, const double* u, double* r, double* res_norm) {
+  aao_status s = need_ready(p, true);
+  if (s != AAO_OK) return s;
+  if (!u || !r) return fail(AAO_EINVAL, "null array");
+  aao::FwdArgs fa = fwd_args(p, u, 0);
+  const int nblk = std::min(1024, std::max(1, (int)(((int64_t)p->B * p->L * p->N + 255) / 256)));
+  HIPCHK(timed(p, aao::KC_RESIDUAL, [&] { return aao::launch_residual(p->M, false, fa, r, p->B, p->stream); }));
+  HIPCHK(aao::launch_finalize(p->fb(), nblk, p->fb(), 0, p->norms(), p->stream));
+  SweepOut o;
+  s = read_back(p, 0, true, o);
+  if (s != AAO_OK) return s;
+  if (res_norm) *res_norm = std::sqrt(o.res2) / std::sqrt(p->w2);
+  return AAO_OK;
+}
+
+aao_status aao_precond(aao_plan_t p, const double* r, double* delta, double alpha) {
+  aao_status s = need_ready(p, false);
+  if (s != AAO_OK) return s;
+  if (!r || !delta) return fail(AAO_EINVAL, "null array");
+  s = upload_tables(p, alpha, 0);
+  if (s != AAO_OK) return s;
+  aao::FwdArgs fa = fwd_args(p, r, 0);
+  HIPCHK(timed(p, aao::KC_FWD, [&] { return aao::launch_fwd(p->M, false, true, p->f32, fa, p->B, p->stream); }));
+  s = inner_solve(p, 0, p->S);
+  if (s != AAO_OK) return s;
+  aao::BwdArgs ba = bwd_args(p, delta);
+  HIPCHK(timed(p, aao::KC_BWD, [&] { return aao::launch_bwd(p->M, false, true, p->f32, ba, p->B, p->stream); }));
+  SweepOut o;
+  return read_back(p, p->S, false, o);
+}
+
+aao_status aao_sweep(aao_plan_t p, double* u, double alpha, double* res_rel, double* dlast_inf) {
+  aao_status s = need_ready(p, true);
+  if (s != AAO_OK) return s;
+  if (!u) return fail(AAO_EINVAL, "null u");
+  SweepOut o;
+  bool stopped;
+  s = do_sweep(p, u, alpha, 0, 0.0, o, stopped);
+  if (s != AAO_OK) return s;
+  if (res_rel) *res_rel = std::sqrt(o.res2) / std::sqrt(p->w2);
+  if (dlast_inf) *dlast_inf = o.dmax;
+  return AAO_OK;
+}
+
+static aao_status run_solve(aao_plan_t p, double* u, const double* alphas, int n_alphas, double m0,
+                            double tol, int stop_rule, int max_iter, aao_solve_info* info, int adj,
+                            double gnorm_inf) {
+  if (!info) return fail(AAO_EINVAL, "null info");
+  if (max_iter < 1) return fail(AAO_EINVAL, "max_iter must be >= 1");
+  if (alphas && n_alphas < 1) return fail(AAO_EINVAL, "n_alphas must be >= 1");
+  if (stop_rule != AAO_STOP_LASTSTEP && stop_rule != AAO_STOP_RESIDUAL) return fail(AAO_EINVAL, "bad stop rule");
+  if (adj && stop_rule != AAO_STOP_LASTSTEP) return fail(AAO_EINVAL, "adjoint supports the last-step rule only");
+  std::memset(info, 0, sizeof(*info));
+  // Alg. 2 (Sec. 3.3): gamma = L (3 eps + tau) ||w||_inf; eps is the unit
+  // roundoff of the inner-solve precision.
+  const double eps = p->f32 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
+  const double wi = adj ? gnorm_inf : p->winf;
+  const double gamma = p->L * (3 * eps + p->inner_tol) * wi;
+  double m = m0 > 0 ? m0 : (adj ? wi : p->L * p->dt * p->Anorm_inf * p->winf);
+  info->gamma = gamma;
+  info->m0 = m;
+  for (int k = 0; k < max_iter; ++k) {
+    double alpha;
+    if (alphas) {
+      alpha = alphas[std::min(k, n_alphas - 1)];
+    } else if (p->f32) {
+      // Complex64 inner solves: in the defect-correction form the error of a
+      // sweep is relative to the current residual, m_{k+1} = alpha m_k +
+      // (gamma_r / alpha) m_k with gamma_r = L (3 eps + tau); minimising over
+      // alpha as in eq. (minimeq) gives the constant alpha = sqrt(gamma_r).
+      const double gr = p->L * (3 * eps + p->inner_tol);
+      alpha = std::min(std::sqrt(gr), 0.5);
+      m = m * (alpha + gr / alpha);
+    } else {
+      if (m <= tol) {  // Alg. 2 loop condition: the error model is below tol
+        info->converged = 1;
+        return AAO_OK;
+      }
+      alpha = std::min(std::sqrt(gamma / m), 0.5);
+      m = 2 * std::sqrt(m * gamma);
+    }
+    SweepOut o;
+    bool stopped = false;
+    aao_status s = AAO_ENODIAG;
+    for (int tries = 0; tries < 6 && s == AAO_ENODIAG; ++tries) {
+      s = do_sweep(p, u, alpha, adj, stop_rule == AAO_STOP_RESIDUAL ? tol : 0.0, o, stopped);
+      if (s == AAO_ENODIAG && alphas) return s;
+      if (s == AAO_ENODIAG) alpha = std::min(alpha * 1.05, 0.5);  // step off a non-diagonalisable alpha
+    }
+    if (s != AAO_OK) return s;
+    const double wn = std::sqrt(adj ? 1.0 : p->w2);
+    if (k < AAO_MAX_HIST) {
+      info->alpha[k] = alpha;
+      info->m[k] = m;
+      info->res_rel[k] = std::sqrt(o.res2) / wn;
+      info->dlast_inf[k] = stopped ? 0.0 : o.dmax;
+      info->inner_mean[k] = o.inner_mean;
+      info->inner_max[k] = o.inner_max;
+    }
+    if (stopped) {
+      info->iterations = k;
+      info->converged = 1;
+      return AAO_OK;
+    }
+    info->iterations = k + 1;
+    if (stop_rule == AAO_STOP_LASTSTEP && o.dmax <= tol) {
+      info->converged = 1;
+      return AAO_OK;
+    }
+  }
+  return fail(AAO_ENOCONV, "no convergence within max_iter sweeps");
+}
+
+aao_status aao_solve(aao_plan_t p, double* u, const double* alphas, int n_alphas, double m0, double tol,
+                     int stop_rule, int max_iter, aao_solve_info* info) {
+  aao_status s = need_ready(p, true);
+  if (s != AAO_OK) return s;
+  if (!u) return fail(AAO_EINVAL, "null u");
+  HIPCHK(timed(p, aao::KC_INIT, [&] { return aao::launch_init_u(u, p->u0, p->B, p->L, p->M, p->N, p->stream); }));
+  return run_solve(p, u, alphas, n_alphas, m0, tol, stop_rule, max_iter, info, 0, 0.0);
+}
+
+aao_status aao_adjoint_solve(aao_plan_t p, const double* g_last, double* lam, const double* alphas,
+                             int n_alphas, double m0, double tol, int max_iter, aao_solve_info* info) {
+  aao_status s = need_ready(p, false);
+  if (s != AAO_OK) return s;
+  if (!g_last || !lam) return fail(AAO_EINVAL, "null array");
+  HIPCHK(aao::launch_norms_bn(g_last, p->B, p->N, p->npart(), kNormBlocks, p->stream));
+  std::vector<double> h(2 * kNormBlocks);
+  HIPCHK(hipMemcpyAsync(h.data(), p->npart(), h.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  double gi = 0, g2 = 0;
+  for (int i = 0; i < kNormBlocks; ++i) {
+    g2 += h[2 * i];
+    gi = std::max(gi, h[2 * i + 1]);
+  }
+  if (!std::isfinite(g2)) return fail(AAO_ENAN, "g_last contains NaN or Inf");
+  HIPCHK(timed(p, aao::KC_INIT, [&] { return aao::launch_fill(lam, 0.0, (int64_t)p->B * p->L * p->M * p->N, p->stream); }));
+  const double* keep_u0 = p->u0;
+  p->u0 = g_last;  // w0 of the transposed residual
+  aao_status r = (gi == 0.0) ? AAO_OK
+                             : run_solve(p, lam, alphas, n_alphas, m0, tol, AAO_STOP_LASTSTEP, max_iter, info, 1, gi);
+  if (gi == 0.0) {
+    std::memset(info, 0, sizeof(*info));
+    info->converged = 1;
+  }
+  p->u0 = keep_u0;
+  return r;
+}
+
+aao_status aao_grad(aao_plan_t p, const double* u, const double* lam, double* gu0, double* gnu) {
+  aao_status s = need_ready(p, false);
+  if (s != AAO_OK) return s;
+  if (!u || !lam || !gu0 || !gnu) return fail(AAO_EINVAL, "null array");
+  if (!p->has_dnu) return fail(AAO_EINVAL, "stencil has no dcoef_dnu");
+  aao::Geo g{p->nx, p->ny, p->N};
+  HIPCHK(timed(p, aao::KC_GRAD, [&] {
+    return aao::launch_grad(p->M, u, lam, gu0, p->gpart(), p->dtaps, p->d_q(), p->dt, g, p->B, p->L,
+                            p->grad_blocks, p->stream);
+  }));
+  HIPCHK(aao::launch_grad_finalize(p->gpart(), p->grad_blocks, p->B, gnu, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  collect_timing(p);
+  return AAO_OK;
+}
+
+aao_status aao_shifted_solve(aao_plan_t p, int S, const double* shifts, const double* b, double* x, int* iters) {
+  aao_status s = need_ready(p, false);
+  if (s != AAO_OK) return s;
+  if (S < 1 || S > p->S) return fail(AAO_EINVAL, "S must be in 1..B*(L/2+1)*M");
+  if (!shifts || !b || !x) return fail(AAO_EINVAL, "null argument");
+  cd* sh = reinterpret_cast<cd*>(p->htab + (p->off_sh - p->off_sf));
+  for (int i = 0; i < S; ++i) sh[i] = cd(shifts[2 * i], shifts[2 * i + 1]);
+  HIPCHK(hipMemcpyAsync(p->d_sh(), sh, (size_t)S * sizeof(double2), hipMemcpyHostToDevice, p->stream));
+  p->cached_alpha = -1;
+  const int64_t n = (int64_t)S * p->N;
+  HIPCHK(aao::launch_copy_c128_in(p->vec(1), p->f32, b, n, p->stream));
+  s = inner_solve(p, 0, S);
+  if (s != AAO_OK) return s;
+  HIPCHK(aao::launch_copy_c128_out(x, p->vec(0), p->f32, n, p->stream));
+  SweepOut o;
+  s = read_back(p, S, false, o);
+  if (s != AAO_OK) return s;
+  if (iters) {
+    const aao::SysState* hs = reinterpret_cast<const aao::SysState*>(p->hread + 128);
+    for (int i = 0; i < S; ++i) iters[i] = hs[i].iters;
+  }
+  return AAO_OK;
+}
+
+aao_status aao_set_timing(aao_plan_t p, int on) {
+  if (!p) return fail(AAO_EINVAL, "null plan");
+  p->timing = on != 0;
+  return AAO_OK;
+}
+
+aao_status aao_reset_stats(aao_plan_t p) {
+  if (!p) return fail(AAO_EINVAL, "null plan");
+  std::memset(&p->stats, 0, sizeof(p->stats));
+  if (p->ws) {
+    HIPCHK(hipMemsetAsync(p->work(), 0, kWorkSlots * sizeof(unsigned long long), p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+  }
+  return AAO_OK;
+}
+
+aao_status aao_get_stats(aao_plan_t p, aao_kernel_stats* out) {
+  if (!p || !out) return fail(AAO_EINVAL, "null argument");
+  *out = p->stats;
+  if (!p->ws) return AAO_OK;
+  unsigned long long w[kWorkSlots];
+  HIPCHK(hipMemcpyAsync(w, p->work(), sizeof(w), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  const double cs = (double)p->csize;
+  const double dof = (double)p->B * p->L * p->M * p->N;
+  const double freq = (double)p->B * p->Lh * p->M * p->N;
+  // fwd: read u (8 B/DOF), write x1; bwd: read x2, read and write u.
+  out->elements[aao::KC_FWD] = dof * out->launches[aao::KC_FWD];
+  out->bytes[aao::KC_FWD] = (8.0 * dof + cs * freq) * out->launches[aao::KC_FWD];
+  out->elements[aao::KC_BWD] = dof * out->launches[aao::KC_BWD];
+  out->bytes[aao::KC_BWD] = (16.0 * dof + cs * freq) * out->launches[aao::KC_BWD];
+  // Krylov kernels: complex words read + written per element processed, for
+  // k > 0 (slot c) and k == 0 (slot 16 + c).
+  struct { int c; double later, first; } kw[] = {
+      {aao::KC_COCG_A, 4, 3}, {aao::KC_COCG_B, 6, 5}, {aao::KC_BICG_1, 6, 4},
+      {aao::KC_BICG_2, 4, 4}, {aao::KC_BICG_3, 7, 6}};
+  for (auto& k : kw) {
+    const double e_later = (double)w[k.c], e_first = (double)w[16 + k.c];
+    out->elements[k.c] = e_later + e_first;
+    out->bytes[k.c] = cs * (k.later * e_later + k.first * e_first);
+  }
+  return AAO_OK;
+}
+
+aao_status aao_tables(aao_plan_t p, double alpha, double* d, double* r, double* djm, double* cond_max) {
+  if (!p) return fail(AAO_EINVAL, "null plan");
+  if (!(alpha > 0.0 && alpha < 1.0)) return fail(AAO_EINVAL, "alpha must lie in (0, 1)");
+  double cm = 0;
+  for (int j = 0; j < p->Lh; ++j) {
+    aao::FreqTable ft;
+    std::string why = aao::freq_table(p->t, p->Q, alpha, p->L, j, ft);
+    if (d) { d[2 * j] = ft.d.real(); d[2 * j + 1] = ft.d.imag(); }
+    if (r) { r[2 * j] = ft.r.real(); r[2 * j + 1] = ft.r.imag(); }
+    if (djm)
+      for (int m = 0; m < p->M; ++m) {
+        djm[2 * (j * p->M + m)] = ft.lam[m].real();
+        djm[2 * (j * p->M + m) + 1] = ft.lam[m].imag();
+      }
+    cm = std::max(cm, ft.cond);
+    if (!why.empty()) {
+      if (cond_max) *cond_max = cm;
+      return fail(AAO_ENODIAG, why);
+    }
+  }
+  if (cond_max) *cond_max = cm;
+  return AAO_OK;
+}
+
+aao_status aao_collocation(aao_plan_t p, double* nodes, double* Q) {
+  if (!p) return fail(AAO_EINVAL, "null plan");
+  if (nodes) std::copy(p->t.begin(), p->t.end(), nodes);
+  if (Q) std::copy(p->Q.begin(), p->Q.end(), Q);
+  return AAO_OK;
+}
+
+void aao_destroy(aao_plan_t p) {
+  if (!p) return;
+  if (p->stream) hipStreamSynchronize(p->stream);
+  for (auto& t : p->pending) {
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  for (auto e : p->pool) hipEventDestroy(e);
+  if (p->dtab) hipFree(p->dtab);
+  if (p->htab) hipHostFree(p->htab);
+  if (p->hread) hipHostFree(p->hread);
+  delete p;
+}
+
+}  // extern "C"

@@ -1,0 +1,1063 @@
+// HIP kernels of the alpha-circulant preconditioned Richardson sweep (gfx950).
+//
+// Layouts (all C order): u, r [B][L][M][N] FP64; frequency data x1, x2 and the
+// Krylov vectors [B][Lh][M][N] complex (double2 or float2), Lh = L/2 + 1 (only
+// the non-redundant half of the DFT over l is kept: the time data is real, so
+// frequency L-j is the conjugate of frequency j).
+//
+// The DFT over l runs in LDS on a tile of TN consecutive spatial points: two
+// real columns (n, n+1) are packed into one complex column, transformed by an
+// in-place radix-2 FFT (bit-reversed load, natural-order result) and separated
+// again; the M x M node transform of each frequency is applied on the way out.
+#include "aao_kernels.hpp"
+
+namespace aao {
+
+namespace {
+
+template <typename T> struct cvec;
+template <> struct cvec<double> { using type = double2; };
+template <> struct cvec<float> { using type = float2; };
+
+__device__ __forceinline__ double2 mk(double x, double y) { double2 r; r.x = x; r.y = y; return r; }
+__device__ __forceinline__ float2 mkf(float x, float y) { float2 r; r.x = x; r.y = y; return r; }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return mk(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return mk(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
+  return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return mk(a.x, -a.y); }
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  double d = b.x * b.x + b.y * b.y;
+  return mk((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ __forceinline__ double2 to_d2(double2 a) { return a; }
+__device__ __forceinline__ double2 to_d2(float2 a) { return mk(a.x, a.y); }
+template <typename V> __device__ __forceinline__ V from_d2(double2 a);
+template <> __device__ __forceinline__ double2 from_d2<double2>(double2 a) { return a; }
+template <> __device__ __forceinline__ float2 from_d2<float2>(double2 a) {
+  return mkf((float)a.x, (float)a.y);
+}
+
+// generic complex arithmetic for T2 in {double2, float2}
+template <typename V> __device__ __forceinline__ V vadd(V a, V b) { V r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename V> __device__ __forceinline__ V vsub(V a, V b) { V r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename V> __device__ __forceinline__ V vmul(V a, V b) {
+  V r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+}
+template <typename V, typename S> __device__ __forceinline__ V vscale(V a, S s) { V r; r.x = a.x * s; r.y = a.y * s; return r; }
+template <typename V> __device__ __forceinline__ V vzero() { V r; r.x = 0; r.y = 0; return r; }
+
+__device__ __forceinline__ int wrap_index(int x, int y, int dx, int dy, const Geo& g) {
+  int xx = x + dx;
+  xx += (xx < 0) ? g.nx : 0;
+  xx -= (xx >= g.nx) ? g.nx : 0;
+  int yy = y + dy;
+  yy += (yy < 0) ? g.ny : 0;
+  yy -= (yy >= g.ny) ? g.ny : 0;
+  return yy * g.nx + xx;
+}
+
+__device__ __forceinline__ int bitrev(int v, int logL) {
+  return logL == 0 ? 0 : (int)(__brev((unsigned)v) >> (32 - logL));
+}
+
+// Sum of K values over the 256-thread block; every thread receives the result.
+// The butterfly over lanes adds each pair in both orders, which is exact-equal,
+// so all lanes (and every workgroup doing the same reduction) agree bitwise.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* sh) {
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    double x = v[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    v[i] = x;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) sh[wid * K + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < K; ++i) v[i] = (sh[i] + sh[K + i]) + (sh[2 * K + i] + sh[3 * K + i]);
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+// In-place radix-2 DIT FFT over the row index of c[L][ncol] (bit-reversed
+// input order, natural output order).  INV selects e^{+2 pi i ...}.
+template <bool INV>
+__device__ __forceinline__ void lds_fft(double2* c, const double2* tw, int L, int logL, int ncol) {
+  for (int s = 0; s < logL; ++s) {
+    const int half = 1 << s;
+    const int tstride = L >> (s + 1);
+    __syncthreads();
+    const int total = (L >> 1) * ncol;
+    for (int idx = threadIdx.x; idx < total; idx += kBlock) {
+      const int col = idx % ncol;
+      const int k = idx / ncol;
+      const int pos = k & (half - 1);
+      const int i0 = ((k >> s) << (s + 1)) + pos;
+      const int i1 = i0 + half;
+      double2 w = tw[pos * tstride];
+      if (INV) w.y = -w.y;
+      const double2 a = c[i0 * ncol + col];
+      const double2 b = cmul(w, c[i1 * ncol + col]);
+      c[i0 * ncol + col] = cadd(a, b);
+      c[i1 * ncol + col] = csub(a, b);
+    }
+  }
+  __syncthreads();
+}
+
+// ----------------------------------------------------------------------------
+// Forward transform with the fused all-at-once residual.
+// MODE 0: r = w - C u computed on the fly; MODE 1: r read from memory.
+// ADJ: residual of C^T (coupling from step l+1 into the last node, Q^T, A^T).
+template <int M, bool ADJ, int MODE, typename OutV>
+__global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
+  extern __shared__ double lds[];
+  const int TN = a.TN, P = TN >> 1, L = a.L, N = a.g.N;
+  const int b = blockIdx.y;
+  const int n0 = blockIdx.x * TN;
+  double2* tw = reinterpret_cast<double2*>(lds + (size_t)L * M * TN);
+  __shared__ double sh[4];
+  for (int i = threadIdx.x; i < (L >> 1); i += kBlock) tw[i] = a.tw[i];
+
+  double res2 = 0.0;
+  for (int idx = threadIdx.x; idx < L * TN; idx += kBlock) {
+    const int l = idx >> a.logTN;
+    const int nl = idx & (TN - 1);
+    const int n = n0 + nl;
+    double rv[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) rv[m] = 0.0;
+    if (n < N) {
+      const size_t base = ((size_t)b * L + l) * M * (size_t)N;
+      if (MODE == 1) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) rv[m] = a.u[base + (size_t)m * N + n];
+      } else {
+        const double* ul = a.u + base;
+        const int x = n % a.g.nx, y = n / a.g.nx;
+        double v[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = 0.0;
+        for (int t = 0; t < a.taps.n; ++t) {
+          const int nb = wrap_index(x, y, a.taps.dx[t], a.taps.dy[t], a.g);
+          const double ct = a.taps.c[t];
+#pragma unroll
+          for (int m = 0; m < M; ++m) v[m] = fma(ct, ul[(size_t)m * N + nb], v[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          double s = 0.0;
+#pragma unroll
+          for (int k = 0; k < M; ++k) s = fma(a.q[m * M + k], v[k], s);
+          rv[m] = fma(a.dt, s, -ul[(size_t)m * N + n]);
+        }
+        if (!ADJ) {
+          if (l == 0) {
+            const double w0 = a.w0[(size_t)b * N + n];
+#pragma unroll
+            for (int m = 0; m < M; ++m) rv[m] += w0;
+          } else {
+            const double up = a.u[base - (size_t)N + n];  // u_{l-1, M}
+#pragma unroll
+            for (int m = 0; m < M; ++m) rv[m] += up;
+          }
+        } else {
+          if (l == L - 1) {
+            rv[M - 1] += a.w0[(size_t)b * N + n];
+          } else {
+            const double* un = ul + (size_t)M * N;  // lambda_{l+1, .}
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) s += un[(size_t)m * N + n];
+            rv[M - 1] += s;
+          }
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) res2 = fma(rv[m], rv[m], res2);
+      }
+    }
+    const double sc = a.scale[l];
+    const int lr = bitrev(l, a.logL);
+#pragma unroll
+    for (int m = 0; m < M; ++m) lds[((size_t)lr * M + m) * TN + nl] = rv[m] * sc;
+  }
+
+  double2* c = reinterpret_cast<double2*>(lds);
+  const int ncol = M * P;
+  lds_fft<false>(c, tw, L, a.logL, ncol);
+
+  OutV* out = reinterpret_cast<OutV*>(a.out);
+  for (int idx = threadIdx.x; idx < a.Lh * P; idx += kBlock) {
+    const int j = idx / P;
+    const int p = idx - j * P;
+    const int jm = (L - j) & (L - 1);
+    double2 A[M], Bv[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const double2 Z = c[j * ncol + m * P + p];
+      const double2 Zc = c[jm * ncol + m * P + p];
+      A[m] = mk(0.5 * (Z.x + Zc.x), 0.5 * (Z.y - Zc.y));
+      Bv[m] = mk(0.5 * (Z.y + Zc.y), -0.5 * (Z.x - Zc.x));
+      if (ADJ) {
+        A[m].y = -A[m].y;
+        Bv[m].y = -Bv[m].y;
+      }
+    }
+    const double2* mx = a.mix + (size_t)j * M * M;
+    const int n = n0 + 2 * p;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      double2 xa = mk(0, 0), xb = mk(0, 0);
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double2 w = mx[m * M + k];
+        xa = cadd(xa, cmul(w, A[k]));
+        xb = cadd(xb, cmul(w, Bv[k]));
+      }
+      const size_t o = (((size_t)b * a.Lh + j) * M + m) * (size_t)N + n;
+      if (n < N) out[o] = from_d2<OutV>(xa);
+      if (n + 1 < N) out[o + 1] = from_d2<OutV>(xb);
+    }
+  }
+  if (MODE == 0) {
+    double v[1] = {res2};
+    block_sum<1>(v, sh);
+    if (threadIdx.x == 0) a.part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = v[0];
+  }
+}
+
+// Residual only (row a1 on its own): r = w - C u written to memory.
+template <int M, bool ADJ>
+__global__ __launch_bounds__(kBlock) void k_residual(FwdArgs a, double* r_out, int B) {
+  __shared__ double sh[4];
+  const int L = a.L, N = a.g.N;
+  const size_t total = (size_t)B * L * N;
+  double res2 = 0.0;
+  for (size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * kBlock) {
+    const int n = (int)(idx % N);
+    const size_t bl = idx / N;
+    const int l = (int)(bl % L);
+    const int b = (int)(bl / L);
+    const size_t base = ((size_t)b * L + l) * M * (size_t)N;
+    const double* ul = a.u + base;
+    const int x = n % a.g.nx, y = n / a.g.nx;
+    double v[M], rv[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = 0.0;
+    for (int t = 0; t < a.taps.n; ++t) {
+      const int nb = wrap_index(x, y, a.taps.dx[t], a.taps.dy[t], a.g);
+#pragma unroll
+      for (int m = 0; m < M; ++m) v[m] = fma(a.taps.c[t], ul[(size_t)m * N + nb], v[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) s = fma(a.q[m * M + k], v[k], s);
+      rv[m] = fma(a.dt, s, -ul[(size_t)m * N + n]);
+    }
+    if (!ADJ) {
+      const double add = (l == 0) ? a.w0[(size_t)b * N + n] : a.u[base - (size_t)N + n];
+#pragma unroll
+      for (int m = 0; m < M; ++m) rv[m] += add;
+    } else {
+      if (l == L - 1) {
+        rv[M - 1] += a.w0[(size_t)b * N + n];
+      } else {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) s += ul[(size_t)(M + m) * N + n];
+        rv[M - 1] += s;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      r_out[base + (size_t)m * N + n] = rv[m];
+      res2 = fma(rv[m], rv[m], res2);
+    }
+  }
+  double v[1] = {res2};
+  block_sum<1>(v, sh);
+  if (threadIdx.x == 0) a.part[blockIdx.x] = v[0];
+}
+
+// ----------------------------------------------------------------------------
+// Inverse transform and update.  MODE 0: u += delta; MODE 1: u = delta.
+template <int M, bool ADJ, int MODE, typename InV>
+__global__ __launch_bounds__(kBlock) void k_bwd(BwdArgs a) {
+  extern __shared__ double lds[];
+  const int TN = a.TN, P = TN >> 1, L = a.L, N = a.g.N;
+  const int b = blockIdx.y;
+  const int n0 = blockIdx.x * TN;
+  double2* tw = reinterpret_cast<double2*>(lds + (size_t)L * M * TN);
+  __shared__ double sh[4];
+  for (int i = threadIdx.x; i < (L >> 1); i += kBlock) tw[i] = a.tw[i];
+  double2* c = reinterpret_cast<double2*>(lds);
+  const int ncol = M * P;
+  const InV* in = reinterpret_cast<const InV*>(a.in);
+
+  for (int idx = threadIdx.x; idx < a.Lh * P; idx += kBlock) {
+    const int j = idx / P;
+    const int p = idx - j * P;
+    const int n = n0 + 2 * p;
+    double2 xa[M], xb[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const size_t o = (((size_t)b * a.Lh + j) * M + m) * (size_t)N + n;
+      xa[m] = (n < N) ? to_d2(in[o]) : mk(0, 0);
+      xb[m] = (n + 1 < N) ? to_d2(in[o + 1]) : mk(0, 0);
+    }
+    const double2* mx = a.mix + (size_t)j * M * M;
+    const bool selfconj = (j == 0) || (2 * j == L);
+    const int jr = bitrev(j, a.logL);
+    const int jmr = bitrev((L - j) & (L - 1), a.logL);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      double2 ya = mk(0, 0), yb = mk(0, 0);
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double2 w = mx[m * M + k];
+        ya = cadd(ya, cmul(w, xa[k]));
+        yb = cadd(yb, cmul(w, xb[k]));
+      }
+      if (ADJ) {
+        ya.y = -ya.y;
+        yb.y = -yb.y;
+      }
+      if (selfconj) {
+        ya.y = 0.0;
+        yb.y = 0.0;
+      }
+      c[jr * ncol + m * P + p] = mk(ya.x - yb.y, ya.y + yb.x);
+      if (!selfconj) c[jmr * ncol + m * P + p] = mk(ya.x + yb.y, yb.x - ya.y);
+    }
+  }
+  lds_fft<true>(c, tw, L, a.logL, ncol);
+
+  const int lmon = ADJ ? 0 : L - 1;
+  double dmax = 0.0;
+  for (int idx = threadIdx.x; idx < L * M * TN; idx += kBlock) {
+    const int nl = idx & (TN - 1);
+    const int lm = idx >> a.logTN;
+    const int m = lm % M;
+    const int l = lm / M;
+    const int n = n0 + nl;
+    if (n >= N) continue;
+    const double d = lds[idx] * a.scale[l];
+    const size_t o = (((size_t)b * L + l) * M + m) * (size_t)N + n;
+    if (MODE == 0) a.u[o] += d;
+    else a.u[o] = d;
+    if (l == lmon) dmax = fmax(dmax, fabs(d));
+  }
+  dmax = block_max(dmax, sh);
+  if (threadIdx.x == 0) a.part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = dmax;
+}
+
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* ps, int ns, const double* pm,
+                                                     int nm, double* out) {
+  __shared__ double sh[4];
+  double s = 0.0, mx = 0.0;
+  for (int i = threadIdx.x; i < ns; i += kBlock) s += ps[i];
+  for (int i = threadIdx.x; i < nm; i += kBlock) mx = fmax(mx, pm[i]);
+  double v[1] = {s};
+  block_sum<1>(v, sh);
+  mx = block_max(mx, sh);
+  if (threadIdx.x == 0) {
+    out[0] = v[0];
+    out[1] = mx;
+  }
+}
+
+__global__ void k_init_u(double* u, const double* u0, int B, int L, int M, int N) {
+  const size_t total = (size_t)B * L * M * N;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int n = (int)(i % N);
+    const int b = (int)(i / ((size_t)L * M * N));
+    u[i] = u0[(size_t)b * N + n];
+  }
+}
+
+__global__ void k_fill(double* p, double v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// part[2*blk] = sum v^2, part[2*blk+1] = max |v| over a grid-stride share.
+__global__ __launch_bounds__(kBlock) void k_norms(const double* v, int64_t n, double* part) {
+  __shared__ double sh[4];
+  double s = 0.0, mx = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    s = fma(v[i], v[i], s);
+    mx = fmax(mx, fabs(v[i]));
+  }
+  double t[1] = {s};
+  block_sum<1>(t, sh);
+  mx = block_max(mx, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = t[0];
+    part[2 * blockIdx.x + 1] = mx;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Batched Krylov solvers for (I - c_s A) x_s = b_s.  Grid (wps, num_sys); each
+// workgroup owns one chunk of one system.  Scalars are reduced from per-chunk
+// partial sums by every workgroup in the same fixed order (bitwise identical),
+// so no grid-wide synchronisation and no host round trip is needed.
+__device__ __forceinline__ double* qpart(const KrylovArgs& a, int q, int s) {
+  return a.part + ((size_t)q * a.num_sys + s) * a.wps;
+}
+
+template <int K>
+__device__ __forceinline__ void reduce_parts(const KrylovArgs& a, const int (&qs)[K], int s,
+                                             double (&v)[K], double* sh) {
+#pragma unroll
+  for (int i = 0; i < K; ++i) v[i] = 0.0;
+  for (int c = threadIdx.x; c < a.wps; c += kBlock) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) v[i] += qpart(a, qs[i], s)[c];
+  }
+  block_sum<K>(v, sh);
+}
+
+template <int K>
+__device__ __forceinline__ void write_parts(const KrylovArgs& a, const int (&qs)[K], int s,
+                                            double (&v)[K], double* sh) {
+  block_sum<K>(v, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) qpart(a, qs[i], s)[blockIdx.x] = v[i];
+  }
+}
+
+// Elements processed, for the bandwidth accounting: slot cls for k > 0 and
+// slot 16 + cls for k == 0 (the first iteration moves fewer vectors).
+__device__ __forceinline__ void count_work(const KrylovArgs& a, int cls, int k, int n) {
+  if (threadIdx.x == 0) atomicAdd(a.work + (k == 0 ? 16 + cls : cls), (unsigned long long)n);
+}
+
+// Shifted operator at point n on a vector given through an accessor.
+template <typename V, typename F>
+__device__ __forceinline__ V shifted_apply(const KrylovArgs& a, int n, V center, V shift, F get) {
+  const int x = n % a.g.nx, y = n / a.g.nx;
+  V acc = vzero<V>();
+  for (int t = 0; t < a.taps.n; ++t) {
+    const int nb = wrap_index(x, y, a.taps.dx[t], a.taps.dy[t], a.g);
+    acc = vadd(acc, vscale(get(nb), (decltype(center.x))a.taps.c[t]));
+  }
+  return vsub(center, vmul(shift, acc));
+}
+
+// COCG (conjugate orthogonal CG, bilinear form x^T y) for complex-symmetric
+// I - c A.  Kernel A: convergence test, p = r + beta p_old, q = (I - cA) p,
+// partial mu = p^T q.  At k = 0 also rho_0 = r^T r and ||b||^2.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cocg_a(KrylovArgs a, int k) {
+  using V = typename cvec<T>::type;
+  __shared__ double sh[4 * 8];
+  const int s = blockIdx.y;
+  SysState* st = a.st + s;
+  // One read of the flag per workgroup: kernel A may clear it concurrently
+  // (workgroup 0, on convergence), and every thread must take the same path.
+  __shared__ int act;
+  if (threadIdx.x == 0) act = st->active;
+  __syncthreads();
+  if (!act) return;
+  double2 beta = mk(0, 0);
+  if (k > 0) {
+    const int cur = k & 1, prv = cur ^ 1;
+    const int qs[6] = {QP_RHO0_RE + 2 * cur, QP_RHO0_IM + 2 * cur, QP_RHO0_RE + 2 * prv,
+                       QP_RHO0_IM + 2 * prv, QP_RR0 + cur, QP_BB};
+    double v[6];
+    reduce_parts<6>(a, qs, s, v, sh);
+    const bool conv = v[4] <= a.tol2 * v[5];
+    if (conv || k >= a.maxit || st->breakdown) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->active = 0;
+        st->iters = k;
+        st->flag = conv ? 0 : (st->breakdown ? 2 : 1);
+      }
+      return;
+    }
+    beta = cdiv(mk(v[0], v[1]), mk(v[2], v[3]));
+  }
+  const size_t off = (size_t)s * a.g.N;
+  const V* R = reinterpret_cast<const V*>(a.R) + off;
+  const V* Po = reinterpret_cast<const V*>(a.P[(k + 1) & 1]) + off;
+  V* Pn = reinterpret_cast<V*>(a.P[k & 1]) + off;
+  V* Qv = reinterpret_cast<V*>(a.V[0]) + off;
+  const V sft = from_d2<V>(a.shift[s]);
+  const V bt = from_d2<V>(beta);
+  const int n0 = blockIdx.x * a.chunk;
+  const int n1 = min(a.g.N, n0 + a.chunk);
+  double mu_re = 0, mu_im = 0, rho_re = 0, rho_im = 0, bb = 0;
+  if (k == 0) {
+    for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
+      const V r = R[n];
+      const V q = shifted_apply(a, n, r, sft, [&](int i) { return R[i]; });
+      Pn[n] = r;
+      Qv[n] = q;
+      mu_re += (double)r.x * q.x - (double)r.y * q.y;
+      mu_im += (double)r.x * q.y + (double)r.y * q.x;
+      rho_re += (double)r.x * r.x - (double)r.y * r.y;
+      rho_im += 2.0 * (double)r.x * r.y;
+      bb += (double)r.x * r.x + (double)r.y * r.y;
+    }
+    double v[5] = {mu_re, mu_im, rho_re, rho_im, bb};
+    const int qs[5] = {QP_A_RE, QP_A_IM, QP_RHO0_RE, QP_RHO0_IM, QP_BB};
+    write_parts<5>(a, qs, s, v, sh);
+  } else {
+    for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
+      const V p = vadd(R[n], vmul(bt, Po[n]));
+      const V q = shifted_apply(a, n, p, sft, [&](int i) { return vadd(R[i], vmul(bt, Po[i])); });
+      Pn[n] = p;
+      Qv[n] = q;
+      mu_re += (double)p.x * q.x - (double)p.y * q.y;
+      mu_im += (double)p.x * q.y + (double)p.y * q.x;
+    }
+    double v[2] = {mu_re, mu_im};
+    const int qs[2] = {QP_A_RE, QP_A_IM};
+    write_parts<2>(a, qs, s, v, sh);
+  }
+  count_work(a, KC_COCG_A, k, n1 - n0);
+}
+
+// Kernel B: a = rho / mu, x += a p, r -= a q, partial rho' = r^T r, ||r||^2.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cocg_b(KrylovArgs a, int k) {
+  using V = typename cvec<T>::type;
+  __shared__ double sh[4 * 8];
+  const int s = blockIdx.y;
+  SysState* st = a.st + s;
+  // One read of the flag per workgroup: kernel A may clear it concurrently
+  // (workgroup 0, on convergence), and every thread must take the same path.
+  __shared__ int act;
+  if (threadIdx.x == 0) act = st->active;
+  __syncthreads();
+  if (!act) return;
+  const int cur = k & 1, nxt = cur ^ 1;
+  double v[4];
+  {
+    const int qs[4] = {QP_RHO0_RE + 2 * cur, QP_RHO0_IM + 2 * cur, QP_A_RE, QP_A_IM};
+    reduce_parts<4>(a, qs, s, v, sh);
+  }
+  double2 al = mk(0, 0);
+  const double mu2 = v[2] * v[2] + v[3] * v[3];
+  if (mu2 > 0.0 && isfinite(mu2)) {
+    al = cdiv(mk(v[0], v[1]), mk(v[2], v[3]));
+  } else if (blockIdx.x == 0 && threadIdx.x == 0 && (v[0] != 0.0 || v[1] != 0.0)) {
+    st->breakdown = 1;  // consumed by the next kernel A
+  }
+  const size_t off = (size_t)s * a.g.N;
+  V* X = reinterpret_cast<V*>(a.X) + off;
+  V* R = reinterpret_cast<V*>(a.R) + off;
+  const V* Pc = reinterpret_cast<const V*>(a.P[k & 1]) + off;
+  const V* Qv = reinterpret_cast<const V*>(a.V[0]) + off;
+  const V av = from_d2<V>(al);
+  const int n0 = blockIdx.x * a.chunk;
+  const int n1 = min(a.g.N, n0 + a.chunk);
+  double rho_re = 0, rho_im = 0, rr = 0;
+  for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
+    const V p = Pc[n];
+    const V x = (k == 0) ? vmul(av, p) : vadd(X[n], vmul(av, p));
+    const V r = vsub(R[n], vmul(av, Qv[n]));
+    X[n] = x;
+    R[n] = r;
+    rho_re += (double)r.x * r.x - (double)r.y * r.y;
+    rho_im += 2.0 * (double)r.x * r.y;
+    rr += (double)r.x * r.x + (double)r.y * r.y;
+  }
+  double w[3] = {rho_re, rho_im, rr};
+  const int qs[3] = {QP_RHO0_RE + 2 * nxt, QP_RHO0_IM + 2 * nxt, QP_RR0 + nxt};
+  write_parts<3>(a, qs, s, w, sh);
+  count_work(a, KC_COCG_B, k, n1 - n0);
+}
+
+// BiCGStab (Hermitian inner products <a, b> = sum conj(a) b), r_hat = r_0.
+// Phase 1: convergence test, beta = (rho_k / rho_{k-1}) (alpha / omega),
+// p = r + beta (p_old - omega v_old), v = (I - cA) p, partial <r_hat, v>.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bicg1(KrylovArgs a, int k) {
+  using V = typename cvec<T>::type;
+  __shared__ double sh[4 * 8];
+  const int s = blockIdx.y;
+  SysState* st = a.st + s;
+  // One read of the flag per workgroup: kernel A may clear it concurrently
+  // (workgroup 0, on convergence), and every thread must take the same path.
+  __shared__ int act;
+  if (threadIdx.x == 0) act = st->active;
+  __syncthreads();
+  if (!act) return;
+  const int cur = k & 1;
+  const size_t off = (size_t)s * a.g.N;
+  const V* R = reinterpret_cast<const V*>(a.R) + off;
+  V* Rh = reinterpret_cast<V*>(a.Rh) + off;
+  V* Pn = reinterpret_cast<V*>(a.P[k & 1]) + off;
+  const V* Po = reinterpret_cast<const V*>(a.P[(k + 1) & 1]) + off;
+  V* Vn = reinterpret_cast<V*>(a.V[k & 1]) + off;
+  const V* Vo = reinterpret_cast<const V*>(a.V[(k + 1) & 1]) + off;
+  const V sft = from_d2<V>(a.shift[s]);
+  const int n0 = blockIdx.x * a.chunk;
+  const int n1 = min(a.g.N, n0 + a.chunk);
+  double hv_re = 0, hv_im = 0;
+  if (k == 0) {
+    double bb = 0;
+    for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
+      const V r = R[n];
+      const V v = shifted_apply(a, n, r, sft, [&](int i) { return R[i]; });
+      Rh[n] = r;
+      Pn[n] = r;
+      Vn[n] = v;
+      hv_re += (double)r.x * v.x + (double)r.y * v.y;
+      hv_im += (double)r.x * v.y - (double)r.y * v.x;
+      bb += (double)r.x * r.x + (double)r.y * r.y;
+    }
+    // rho_0 = <r_hat, r> = ||b||^2 (real)
+    double w[4] = {hv_re, hv_im, bb, bb};
+    const int qs[4] = {QP_A_RE, QP_A_IM, QP_BB, QP_RHO0_RE};
+    write_parts<4>(a, qs, s, w, sh);
+    if (threadIdx.x == 0) qpart(a, QP_RHO0_IM, s)[blockIdx.x] = 0.0;
+  } else {
+    const int qs[4] = {QP_RHO0_RE + 2 * cur, QP_RHO0_IM + 2 * cur, QP_RR0 + cur, QP_BB};
+    double v[4];
+    reduce_parts<4>(a, qs, s, v, sh);
+    const bool conv = v[2] <= a.tol2 * v[3];
+    if (conv || k >= a.maxit || st->breakdown) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->active = 0;
+        st->iters = k;
+        st->flag = conv ? 0 : (st->breakdown ? 2 : 1);
+      }
+      return;
+    }
+    const double2 rho = mk(v[0], v[1]);
+    const double2 beta = cmul(cdiv(rho, st->rho), cdiv(st->alpha, st->omega));
+    const V bt = from_d2<V>(beta);
+    const V om = from_d2<V>(st->omega);
+    auto pnew = [&](int i) { return vadd(R[i], vmul(bt, vsub(Po[i], vmul(om, Vo[i])))); };
+    for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
+      const V p = pnew(n);
+      const V v = shifted_apply(a, n, p, sft, pnew);
+      Pn[n] = p;
+      Vn[n] = v;
+      const V rh = Rh[n];
+      hv_re += (double)rh.x * v.x + (double)rh.y * v.y;
+      hv_im += (double)rh.x * v.y - (double)rh.y * v.x;
+    }
+    double w[2] = {hv_re, hv_im};
+    const int qw[2] = {QP_A_RE, QP_A_IM};
+    write_parts<2>(a, qw, s, w, sh);
+  }
+  count_work(a, KC_BICG_1, k, n1 - n0);
+}
+
+// Phase 2: alpha = rho_k / <r_hat, v>; s = r - alpha v; t = (I - cA) s;
+// partials <t, s>, <t, t>.  Workgroup 0 records rho_k and alpha_k.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bicg2(KrylovArgs a, int k) {
+  using V = typename cvec<T>::type;
+  __shared__ double sh[4 * 8];
+  const int s = blockIdx.y;
+  SysState* st = a.st + s;
+  // One read of the flag per workgroup: kernel A may clear it concurrently
+  // (workgroup 0, on convergence), and every thread must take the same path.
+  __shared__ int act;
+  if (threadIdx.x == 0) act = st->active;
+  __syncthreads();
+  if (!act) return;
+  const int cur = k & 1;
+  double v[4];
+  {
+    const int qs[4] = {QP_RHO0_RE + 2 * cur, QP_RHO0_IM + 2 * cur, QP_A_RE, QP_A_IM};
+    reduce_parts<4>(a, qs, s, v, sh);
+  }
+  const double2 rho = mk(v[0], v[1]);
+  const double2 hv = mk(v[2], v[3]);
+  double2 al = mk(0, 0);
+  if (hv.x * hv.x + hv.y * hv.y > 0.0) al = cdiv(rho, hv);
+  else if (blockIdx.x == 0 && threadIdx.x == 0 && (rho.x != 0.0 || rho.y != 0.0)) st->breakdown = 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rho = rho;
+    st->alpha = al;
+  }
+  const size_t off = (size_t)s * a.g.N;
+  const V* R = reinterpret_cast<const V*>(a.R) + off;
+  const V* Vc = reinterpret_cast<const V*>(a.V[k & 1]) + off;
+  V* Sv = reinterpret_cast<V*>(a.S) + off;
+  V* Tv = reinterpret_cast<V*>(a.T) + off;
+  const V sft = from_d2<V>(a.shift[s]);
+  const V av = from_d2<V>(al);
+  const int n0 = blockIdx.x * a.chunk;
+  const int n1 = min(a.g.N, n0 + a.chunk);
+  auto sval = [&](int i) { return vsub(R[i], vmul(av, Vc[i])); };
+  double ts_re = 0, ts_im = 0, tt = 0;
+  for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
+    const V sv = sval(n);
+    const V t = shifted_apply(a, n, sv, sft, sval);
+    Sv[n] = sv;
+    Tv[n] = t;
+    ts_re += (double)t.x * sv.x + (double)t.y * sv.y;
+    ts_im += (double)t.x * sv.y - (double)t.y * sv.x;
+    tt += (double)t.x * t.x + (double)t.y * t.y;
+  }
+  double w[3] = {ts_re, ts_im, tt};
+  const int qs[3] = {QP_B_RE, QP_B_IM, QP_TT};
+  write_parts<3>(a, qs, s, w, sh);
+  count_work(a, KC_BICG_2, k, n1 - n0);
+}
+
+// Phase 3: omega = <t, s> / <t, t>; x += alpha p + omega s; r = s - omega t;
+// partials rho_{k+1} = <r_hat, r>, ||r||^2.  Workgroup 0 records omega_k.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bicg3(KrylovArgs a, int k) {
+  using V = typename cvec<T>::type;
+  __shared__ double sh[4 * 8];
+  const int s = blockIdx.y;
+  SysState* st = a.st + s;
+  // One read of the flag per workgroup: kernel A may clear it concurrently
+  // (workgroup 0, on convergence), and every thread must take the same path.
+  __shared__ int act;
+  if (threadIdx.x == 0) act = st->active;
+  __syncthreads();
+  if (!act) return;
+  const int nxt = (k & 1) ^ 1;
+  double v[3];
+  {
+    const int qs[3] = {QP_B_RE, QP_B_IM, QP_TT};
+    reduce_parts<3>(a, qs, s, v, sh);
+  }
+  double2 om = mk(0, 0);
+  if (v[2] > 0.0) om = mk(v[0] / v[2], v[1] / v[2]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->omega = om;
+    if (v[2] > 0.0 && om.x == 0.0 && om.y == 0.0) st->breakdown = 1;
+  }
+  const size_t off = (size_t)s * a.g.N;
+  V* X = reinterpret_cast<V*>(a.X) + off;
+  V* R = reinterpret_cast<V*>(a.R) + off;
+  const V* Rh = reinterpret_cast<const V*>(a.Rh) + off;
+  const V* Pc = reinterpret_cast<const V*>(a.P[k & 1]) + off;
+  const V* Sv = reinterpret_cast<const V*>(a.S) + off;
+  const V* Tv = reinterpret_cast<const V*>(a.T) + off;
+  const V av = from_d2<V>(st->alpha);
+  const V ov = from_d2<V>(om);
+  const int n0 = blockIdx.x * a.chunk;
+  const int n1 = min(a.g.N, n0 + a.chunk);
+  double hr_re = 0, hr_im = 0, rr = 0;
+  for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
+    const V sv = Sv[n];
+    const V inc = vadd(vmul(av, Pc[n]), vmul(ov, sv));
+    const V x = (k == 0) ? inc : vadd(X[n], inc);
+    const V r = vsub(sv, vmul(ov, Tv[n]));
+    X[n] = x;
+    R[n] = r;
+    const V rh = Rh[n];
+    hr_re += (double)rh.x * r.x + (double)rh.y * r.y;
+    hr_im += (double)rh.x * r.y - (double)rh.y * r.x;
+    rr += (double)r.x * r.x + (double)r.y * r.y;
+  }
+  double w[3] = {hr_re, hr_im, rr};
+  const int qs[3] = {QP_RHO0_RE + 2 * nxt, QP_RHO0_IM + 2 * nxt, QP_RR0 + nxt};
+  write_parts<3>(a, qs, s, w, sh);
+  count_work(a, KC_BICG_3, k, n1 - n0);
+}
+
+__global__ void k_krylov_init(SysState* st, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    SysState z;
+    z.active = 1;
+    z.iters = 0;
+    z.flag = 0;
+    z.breakdown = 0;
+    z.rho = mk(1, 0);
+    z.alpha = mk(1, 0);
+    z.omega = mk(1, 0);
+    st[i] = z;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_active(const SysState* st, int n, int* out) {
+  __shared__ double sh[4];
+  double c = 0;
+  for (int i = threadIdx.x; i < n; i += kBlock) c += st[i].active;
+  double v[1] = {c};
+  block_sum<1>(v, sh);
+  if (threadIdx.x == 0) out[0] = (int)v[0];
+}
+
+template <typename V>
+__global__ void k_copy_in(V* dst, const double2* src, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = from_d2<V>(src[i]);
+}
+
+template <typename V>
+__global__ void k_copy_out(double2* dst, const V* src, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = to_d2(src[i]);
+}
+
+// grad_u0[b][n] = sum_m lambda[b][0][m][n];
+// part[b][blk] = dt sum_{l,m} lambda_{l,m} (sum_k q_mk (dA u_{l,k}))  over a share of n.
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_grad(const double* u, const double* lam, double* gu0,
+                                                 double* part, Taps dt_, const double* __restrict__ q_,
+                                                 double dt, Geo g, int L) {
+  __shared__ double sh[4];
+  __shared__ double q[kMaxM * kMaxM];
+  for (int i = threadIdx.x; i < M * M; i += kBlock) q[i] = q_[i];
+  __syncthreads();
+  const int b = blockIdx.y;
+  const int N = g.N;
+  double acc = 0.0;
+  for (int n = blockIdx.x * kBlock + threadIdx.x; n < N; n += gridDim.x * kBlock) {
+    const int x = n % g.nx, y = n / g.nx;
+    double s0 = 0.0;
+    for (int m = 0; m < M; ++m) s0 += lam[(((size_t)b * L) * M + m) * N + n];
+    gu0[(size_t)b * N + n] = s0;
+    for (int l = 0; l < L; ++l) {
+      const double* ul = u + ((size_t)b * L + l) * M * (size_t)N;
+      const double* ll = lam + ((size_t)b * L + l) * M * (size_t)N;
+      double v[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) v[m] = 0.0;
+      for (int t = 0; t < dt_.n; ++t) {
+        const int nb = wrap_index(x, y, dt_.dx[t], dt_.dy[t], g);
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = fma(dt_.c[t], ul[(size_t)m * N + nb], v[m]);
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) s = fma(q[m * M + k], v[k], s);
+        acc = fma(ll[(size_t)m * N + n], s, acc);
+      }
+    }
+  }
+  double v[1] = {acc * dt};
+  block_sum<1>(v, sh);
+  if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = v[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_grad_finalize(const double* part, int nblk, double* gnu) {
+  __shared__ double sh[4];
+  const int b = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += kBlock) s += part[(size_t)b * nblk + i];
+  double v[1] = {s};
+  block_sum<1>(v, sh);
+  if (threadIdx.x == 0) gnu[b] = v[0];
+}
+
+int grid_for(int64_t n, int per = kBlock, int cap = 8192) {
+  int64_t g = (n + per - 1) / per;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+template <int M>
+hipError_t fwd_m(bool adj, bool from_r, bool out_f32, const FwdArgs& a, int B, hipStream_t st) {
+  dim3 grid((a.g.N + a.TN - 1) / a.TN, B);
+  size_t lds = (size_t)a.L * M * a.TN * sizeof(double) + (size_t)(a.L / 2 + 1) * sizeof(double2);
+#define AAO_FWD(ADJ, MODE, OV) hipLaunchKernelGGL((k_fwd<M, ADJ, MODE, OV>), grid, dim3(kBlock), lds, st, a)
+  if (!adj) {
+    if (!from_r) { if (out_f32) AAO_FWD(false, 0, float2); else AAO_FWD(false, 0, double2); }
+    else { if (out_f32) AAO_FWD(false, 1, float2); else AAO_FWD(false, 1, double2); }
+  } else {
+    if (!from_r) { if (out_f32) AAO_FWD(true, 0, float2); else AAO_FWD(true, 0, double2); }
+    else { if (out_f32) AAO_FWD(true, 1, float2); else AAO_FWD(true, 1, double2); }
+  }
+#undef AAO_FWD
+  return hipGetLastError();
+}
+
+template <int M>
+hipError_t bwd_m(bool adj, bool to_delta, bool in_f32, const BwdArgs& a, int B, hipStream_t st) {
+  dim3 grid((a.g.N + a.TN - 1) / a.TN, B);
+  size_t lds = (size_t)a.L * M * a.TN * sizeof(double) + (size_t)(a.L / 2 + 1) * sizeof(double2);
+#define AAO_BWD(ADJ, MODE, IV) hipLaunchKernelGGL((k_bwd<M, ADJ, MODE, IV>), grid, dim3(kBlock), lds, st, a)
+  if (!adj) {
+    if (!to_delta) { if (in_f32) AAO_BWD(false, 0, float2); else AAO_BWD(false, 0, double2); }
+    else { if (in_f32) AAO_BWD(false, 1, float2); else AAO_BWD(false, 1, double2); }
+  } else {
+    if (!to_delta) { if (in_f32) AAO_BWD(true, 0, float2); else AAO_BWD(true, 0, double2); }
+    else { if (in_f32) AAO_BWD(true, 1, float2); else AAO_BWD(true, 1, double2); }
+  }
+#undef AAO_BWD
+  return hipGetLastError();
+}
+
+template <int M>
+hipError_t res_m(bool adj, const FwdArgs& a, double* r_out, int B, int nblk, hipStream_t st) {
+  if (adj) hipLaunchKernelGGL((k_residual<M, true>), dim3(nblk), dim3(kBlock), 0, st, a, r_out, B);
+  else hipLaunchKernelGGL((k_residual<M, false>), dim3(nblk), dim3(kBlock), 0, st, a, r_out, B);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define AAO_DISPATCH_M(M_, CALL)                     \
+  switch (M_) {                                      \
+    case 1: return CALL(1);                          \
+    case 2: return CALL(2);                          \
+    case 3: return CALL(3);                          \
+    case 4: return CALL(4);                          \
+    case 5: return CALL(5);                          \
+    case 6: return CALL(6);                          \
+    case 7: return CALL(7);                          \
+    case 8: return CALL(8);                          \
+    default: return hipErrorInvalidValue;            \
+  }
+
+hipError_t launch_fwd(int M, bool adj, bool from_r, bool out_f32, const FwdArgs& a, int B,
+                      hipStream_t st) {
+#define C_(m) fwd_m<m>(adj, from_r, out_f32, a, B, st)
+  AAO_DISPATCH_M(M, C_)
+#undef C_
+}
+
+hipError_t launch_bwd(int M, bool adj, bool to_delta, bool in_f32, const BwdArgs& a, int B,
+                      hipStream_t st) {
+#define C_(m) bwd_m<m>(adj, to_delta, in_f32, a, B, st)
+  AAO_DISPATCH_M(M, C_)
+#undef C_
+}
+
+hipError_t launch_residual(int M, bool adj, const FwdArgs& a, double* r_out, int B, hipStream_t st) {
+  const int nblk = grid_for((int64_t)B * a.L * a.g.N, kBlock, 1024);
+#define C_(m) res_m<m>(adj, a, r_out, B, nblk, st)
+  AAO_DISPATCH_M(M, C_)
+#undef C_
+}
+
+int residual_blocks(int B, int L, int N) { return grid_for((int64_t)B * L * N, kBlock, 1024); }
+
+hipError_t launch_finalize(const double* ps, int ns, const double* pm, int nm, double* out,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, ps, ns, pm, nm, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_u(double* u, const double* u0, int B, int L, int M, int N, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_u, dim3(grid_for((int64_t)B * L * M * N)), dim3(kBlock), 0, st, u, u0,
+                     B, L, M, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_norms_bn(const double* v, int B, int N, double* part, int nparts, hipStream_t st) {
+  hipLaunchKernelGGL(k_norms, dim3(nparts), dim3(kBlock), 0, st, v, (int64_t)B * N, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_cocg_a(bool f32, const KrylovArgs& a, int k, hipStream_t st) {
+  dim3 grid(a.wps, a.num_sys);
+  if (f32) hipLaunchKernelGGL(k_cocg_a<float>, grid, dim3(kBlock), 0, st, a, k);
+  else hipLaunchKernelGGL(k_cocg_a<double>, grid, dim3(kBlock), 0, st, a, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_cocg_b(bool f32, const KrylovArgs& a, int k, hipStream_t st) {
+  dim3 grid(a.wps, a.num_sys);
+  if (f32) hipLaunchKernelGGL(k_cocg_b<float>, grid, dim3(kBlock), 0, st, a, k);
+  else hipLaunchKernelGGL(k_cocg_b<double>, grid, dim3(kBlock), 0, st, a, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, hipStream_t st) {
+  dim3 grid(a.wps, a.num_sys);
+  switch (phase) {
+    case 1:
+      if (f32) hipLaunchKernelGGL(k_bicg1<float>, grid, dim3(kBlock), 0, st, a, k);
+      else hipLaunchKernelGGL(k_bicg1<double>, grid, dim3(kBlock), 0, st, a, k);
+      break;
+    case 2:
+      if (f32) hipLaunchKernelGGL(k_bicg2<float>, grid, dim3(kBlock), 0, st, a, k);
+      else hipLaunchKernelGGL(k_bicg2<double>, grid, dim3(kBlock), 0, st, a, k);
+      break;
+    default:
+      if (f32) hipLaunchKernelGGL(k_bicg3<float>, grid, dim3(kBlock), 0, st, a, k);
+      else hipLaunchKernelGGL(k_bicg3<double>, grid, dim3(kBlock), 0, st, a, k);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_krylov_init(const KrylovArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_krylov_init, dim3(grid_for(a.num_sys)), dim3(kBlock), 0, st, a.st, a.num_sys);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_active(const SysState* st, int n, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_active, dim3(1), dim3(kBlock), 0, s, st, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_c128_in(void* dst, bool f32, const double* src, int64_t n, hipStream_t st) {
+  const double2* s2 = reinterpret_cast<const double2*>(src);
+  if (f32) hipLaunchKernelGGL(k_copy_in<float2>, dim3(grid_for(n)), dim3(kBlock), 0, st, (float2*)dst, s2, n);
+  else hipLaunchKernelGGL(k_copy_in<double2>, dim3(grid_for(n)), dim3(kBlock), 0, st, (double2*)dst, s2, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_c128_out(double* dst, const void* src, bool f32, int64_t n, hipStream_t st) {
+  double2* d2 = reinterpret_cast<double2*>(dst);
+  if (f32) hipLaunchKernelGGL(k_copy_out<float2>, dim3(grid_for(n)), dim3(kBlock), 0, st, d2, (const float2*)src, n);
+  else hipLaunchKernelGGL(k_copy_out<double2>, dim3(grid_for(n)), dim3(kBlock), 0, st, d2, (const double2*)src, n);
+  return hipGetLastError();
+}
+
+template <int M>
+static hipError_t grad_m(const double* u, const double* lam, double* gu0, double* part,
+                         const Taps& dtaps, const double* q, double dt, const Geo& g, int B, int L,
+                         int nblk, hipStream_t st) {
+  hipLaunchKernelGGL((k_grad<M>), dim3(nblk, B), dim3(kBlock), 0, st, u, lam, gu0, part, dtaps, q,
+                     dt, g, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(int M, const double* u, const double* lam, double* gu0, double* part,
+                       const Taps& dtaps, const double* q, double dt, const Geo& g, int B, int L,
+                       int nblk, hipStream_t st) {
+#define C_(m) grad_m<m>(u, lam, gu0, part, dtaps, q, dt, g, B, L, nblk, st)
+  AAO_DISPATCH_M(M, C_)
+#undef C_
+}
+
+hipError_t launch_grad_finalize(const double* part, int nblk, int B, double* gnu, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_finalize, dim3(B), dim3(kBlock), 0, st, part, nblk, gnu);
+  return hipGetLastError();
+}
+
+}  // namespace aao

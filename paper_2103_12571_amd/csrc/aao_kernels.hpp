@@ -1,0 +1,121 @@
+// Kernel-side interface of the alpha-circulant sweep (internal to libaao.so).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace aao {
+
+constexpr int kMaxTaps = 32;
+constexpr int kMaxM = 8;
+constexpr int kBlock = 256;
+
+// Periodic grid: n = y * nx + x, N = nx * ny.
+struct Geo {
+  int nx, ny, N;
+};
+
+// Stencil taps: (A v)[n] = sum_t c[t] v[wrap(x + dx[t], y + dy[t])].
+struct Taps {
+  int n;
+  int dx[kMaxTaps];
+  int dy[kMaxTaps];
+  double c[kMaxTaps];
+};
+
+// Per shifted system state of the batched Krylov solvers.
+struct SysState {
+  int active;     // 1 while iterating
+  int iters;      // iterations done when it stopped
+  int flag;       // 0 converged, 1 hit the iteration cap, 2 breakdown
+  int breakdown;  // set by an update kernel, consumed by the next matvec kernel
+  double2 rho;    // BiCGStab: rho_k
+  double2 alpha;  // BiCGStab: alpha_k
+  double2 omega;  // BiCGStab: omega_k
+};
+
+// Forward transform + fused residual (rows a1, a2).
+struct FwdArgs {
+  const double* u;      // u (or lambda) [B][L][M][N], or r when the input is a residual
+  const double* w0;     // u0 [B][N] (primal) or g_last [B][N] (adjoint)
+  void* out;            // x1 [B][Lh][M][N] complex (double2 or float2)
+  const double* scale;  // [L] scaling applied before the DFT over l
+  const double2* tw;    // [L/2] e^{-2 pi i k / L}
+  const double2* mix;   // [Lh][M][M] per-frequency node transform
+  double* part;         // per-workgroup sum of r^2
+  Geo g;
+  Taps taps;            // A (primal) or A^T (adjoint)
+  double q[kMaxM * kMaxM];  // Q (primal) or Q^T (adjoint), row-major
+  double dt;
+  int L, logL, Lh, TN, logTN;
+};
+
+// Inverse transform + update (row a4).
+struct BwdArgs {
+  const void* in;       // x2 [B][Lh][M][N] complex (double2 or float2)
+  double* u;            // updated in place, or receives delta
+  const double* scale;  // [L] scaling applied after the inverse DFT
+  const double2* tw;
+  const double2* mix;   // [Lh][M][M]
+  double* part;         // per-workgroup max |delta| over the monitored step
+  Geo g;
+  int L, logL, Lh, TN, logTN;
+};
+
+// Batched Krylov solvers (row a3).
+struct KrylovArgs {
+  void* X;       // solution
+  void* R;       // residual (holds the right-hand side on entry)
+  void* P[2];    // search directions (double-buffered: the matvec reads halos)
+  void* V[2];    // BiCGStab: A p (double-buffered), COCG: V[0] = A p
+  void* Rh;      // BiCGStab: shadow residual
+  void* S;       // BiCGStab: s
+  void* T;       // BiCGStab: A s
+  const double2* shift;  // [num_sys] shifted operator is I - shift * A
+  SysState* st;
+  double* part;  // [quantity][num_sys][wps]
+  unsigned long long* work;  // element counters per kernel class
+  Geo g;
+  Taps taps;
+  int num_sys, wps, chunk;
+  double tol2;
+  int maxit;
+};
+
+// Partial-sum quantities of the Krylov kernels: part[q][system][chunk].
+enum PartialQ {
+  QP_RHO0_RE = 0, QP_RHO0_IM, QP_RHO1_RE, QP_RHO1_IM, QP_RR0, QP_RR1, QP_A_RE, QP_A_IM,
+  QP_B_RE, QP_B_IM, QP_TT, QP_BB, QP_COUNT
+};
+
+enum KernelClass {
+  KC_FWD = 0, KC_BWD, KC_COCG_A, KC_COCG_B, KC_BICG_1, KC_BICG_2, KC_BICG_3,
+  KC_FFT_INNER, KC_RESIDUAL, KC_MISC, KC_INIT, KC_GRAD
+};
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_fwd(int M, bool adj, bool from_r, bool out_f32, const FwdArgs& a, int B,
+                      hipStream_t st);
+hipError_t launch_bwd(int M, bool adj, bool to_delta, bool in_f32, const BwdArgs& a, int B,
+                      hipStream_t st);
+hipError_t launch_residual(int M, bool adj, const FwdArgs& a, double* r_out, int B, hipStream_t st);
+hipError_t launch_finalize(const double* part_sum, int n_sum, const double* part_max, int n_max,
+                           double* out, hipStream_t st);
+hipError_t launch_init_u(double* u, const double* u0, int B, int L, int M, int N, hipStream_t st);
+hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t st);
+hipError_t launch_norms_bn(const double* v, int B, int N, double* part, int nparts,
+                           hipStream_t st);
+hipError_t launch_cocg_a(bool f32, const KrylovArgs& a, int k, hipStream_t st);
+hipError_t launch_cocg_b(bool f32, const KrylovArgs& a, int k, hipStream_t st);
+hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, hipStream_t st);
+hipError_t launch_krylov_init(const KrylovArgs& a, hipStream_t st);
+hipError_t launch_count_active(const SysState* st, int n, int* out, hipStream_t s);
+hipError_t launch_copy_c128_in(void* dst, bool f32, const double* src, int64_t n, hipStream_t st);
+hipError_t launch_copy_c128_out(double* dst, const void* src, bool f32, int64_t n,
+                                hipStream_t st);
+hipError_t launch_grad(int M, const double* u, const double* lam, double* gu0, double* part,
+                       const Taps& dtaps, const double* q, double dt, const Geo& g, int B,
+                       int L, int nblk, hipStream_t st);
+hipError_t launch_grad_finalize(const double* part, int nblk, int B, double* gnu,
+                                hipStream_t st);
+
+}  // namespace aao

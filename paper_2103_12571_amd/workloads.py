@@ -60,7 +60,7 @@ WORKLOADS = {
                            init="gauss", tol=1e-11, inner="bicgstab"),
     # 2D heat nu=1e-2 on 1024^2, L=32, dt=1e-3; complex64 inner solves.
     "heat2d_1024_mixed": Workload("heat2d_1024_mixed", "heat2d", 1024, 1024, 32, 3, 1e-3, nu=1e-2,
-                                  init="modes", tol=1e-10, inner="cocg", precision="mixed",
+                                  init="modes", tol=1e-8, inner="cocg", precision="mixed",
                                   inner_tol=1e-6),
     # 2D advection-diffusion nu=5e-3, v=(1, 0.5) on 512^2, L=64, B=8; adjoint.
     "advdiff2d_512_adj": Workload("advdiff2d_512_adj", "advdiff2d", 512, 512, 64, 3, 1e-3, nu=5e-3,

@@ -1,0 +1,76 @@
+"""Adjoint sweep (transposed all-at-once system) and gradients vs the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_12571_amd import workloads as wl
+from paper_2103_12571_amd.stencil import plan_for
+from tests.gpu_util import dev, host, need_gpu, rel_l2, say, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(w):
+    op = oracle.stencil_for(w.kind, w.nx, w.ny, nu=w.nu, c=w.vel)
+    Q = oracle.collocation_matrix(oracle.radau_right_nodes(w.M))
+    return op, Q
+
+
+@pytest.mark.parametrize("name,w,tol", [
+    ("advdiff_16x12_L8_B2_fp64", wl.WORKLOADS["advdiff2d_512_adj"].with_(nx=16, ny=12, L=8, batch=2,
+                                                                           precision="fp64", inner_tol=1e-13,
+                                                                           tol=1e-13), 1e-10),
+    ("advdiff_32_L16_B2_mixed", wl.WORKLOADS["advdiff2d_512_adj"].with_(nx=32, ny=32, L=16, batch=2), 1e-8),
+    ("heat2d_20x16_L4_M2_cocg", wl.WORKLOADS["heat2d_256"].with_(nx=20, ny=16, L=4, M=2, tol=1e-13), 1e-10),
+])
+def test_adjoint_solve_parity(name, w, tol):
+    need_gpu()
+    say("adjoint", name)
+    p = plan_for(w)
+    g = np.random.default_rng(7).standard_normal((w.batch, w.N))
+    lam, info = p.adjoint_solve(dev(g), tol=1e-12 if w.precision == "fp64" else 1e-9, max_iter=40)
+    lam = host(lam)
+    op, Q = _setup(w)
+    for b in range(w.batch):
+        lo = oracle.adjoint_solve(op, Q, w.dt, g[b], w.L)
+        e = rel_l2(lam[b], lo)
+        say("  b", b, "sweeps", info["iterations"], "err %.2e" % e)
+        assert e < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("mixed", 1e-7)])
+def test_gradients_vs_oracle_and_fd(prec, tol):
+    """Workload advdiff2d_512_adj at 24 x 20, L = 8, B = 2."""
+    need_gpu()
+    from paper_2103_12571_amd.autograd import solve_uT
+    w = wl.WORKLOADS["advdiff2d_512_adj"].with_(nx=24, ny=20, L=8, batch=2, precision=prec,
+                                                 inner_tol=1e-13 if prec == "fp64" else 1e-6,
+                                                 tol=1e-13 if prec == "fp64" else 1e-9)
+    say("gradients", prec)
+    u0 = wl.initial_batch(w)
+    ut = wl.target_batch(w)
+    u0_t = dev(u0).requires_grad_(True)
+    nu_t = torch.tensor(w.nu, dtype=torch.float64, device="cuda", requires_grad=True)
+    uT = solve_uT(u0_t, nu_t, w, tol=w.tol, adj_tol=w.tol)
+    loss = 0.5 * ((uT - dev(ut)) ** 2).sum()
+    loss.backward()
+    gu0 = host(u0_t.grad)
+    gnu = float(nu_t.grad)
+    op, Q = _setup(w)
+    gnu_o = 0.0
+    for b in range(w.batch):
+        U = oracle.sequential_solve(op, Q, w.dt, u0[b], w.L)
+        lam = oracle.adjoint_solve(op, Q, w.dt, U[-1, -1] - ut[b], w.L)
+        g0, gn = oracle.gradients(op, Q, w.dt, U, lam)
+        assert rel_l2(gu0[b], g0) < tol
+        gnu_o += gn
+    say("  dJ/dnu gpu %.12e oracle %.12e" % (gnu, gnu_o))
+    assert abs(gnu - gnu_o) < tol * abs(gnu_o)
+    # central finite difference of the oracle loss in nu
+    def J(nu):
+        o = oracle.stencil_for(w.kind, w.nx, w.ny, nu=nu, c=w.vel)
+        return sum(0.5 * np.sum((oracle.sequential_solve(o, Q, w.dt, u0[b], w.L)[-1, -1] - ut[b]) ** 2)
+                   for b in range(w.batch))
+    h = 1e-6 * w.nu
+    fd = (J(w.nu + h) - J(w.nu - h)) / (2 * h)
+    assert abs(gnu - fd) < 1e-5 * abs(fd)

@@ -1,0 +1,208 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Row a1: aao_residual vs the oracle's w - C u.  Rows a2-a4: aao_precond vs a
+sparse direct solve of C_alpha (eq. (prec)).  Row a3: aao_shifted_solve vs a
+sparse direct solve of I - c A.  Rows a1-a5 together: aao_solve vs sequential
+collocation.  Shapes span several transform tiles and a ragged tail.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_12571_amd import workloads as wl
+from paper_2103_12571_amd.stencil import plan_for
+from tests.gpu_util import dev, host, need_gpu, rel_l2, say, torch
+
+pytestmark = pytest.mark.gpu
+
+Q3 = None
+
+
+def _oracle_op(w):
+    return oracle.stencil_for(w.kind, w.nx, w.ny, nu=w.nu, c=w.vel)
+
+
+def _Q(M):
+    return oracle.collocation_matrix(oracle.radau_right_nodes(M))
+
+
+CASES = [
+    # name, workload, overrides (ragged N: 40 and 10x12 are not multiples of the tile)
+    ("heat1d_N40_L8_M3", wl.WORKLOADS["heat1d_64"].with_(nx=40, L=8, nu=0.05), {}),
+    ("heat1d_N200_L4_M2_B2", wl.WORKLOADS["heat1d_64"].with_(nx=200, L=4, M=2, batch=2), {}),
+    ("heat2d_12x10_L16_M3", wl.WORKLOADS["heat2d_256"].with_(nx=12, ny=10, L=16), {}),
+    ("heat2d_20x24_L1_M1", wl.WORKLOADS["heat2d_256"].with_(nx=20, ny=24, L=1, M=1), {}),
+    ("adv1d_N130_L32_M3", wl.WORKLOADS["adv1d_4096"].with_(nx=130, L=32), {}),
+    ("advdiff_10x12_L8_M3_B2", wl.WORKLOADS["advdiff2d_512_adj"].with_(nx=10, ny=12, L=8, batch=2,
+                                                                         precision="fp64"), {}),
+    ("heat2d_64x64_L2_M4", wl.WORKLOADS["heat2d_256"].with_(nx=64, ny=64, L=2, M=4), {}),
+]
+
+
+def _rand(shape, seed):
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+@pytest.mark.parametrize("name,w,ov", CASES, ids=[c[0] for c in CASES])
+def test_residual_parity(name, w, ov):
+    need_gpu()
+    say("residual", name)
+    p = plan_for(w, inner_tol=1e-13)
+    u0 = _rand((w.batch, w.N), 1)
+    u = _rand((w.batch, w.L, w.M, w.N), 2)
+    p.set_u0(dev(u0))
+    r, nrm = p.residual(dev(u))
+    r = host(r)
+    op, Q = _oracle_op(w), _Q(w.M)
+    for b in range(w.batch):
+        ro = oracle.residual(op, Q, w.dt, u0[b], u[b])
+        assert rel_l2(r[b], ro) < 1e-13
+    w2 = w.M * np.sum(u0 ** 2)
+    ro_all = np.stack([oracle.residual(op, Q, w.dt, u0[b], u[b]) for b in range(w.batch)])
+    assert abs(nrm - np.linalg.norm(ro_all) / math.sqrt(w2)) < 1e-12 * nrm
+
+
+@pytest.mark.parametrize("alpha", [1e-6, 1e-2, 0.3])
+@pytest.mark.parametrize("name,w,ov", CASES, ids=[c[0] for c in CASES])
+def test_precond_parity(name, w, ov, alpha):
+    """delta = C_alpha^{-1} r through Alg. 1's diagonalised steps (rows a2-a4)."""
+    need_gpu()
+    say("precond", name, alpha)
+    p = plan_for(w, inner_tol=1e-14, inner_maxit=4000)
+    r = _rand((w.batch, w.L, w.M, w.N), 3)
+    d = host(p.precond(dev(r), alpha))
+    op, Q = _oracle_op(w), _Q(w.M)
+    for b in range(w.batch):
+        do = oracle.precond_solve(op, Q, w.dt, alpha, r[b])
+        # round-off of the diagonalisation grows like L / alpha (Theorem 2)
+        tol = 1e-12 * max(1.0, w.L / alpha) ** 0.5 * 10
+        assert rel_l2(d[b], do) < max(tol, 1e-11), (b, rel_l2(d[b], do))
+
+
+@pytest.mark.parametrize("inner,kind", [("cocg", "heat2d"), ("bicgstab", "advdiff2d"), ("bicgstab", "heat2d")])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_shifted_solve_parity(inner, kind, prec):
+    """Row a3 alone: (I - c_s A) x_s = b_s for complex shifts c_s."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    need_gpu()
+    say("shifted", inner, kind, prec)
+    w = wl.Workload("t", kind, 24, 20, 8, 3, 1e-3, nu=1e-2, vel=(1.0, 0.5), inner=inner, precision=prec)
+    tol = 1e-13 if prec == "fp64" else 1e-6
+    p = plan_for(w, inner_tol=tol)
+    S = 10
+    rng = np.random.default_rng(4)
+    shifts = (rng.uniform(0.0, 0.05, S) + 1j * rng.uniform(-0.05, 0.05, S))
+    b = rng.standard_normal((S, w.N)) + 1j * rng.standard_normal((S, w.N))
+    x, its = p.shifted_solve(shifts, torch.as_tensor(b, device="cuda"))
+    x = x.cpu().numpy()
+    A = _oracle_op(w).matrix()
+    for s in range(S):
+        xo = spla.spsolve((sp.identity(w.N) - shifts[s] * A).tocsc(), b[s])
+        assert rel_l2(x[s], xo) < (1e-11 if prec == "fp64" else 5e-5)
+    assert np.all(its > 0)
+
+
+def _solve_and_compare(w, tol_rel, **solve_kw):
+    p = plan_for(w)
+    u0 = wl.initial_batch(w)
+    p.set_u0(dev(u0))
+    u, info = p.solve(**solve_kw)
+    u = host(u)
+    op, Q = _oracle_op(w), _Q(w.M)
+    errs = []
+    for b in range(w.batch):
+        backend = "sparse" if w.N * w.M <= 20000 else "spectral"
+        Uo = oracle.sequential_solve(op, Q, w.dt, u0[b], w.L, backend=backend)
+        errs.append(rel_l2(u[b], Uo))
+    say("  sweeps", info["iterations"], "alpha", ["%.2e" % a for a in info["alpha"]],
+        "inner mean", ["%.1f" % v for v in info["inner_mean"]], "err", ["%.2e" % e for e in errs])
+    assert max(errs) <= tol_rel, errs
+    return info, errs
+
+
+def test_solve_heat1d_64_fixed_alpha_residual_stop():
+    """Workload heat1d_64: fixed alpha = 1e-3, stop at relative residual 1e-12."""
+    need_gpu()
+    w = wl.WORKLOADS["heat1d_64"]
+    say("solve", w.name)
+    info, _ = _solve_and_compare(w, 1e-10, alphas=[w.alpha], tol=w.tol, stop="residual", max_iter=20)
+    assert info["converged"]
+    # closed form: u(T) = R(dT lam)^L sin(2 pi x) (Pade R of Radau IIA, M = 3)
+    z = w.dt * w.nu * (2 * math.cos(2 * math.pi / w.nx) - 2) * w.nx ** 2
+    R = (1 + 2 * z / 5 + z * z / 20) / (1 - 3 * z / 5 + 3 * z * z / 20 - z ** 3 / 60)
+    assert abs(R ** 4 - 0.85403178) < 1e-8
+
+
+def test_richardson_factor_matches_closed_form():
+    """Per sweep the single-mode error shrinks by |alpha R^L / (1 - alpha R^L)|,
+    derived from eq. (Riteration); Theorem 1 bounds it by alpha / (1 - alpha)."""
+    need_gpu()
+    w = wl.WORKLOADS["heat1d_64"]
+    op, Q = _oracle_op(w), _Q(w.M)
+    u0 = wl.initial_condition(w)
+    Ustar = oracle.sequential_solve(op, Q, w.dt, u0, w.L)
+    z = w.dt * w.nu * (2 * math.cos(2 * math.pi / w.nx) - 2) * w.nx ** 2
+    RL = ((1 + 2 * z / 5 + z * z / 20) / (1 - 3 * z / 5 + 3 * z * z / 20 - z ** 3 / 60)) ** w.L
+    for alpha in (0.05, 0.3):
+        p = plan_for(w, inner_tol=1e-14)
+        p.set_u0(dev(u0[None]))
+        u = torch.as_tensor(np.tile(u0, (1, w.L, w.M, 1)), device="cuda").contiguous()
+        errs = []
+        for _ in range(3):
+            p.sweep(u, alpha)
+            errs.append(np.linalg.norm(host(u)[0] - Ustar))
+        rho = abs(alpha * RL / (1 - alpha * RL))
+        say("  alpha", alpha, "ratios", errs[1] / errs[0], errs[2] / errs[1], "closed form", rho)
+        assert abs(errs[1] / errs[0] - rho) < 1e-6 * rho
+        assert abs(errs[2] / errs[1] - rho) < 1e-5 * rho
+        assert rho <= alpha / (1 - alpha)
+
+
+@pytest.mark.parametrize("name,w,tol", [
+    ("heat2d_32_L16_cocg_alg2", wl.WORKLOADS["heat2d_256"].with_(nx=32, ny=32, L=16), 1e-10),
+    ("heat2d_48x40_L8_M2_B3", wl.WORKLOADS["heat2d_256"].with_(nx=48, ny=40, L=8, M=2, batch=3), 1e-10),
+    ("adv1d_512_L32_bicgstab_alg2", wl.WORKLOADS["adv1d_4096"].with_(nx=512, L=32), 1e-10),
+    ("advdiff_32_L16_B2_fp64", wl.WORKLOADS["advdiff2d_512_adj"].with_(nx=32, ny=32, L=16, batch=2,
+                                                                         precision="fp64", inner_tol=1e-12), 1e-10),
+    ("heat2d_64_L8_mixed", wl.WORKLOADS["heat2d_1024_mixed"].with_(nx=64, ny=64, L=8), 1e-8),
+])
+def test_solve_alg2_parity(name, w, tol):
+    need_gpu()
+    say("solve", name)
+    info, _ = _solve_and_compare(w, tol, tol=w.tol, max_iter=40)
+    assert info["converged"]
+
+
+def test_solve_errors_and_edges():
+    need_gpu()
+    from paper_2103_12571_amd import binding as bd
+    w = wl.WORKLOADS["heat1d_64"]
+    p = plan_for(w)
+    u = torch.zeros((1, w.L, w.M, w.N), dtype=torch.float64, device="cuda")
+    with pytest.raises(bd.AAOError) as e:
+        p.sweep(u, 0.1)  # before aao_set_u0
+    assert e.value.status == bd.AAO_ESTATE
+    u0 = wl.initial_batch(w)
+    p.set_u0(dev(u0))
+    for bad in (0.0, 1.0, 2.0):
+        with pytest.raises(bd.AAOError) as e:
+            p.sweep(u, bad)
+        assert e.value.status == bd.AAO_EINVAL
+    bad_u0 = u0.copy()
+    bad_u0[0, 3] = np.nan
+    with pytest.raises(bd.AAOError) as e:
+        p.set_u0(dev(bad_u0))
+    assert e.value.status == bd.AAO_ENAN
+    p.set_u0(dev(u0))
+    _, info = p.solve(alphas=[0.4], tol=1e-30, max_iter=2, raise_on_noconv=False)
+    assert info["iterations"] == 2 and not info["converged"]
+    with pytest.raises(bd.AAOError) as e:
+        p.solve(alphas=[0.4], tol=1e-30, max_iter=2)
+    assert e.value.status == bd.AAO_ENOCONV
+    # zero initial value: converged at once, u stays zero
+    p.set_u0(torch.zeros((1, w.N), dtype=torch.float64, device="cuda"))
+    u, info = p.solve(alphas=[1e-3], tol=1e-12, stop="residual", max_iter=5)
+    assert float(u.abs().max()) == 0.0
