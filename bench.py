@@ -143,7 +143,7 @@ def main():
                     "traffic": tr, "launches": s["launches"],
                     "avg_launch_us": round(1e3 * s["ms"] / s["launches"], 2),
                     "bytes_per_launch": s["bytes"] / s["launches"]}
-    kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+    kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3), "bytes": v["bytes"],
                    "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 and v["bytes"] > 0 else None}
                for k, v in stats.items()}
 

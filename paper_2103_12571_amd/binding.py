@@ -244,6 +244,8 @@ class Plan:
                             {"laststep": AAO_STOP_LASTSTEP, "residual": AAO_STOP_RESIDUAL}[stop],
                             int(max_iter), C.byref(info))
         if s != AAO_OK and (raise_on_noconv or s != AAO_ENOCONV):
+            if s == AAO_ENOCONV:
+                raise AAOError(s, "%s; history %s" % (lib().aao_last_error().decode(), info.as_dict()))
             check(s)
         return u, info.as_dict()
 
@@ -253,9 +255,12 @@ class Plan:
         info = aao_solve_info()
         al = None if alphas is None else np.ascontiguousarray(alphas, dtype=np.float64)
         self._sync_stream()
-        check(lib().aao_adjoint_solve(self._h, _ptr(g), _ptr(lam), _dptr(al) if al is not None else None,
-                                      0 if al is None else len(al), float(m0), float(tol), int(max_iter),
-                                      C.byref(info)))
+        s = lib().aao_adjoint_solve(self._h, _ptr(g), _ptr(lam), _dptr(al) if al is not None else None,
+                                    0 if al is None else len(al), float(m0), float(tol), int(max_iter),
+                                    C.byref(info))
+        if s == AAO_ENOCONV:
+            raise AAOError(s, "%s; history %s" % (lib().aao_last_error().decode(), info.as_dict()))
+        check(s)
         return lam, info.as_dict()
 
     def grad(self, u, lam):

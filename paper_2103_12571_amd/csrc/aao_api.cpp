@@ -67,6 +67,10 @@ struct aao_plan {
   int TN = 2, logTN = 1, ntiles = 0;
   // inner solves
   int S = 0, wps = 1, chunk = 256, nvec = 0;
+  int cgTX = 1, cgTY = 1, cg_ntx = 1, cg_nty = 1, cg_ntiles = 1, Rx = 0, Ry = 0;
+  int* hlist = nullptr;      // pinned staging of active-system lists (3 x S)
+  char* hstate = nullptr;    // pinned copies of the system states (2 x S)
+  hipEvent_t chk_ev[2] = {nullptr, nullptr};
   bool f32 = false;
   size_t csize = 16;
   // library-owned device tables and pinned staging
@@ -82,7 +86,7 @@ struct aao_plan {
   char* ws = nullptr;
   size_t ws_bytes = 0, ws_need = 0;
   size_t off_vec = 0, off_part = 0, off_st = 0, off_fb = 0, off_norms = 0, off_cnt = 0,
-         off_work = 0, off_gpart = 0, off_npart = 0;
+         off_work = 0, off_gpart = 0, off_npart = 0, off_list = 0;
   int fb_slots = 0, grad_blocks = 0;
   // state
   const double* u0 = nullptr;
@@ -103,6 +107,7 @@ struct aao_plan {
   unsigned long long* work() const { return reinterpret_cast<unsigned long long*>(ws + off_work); }
   double* gpart() const { return reinterpret_cast<double*>(ws + off_gpart); }
   double* npart() const { return reinterpret_cast<double*>(ws + off_npart); }
+  int* dlist() const { return reinterpret_cast<int*>(ws + off_list); }
   double2* d_tw() const { return reinterpret_cast<double2*>(dtab + off_tw); }
   double* d_sf() const { return reinterpret_cast<double*>(dtab + off_sf); }
   double* d_sb() const { return reinterpret_cast<double*>(dtab + off_sb); }
@@ -259,6 +264,7 @@ aao::KrylovArgs krylov_args(aao_plan* p, int adj, int nsys) {
   a.st = p->st();
   a.part = p->part();
   a.work = p->work();
+  a.sys_list = p->dlist();
   a.g = {p->nx, p->ny, p->N};
   a.taps = adj ? p->tapsT : p->taps;
   a.num_sys = nsys;
@@ -269,30 +275,164 @@ aao::KrylovArgs krylov_args(aao_plan* p, int adj, int nsys) {
   return a;
 }
 
+aao::CgArgs cg_args(aao_plan* p, int adj, int nsys) {
+  aao::CgArgs a{};
+  a.X = p->vec(0);
+  a.R[0] = p->vec(1);
+  a.R[1] = p->vec(2);
+  a.P[0] = p->vec(3);
+  a.P[1] = p->vec(4);
+  a.shift = p->d_sh();
+  a.st = p->st();
+  a.part = p->part();
+  a.sys_list = p->dlist();
+  a.work = p->work();
+  a.g = {p->nx, p->ny, p->N};
+  a.taps = adj ? p->tapsT : p->taps;
+  a.num_sys = nsys;
+  a.TX = p->cgTX;
+  a.TY = p->cgTY;
+  a.ntx = p->cg_ntx;
+  a.nty = p->cg_nty;
+  a.ntiles = p->cg_ntiles;
+  a.Rx = p->Rx;
+  a.Ry = p->Ry;
+  auto magic = [](int d) { return ((1ull << 40) + (unsigned long long)d - 1) / (unsigned long long)d; };
+  a.m_ntx = magic(a.ntx);
+  a.m_tx = magic(a.TX);
+  a.m_pw = magic(a.TX + 4 * a.Rx);
+  a.m_qw = magic(a.TX + 2 * a.Rx);
+  a.xcd_band = (a.ntiles % 8 == 0 && a.ntiles >= 16) ? a.ntiles / 8 : 0;
+  a.fused = a.ntiles <= 256 ? 1 : 0;
+  a.tol2 = p->inner_tol * p->inner_tol;
+  a.maxit = p->inner_maxit;
+  return a;
+}
+
+// Lagged convergence checks: every few iterations the system states are
+// copied to pinned memory behind an event, and the copy made one interval
+// earlier is inspected; the launch queue never drains on a host round trip.
+// Iterations launched after a system converged exit at once (its state says
+// inactive).  Returns the final states in p->hread + 128.
+struct LagCheck {
+  aao_plan* p;
+  int nsys;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int pending = -1, cur = 0;
+  aao::SysState* buf(int i) const {
+    return reinterpret_cast<aao::SysState*>(p->hstate + (size_t)i * p->S * sizeof(aao::SysState));
+  }
+};
+
+// Enqueue a state copy; if an earlier one is outstanding, wait for it and
+// return the number of systems still active in it (else -1).  Active systems
+// are listed in p->hlist[cur] and uploaded when the set shrank.
+aao_status lag_check(LagCheck& c, int& nact, int& n_out, bool final_check) {
+  aao_plan* p = c.p;
+  n_out = -1;
+  if (c.pending >= 0) {
+    HIPCHK(hipEventSynchronize(c.ev[c.pending]));
+    const aao::SysState* hs = c.buf(c.pending);
+    int* lst = p->hlist + (size_t)c.pending * p->S;
+    int n = 0;
+    for (int i = 0; i < c.nsys; ++i)
+      if (hs[i].active) lst[n++] = i;
+    n_out = n;
+    c.pending = -1;
+    if (n > 0 && n < nact) {
+      HIPCHK(hipMemcpyAsync(p->dlist(), lst, (size_t)n * sizeof(int), hipMemcpyHostToDevice, p->stream));
+      nact = n;
+    }
+    if (n == 0 || final_check) return AAO_OK;
+  }
+  HIPCHK(hipMemcpyAsync(c.buf(c.cur), p->st(), (size_t)c.nsys * sizeof(aao::SysState), hipMemcpyDeviceToHost,
+                        p->stream));
+  HIPCHK(hipEventRecord(c.ev[c.cur], p->stream));
+  c.pending = c.cur;
+  c.cur ^= 1;
+  return AAO_OK;
+}
+
+aao_status lag_begin(aao_plan* p, LagCheck& c, int nsys) {
+  c.p = p;
+  c.nsys = nsys;
+  for (int i = 0; i < 2; ++i) {
+    if (!p->chk_ev[i]) HIPCHK(hipEventCreateWithFlags(&p->chk_ev[i], hipEventDisableTiming));
+    c.ev[i] = p->chk_ev[i];
+  }
+  return AAO_OK;
+}
+
+// Single-pass COCG over all nsys systems.
+aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
+  aao::CgArgs a = cg_args(p, adj, nsys);
+  aao::KrylovArgs ka = krylov_args(p, adj, nsys);
+  int* lst0 = p->hlist + (size_t)2 * p->S;
+  for (int i = 0; i < nsys; ++i) lst0[i] = i;
+  HIPCHK(hipMemcpyAsync(p->dlist(), lst0, (size_t)nsys * sizeof(int), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(aao::launch_krylov_init(ka, p->stream));
+  int nact = nsys;
+  HIPCHK(timed(p, aao::KC_COCG_B, [&] { return aao::launch_cg_init(p->f32, a, nact, p->stream); }));
+  if (!a.fused) HIPCHK(timed(p, aao::KC_MISC, [&] { return aao::launch_cg_scalars(a, -1, nact, p->stream); }));
+  LagCheck c;
+  aao_status ls = lag_begin(p, c, nsys);
+  if (ls != AAO_OK) return ls;
+  int next_check = 4;
+  // fused: pass k advances the scalars from pass k-1's sums (pass inner_maxit
+  // only records the iteration cap); else a scalar kernel follows each pass
+  const int last = a.fused ? p->inner_maxit : p->inner_maxit - 1;
+  for (int k = 0; k <= last; ++k) {
+    HIPCHK(timed(p, aao::KC_COCG_A, [&] { return aao::launch_cg_pass(p->f32, a, k, nact, p->stream); }));
+    if (!a.fused)
+      HIPCHK(timed(p, aao::KC_MISC, [&] { return aao::launch_cg_scalars(a, k, nact, p->stream); }));
+    if (k + 1 == next_check) {
+      next_check += (k < 16) ? 4 : 8;
+      int n;
+      aao_status s = lag_check(c, nact, n, false);
+      if (s != AAO_OK) return s;
+      if (n == 0) break;
+    }
+  }
+  if (c.pending >= 0) {  // drain the last outstanding copy
+    int n;
+    aao_status s = lag_check(c, nact, n, true);
+    if (s != AAO_OK) return s;
+  }
+  return AAO_OK;
+}
+
 // Solve the nsys shifted systems held in R into X.  Fills the per-system
 // iteration counts into p->hread (as SysState) after the final check.
 aao_status inner_solve(aao_plan* p, int adj, int nsys) {
+  if (p->inner == AAO_INNER_COCG) return inner_solve_cg(p, adj, nsys);
   aao::KrylovArgs a = krylov_args(p, adj, nsys);
+  int* lst0 = p->hlist + (size_t)2 * p->S;
+  for (int i = 0; i < nsys; ++i) lst0[i] = i;
+  HIPCHK(hipMemcpyAsync(p->dlist(), lst0, (size_t)nsys * sizeof(int), hipMemcpyHostToDevice, p->stream));
   HIPCHK(aao::launch_krylov_init(a, p->stream));
-  int* hcnt = reinterpret_cast<int*>(p->hread);
+  int nact = nsys;
+  LagCheck c;
+  aao_status ls = lag_begin(p, c, nsys);
+  if (ls != AAO_OK) return ls;
+  int next_check = 4;
   for (int k = 0; k <= p->inner_maxit; ++k) {
-    if (p->inner == AAO_INNER_COCG) {
-      HIPCHK(timed(p, aao::KC_COCG_A, [&] { return aao::launch_cocg_a(p->f32, a, k, p->stream); }));
-      if (k < p->inner_maxit)
-        HIPCHK(timed(p, aao::KC_COCG_B, [&] { return aao::launch_cocg_b(p->f32, a, k, p->stream); }));
-    } else {
-      HIPCHK(timed(p, aao::KC_BICG_1, [&] { return aao::launch_bicg(1, p->f32, a, k, p->stream); }));
-      if (k < p->inner_maxit) {
-        HIPCHK(timed(p, aao::KC_BICG_2, [&] { return aao::launch_bicg(2, p->f32, a, k, p->stream); }));
-        HIPCHK(timed(p, aao::KC_BICG_3, [&] { return aao::launch_bicg(3, p->f32, a, k, p->stream); }));
-      }
+    HIPCHK(timed(p, aao::KC_BICG_1, [&] { return aao::launch_bicg(1, p->f32, a, k, nact, p->stream); }));
+    if (k < p->inner_maxit) {
+      HIPCHK(timed(p, aao::KC_BICG_2, [&] { return aao::launch_bicg(2, p->f32, a, k, nact, p->stream); }));
+      HIPCHK(timed(p, aao::KC_BICG_3, [&] { return aao::launch_bicg(3, p->f32, a, k, nact, p->stream); }));
     }
-    if ((k + 1) % kCheckEvery == 0 || k == p->inner_maxit) {
-      HIPCHK(timed(p, aao::KC_MISC, [&] { return aao::launch_count_active(p->st(), nsys, p->cnt(), p->stream); }));
-      HIPCHK(hipMemcpyAsync(hcnt, p->cnt(), sizeof(int), hipMemcpyDeviceToHost, p->stream));
-      HIPCHK(hipStreamSynchronize(p->stream));
-      if (*hcnt == 0) break;
+    if (k + 1 == next_check) {
+      next_check += (k < 16) ? 4 : 8;
+      int n;
+      aao_status s = lag_check(c, nact, n, false);
+      if (s != AAO_OK) return s;
+      if (n == 0) break;
     }
+  }
+  if (c.pending >= 0) {
+    int n;
+    aao_status s = lag_check(c, nact, n, true);
+    if (s != AAO_OK) return s;
   }
   return AAO_OK;
 }
@@ -333,6 +473,8 @@ aao_status alloc_tables(aao_plan* p) {
   HIPCHK(hipMalloc(&p->dtab, p->tab_bytes));
   HIPCHK(hipHostMalloc(&p->htab, p->tab_bytes, hipHostMallocDefault));
   HIPCHK(hipHostMalloc(&p->hread, p->hread_bytes, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc(&p->hlist, (size_t)3 * p->S * sizeof(int), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc(&p->hstate, (size_t)2 * p->S * sizeof(aao::SysState), hipHostMallocDefault));
   std::vector<double2> tw(p->L / 2 + 1);
   for (int k = 0; k < (int)tw.size(); ++k) {
     const double ang = -2.0 * M_PI * (double)k / (double)p->L;
@@ -410,7 +552,7 @@ const char* aao_last_error(void) { return g_err.c_str(); }
 
 const char* aao_kernel_name(int c) {
   static const char* names[AAO_NUM_KERNELS] = {
-      "fwd_residual_dft_l", "bwd_idft_l_update", "cocg_matvec", "cocg_update",
+      "fwd_residual_dft_l", "bwd_idft_l_update", "cocg_pass", "cocg_init",
       "bicgstab_p_matvec", "bicgstab_s_matvec", "bicgstab_update", "fft_inner",
       "residual", "misc", "init", "grad"};
   return (c >= 0 && c < AAO_NUM_KERNELS) ? names[c] : "";
@@ -529,6 +671,30 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
     p->chunk = chunk;
     p->wps = (p->N + chunk - 1) / chunk;
   }
+  // COCG tiles: TX x TY points per workgroup; Rx, Ry: stencil reach
+  for (int i = 0; i < A->ntaps; ++i) {
+    p->Rx = std::max(p->Rx, std::abs(p->taps.dx[i]));
+    p->Ry = std::max(p->Ry, std::abs(p->taps.dy[i]));
+  }
+  if (p->ny == 1) {
+    p->cgTX = std::min(p->nx, 1024);
+    p->cgTY = 1;
+  } else {
+    p->cgTX = std::min(p->nx, 64);
+    p->cgTY = std::min(p->ny, 16);
+  }
+  {  // the COCG tile's two-hop region must fit 8 points per thread (LDS <= 32 KB)
+    auto pts = [&](int tx, int ty) { return (tx + 4 * p->Rx) * (ty + 4 * p->Ry); };
+    while (pts(p->cgTX, p->cgTY) > 8 * aao::kBlock && p->cgTY > 1) p->cgTY = (p->cgTY + 1) / 2;
+    while (pts(p->cgTX, p->cgTY) > 8 * aao::kBlock && p->cgTX > 8) p->cgTX = (p->cgTX + 1) / 2;
+    if (pts(p->cgTX, p->cgTY) > 8 * aao::kBlock) {
+      delete p;
+      return fail(AAO_EINVAL, "stencil reach too large for the COCG tile");
+    }
+  }
+  p->cg_ntx = (p->nx + p->cgTX - 1) / p->cgTX;
+  p->cg_nty = (p->ny + p->cgTY - 1) / p->cgTY;
+  p->cg_ntiles = p->cg_ntx * p->cg_nty;
   p->fb_slots = std::max(p->ntiles * p->B, 1024);
   p->grad_blocks = std::max(1, std::min(256, (p->N + aao::kBlock - 1) / aao::kBlock));
 
@@ -537,7 +703,10 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   p->off_vec = off;
   off = align256(off + (size_t)p->nvec * p->S * p->N * p->csize);
   p->off_part = off;
-  off = align256(off + (size_t)aao::QP_COUNT * p->S * p->wps * sizeof(double));
+  off = align256(off + std::max((size_t)aao::QP_COUNT * p->S * p->wps, (size_t)2 * 5 * p->S * p->cg_ntiles) *
+                           sizeof(double));
+  p->off_list = off;
+  off = align256(off + (size_t)p->S * sizeof(int));
   p->off_st = off;
   off = align256(off + (size_t)p->S * sizeof(aao::SysState));
   p->off_fb = off;
@@ -849,7 +1018,7 @@ aao_status aao_get_stats(aao_plan_t p, aao_kernel_stats* out) {
   // Krylov kernels: complex words read + written per element processed, for
   // k > 0 (slot c) and k == 0 (slot 16 + c).
   struct { int c; double later, first; } kw[] = {
-      {aao::KC_COCG_A, 4, 3}, {aao::KC_COCG_B, 6, 5}, {aao::KC_BICG_1, 6, 4},
+      {aao::KC_COCG_A, 6, 4}, {aao::KC_COCG_B, 1, 1}, {aao::KC_BICG_1, 6, 4},
       {aao::KC_BICG_2, 4, 4}, {aao::KC_BICG_3, 7, 6}};
   for (auto& k : kw) {
     const double e_later = (double)w[k.c], e_first = (double)w[16 + k.c];
@@ -901,6 +1070,10 @@ void aao_destroy(aao_plan_t p) {
   if (p->dtab) hipFree(p->dtab);
   if (p->htab) hipHostFree(p->htab);
   if (p->hread) hipHostFree(p->hread);
+  if (p->hlist) hipHostFree(p->hlist);
+  if (p->hstate) hipHostFree(p->hstate);
+  for (auto e : p->chk_ev)
+    if (e) hipEventDestroy(e);
   delete p;
 }
 

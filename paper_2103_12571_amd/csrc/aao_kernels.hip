@@ -10,119 +10,13 @@
 // in-place radix-2 FFT (bit-reversed load, natural-order result) and separated
 // again; the M x M node transform of each frequency is applied on the way out.
 #include "aao_kernels.hpp"
+#include "aao_device.hpp"
 
 namespace aao {
 
 namespace {
 
-template <typename T> struct cvec;
-template <> struct cvec<double> { using type = double2; };
-template <> struct cvec<float> { using type = float2; };
-
-__device__ __forceinline__ double2 mk(double x, double y) { double2 r; r.x = x; r.y = y; return r; }
-__device__ __forceinline__ float2 mkf(float x, float y) { float2 r; r.x = x; r.y = y; return r; }
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return mk(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return mk(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
-  return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
-}
-__device__ __forceinline__ double2 cconj(double2 a) { return mk(a.x, -a.y); }
-__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
-  double d = b.x * b.x + b.y * b.y;
-  return mk((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
-}
-__device__ __forceinline__ double2 to_d2(double2 a) { return a; }
-__device__ __forceinline__ double2 to_d2(float2 a) { return mk(a.x, a.y); }
-template <typename V> __device__ __forceinline__ V from_d2(double2 a);
-template <> __device__ __forceinline__ double2 from_d2<double2>(double2 a) { return a; }
-template <> __device__ __forceinline__ float2 from_d2<float2>(double2 a) {
-  return mkf((float)a.x, (float)a.y);
-}
-
-// generic complex arithmetic for T2 in {double2, float2}
-template <typename V> __device__ __forceinline__ V vadd(V a, V b) { V r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
-template <typename V> __device__ __forceinline__ V vsub(V a, V b) { V r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
-template <typename V> __device__ __forceinline__ V vmul(V a, V b) {
-  V r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
-}
-template <typename V, typename S> __device__ __forceinline__ V vscale(V a, S s) { V r; r.x = a.x * s; r.y = a.y * s; return r; }
-template <typename V> __device__ __forceinline__ V vzero() { V r; r.x = 0; r.y = 0; return r; }
-
-__device__ __forceinline__ int wrap_index(int x, int y, int dx, int dy, const Geo& g) {
-  int xx = x + dx;
-  xx += (xx < 0) ? g.nx : 0;
-  xx -= (xx >= g.nx) ? g.nx : 0;
-  int yy = y + dy;
-  yy += (yy < 0) ? g.ny : 0;
-  yy -= (yy >= g.ny) ? g.ny : 0;
-  return yy * g.nx + xx;
-}
-
-__device__ __forceinline__ int bitrev(int v, int logL) {
-  return logL == 0 ? 0 : (int)(__brev((unsigned)v) >> (32 - logL));
-}
-
-// Sum of K values over the 256-thread block; every thread receives the result.
-// The butterfly over lanes adds each pair in both orders, which is exact-equal,
-// so all lanes (and every workgroup doing the same reduction) agree bitwise.
-template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double* sh) {
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    double x = v[i];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    v[i] = x;
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < K; ++i) sh[wid * K + i] = v[i];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < K; ++i) v[i] = (sh[i] + sh[K + i]) + (sh[2 * K + i] + sh[3 * K + i]);
-}
-
-__device__ __forceinline__ double block_max(double v, double* sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
-}
-
-// In-place radix-2 DIT FFT over the row index of c[L][ncol] (bit-reversed
-// input order, natural output order).  INV selects e^{+2 pi i ...}.
-template <bool INV>
-__device__ __forceinline__ void lds_fft(double2* c, const double2* tw, int L, int logL, int ncol) {
-  for (int s = 0; s < logL; ++s) {
-    const int half = 1 << s;
-    const int tstride = L >> (s + 1);
-    __syncthreads();
-    const int total = (L >> 1) * ncol;
-    for (int idx = threadIdx.x; idx < total; idx += kBlock) {
-      const int col = idx % ncol;
-      const int k = idx / ncol;
-      const int pos = k & (half - 1);
-      const int i0 = ((k >> s) << (s + 1)) + pos;
-      const int i1 = i0 + half;
-      double2 w = tw[pos * tstride];
-      if (INV) w.y = -w.y;
-      const double2 a = c[i0 * ncol + col];
-      const double2 b = cmul(w, c[i1 * ncol + col]);
-      c[i0 * ncol + col] = cadd(a, b);
-      c[i1 * ncol + col] = csub(a, b);
-    }
-  }
-  __syncthreads();
-}
+using namespace dev;
 
 // ----------------------------------------------------------------------------
 // Forward transform with the fused all-at-once residual.
@@ -471,131 +365,6 @@ __device__ __forceinline__ V shifted_apply(const KrylovArgs& a, int n, V center,
   return vsub(center, vmul(shift, acc));
 }
 
-// COCG (conjugate orthogonal CG, bilinear form x^T y) for complex-symmetric
-// I - c A.  Kernel A: convergence test, p = r + beta p_old, q = (I - cA) p,
-// partial mu = p^T q.  At k = 0 also rho_0 = r^T r and ||b||^2.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cocg_a(KrylovArgs a, int k) {
-  using V = typename cvec<T>::type;
-  __shared__ double sh[4 * 8];
-  const int s = blockIdx.y;
-  SysState* st = a.st + s;
-  // One read of the flag per workgroup: kernel A may clear it concurrently
-  // (workgroup 0, on convergence), and every thread must take the same path.
-  __shared__ int act;
-  if (threadIdx.x == 0) act = st->active;
-  __syncthreads();
-  if (!act) return;
-  double2 beta = mk(0, 0);
-  if (k > 0) {
-    const int cur = k & 1, prv = cur ^ 1;
-    const int qs[6] = {QP_RHO0_RE + 2 * cur, QP_RHO0_IM + 2 * cur, QP_RHO0_RE + 2 * prv,
-                       QP_RHO0_IM + 2 * prv, QP_RR0 + cur, QP_BB};
-    double v[6];
-    reduce_parts<6>(a, qs, s, v, sh);
-    const bool conv = v[4] <= a.tol2 * v[5];
-    if (conv || k >= a.maxit || st->breakdown) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->active = 0;
-        st->iters = k;
-        st->flag = conv ? 0 : (st->breakdown ? 2 : 1);
-      }
-      return;
-    }
-    beta = cdiv(mk(v[0], v[1]), mk(v[2], v[3]));
-  }
-  const size_t off = (size_t)s * a.g.N;
-  const V* R = reinterpret_cast<const V*>(a.R) + off;
-  const V* Po = reinterpret_cast<const V*>(a.P[(k + 1) & 1]) + off;
-  V* Pn = reinterpret_cast<V*>(a.P[k & 1]) + off;
-  V* Qv = reinterpret_cast<V*>(a.V[0]) + off;
-  const V sft = from_d2<V>(a.shift[s]);
-  const V bt = from_d2<V>(beta);
-  const int n0 = blockIdx.x * a.chunk;
-  const int n1 = min(a.g.N, n0 + a.chunk);
-  double mu_re = 0, mu_im = 0, rho_re = 0, rho_im = 0, bb = 0;
-  if (k == 0) {
-    for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
-      const V r = R[n];
-      const V q = shifted_apply(a, n, r, sft, [&](int i) { return R[i]; });
-      Pn[n] = r;
-      Qv[n] = q;
-      mu_re += (double)r.x * q.x - (double)r.y * q.y;
-      mu_im += (double)r.x * q.y + (double)r.y * q.x;
-      rho_re += (double)r.x * r.x - (double)r.y * r.y;
-      rho_im += 2.0 * (double)r.x * r.y;
-      bb += (double)r.x * r.x + (double)r.y * r.y;
-    }
-    double v[5] = {mu_re, mu_im, rho_re, rho_im, bb};
-    const int qs[5] = {QP_A_RE, QP_A_IM, QP_RHO0_RE, QP_RHO0_IM, QP_BB};
-    write_parts<5>(a, qs, s, v, sh);
-  } else {
-    for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
-      const V p = vadd(R[n], vmul(bt, Po[n]));
-      const V q = shifted_apply(a, n, p, sft, [&](int i) { return vadd(R[i], vmul(bt, Po[i])); });
-      Pn[n] = p;
-      Qv[n] = q;
-      mu_re += (double)p.x * q.x - (double)p.y * q.y;
-      mu_im += (double)p.x * q.y + (double)p.y * q.x;
-    }
-    double v[2] = {mu_re, mu_im};
-    const int qs[2] = {QP_A_RE, QP_A_IM};
-    write_parts<2>(a, qs, s, v, sh);
-  }
-  count_work(a, KC_COCG_A, k, n1 - n0);
-}
-
-// Kernel B: a = rho / mu, x += a p, r -= a q, partial rho' = r^T r, ||r||^2.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cocg_b(KrylovArgs a, int k) {
-  using V = typename cvec<T>::type;
-  __shared__ double sh[4 * 8];
-  const int s = blockIdx.y;
-  SysState* st = a.st + s;
-  // One read of the flag per workgroup: kernel A may clear it concurrently
-  // (workgroup 0, on convergence), and every thread must take the same path.
-  __shared__ int act;
-  if (threadIdx.x == 0) act = st->active;
-  __syncthreads();
-  if (!act) return;
-  const int cur = k & 1, nxt = cur ^ 1;
-  double v[4];
-  {
-    const int qs[4] = {QP_RHO0_RE + 2 * cur, QP_RHO0_IM + 2 * cur, QP_A_RE, QP_A_IM};
-    reduce_parts<4>(a, qs, s, v, sh);
-  }
-  double2 al = mk(0, 0);
-  const double mu2 = v[2] * v[2] + v[3] * v[3];
-  if (mu2 > 0.0 && isfinite(mu2)) {
-    al = cdiv(mk(v[0], v[1]), mk(v[2], v[3]));
-  } else if (blockIdx.x == 0 && threadIdx.x == 0 && (v[0] != 0.0 || v[1] != 0.0)) {
-    st->breakdown = 1;  // consumed by the next kernel A
-  }
-  const size_t off = (size_t)s * a.g.N;
-  V* X = reinterpret_cast<V*>(a.X) + off;
-  V* R = reinterpret_cast<V*>(a.R) + off;
-  const V* Pc = reinterpret_cast<const V*>(a.P[k & 1]) + off;
-  const V* Qv = reinterpret_cast<const V*>(a.V[0]) + off;
-  const V av = from_d2<V>(al);
-  const int n0 = blockIdx.x * a.chunk;
-  const int n1 = min(a.g.N, n0 + a.chunk);
-  double rho_re = 0, rho_im = 0, rr = 0;
-  for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
-    const V p = Pc[n];
-    const V x = (k == 0) ? vmul(av, p) : vadd(X[n], vmul(av, p));
-    const V r = vsub(R[n], vmul(av, Qv[n]));
-    X[n] = x;
-    R[n] = r;
-    rho_re += (double)r.x * r.x - (double)r.y * r.y;
-    rho_im += 2.0 * (double)r.x * r.y;
-    rr += (double)r.x * r.x + (double)r.y * r.y;
-  }
-  double w[3] = {rho_re, rho_im, rr};
-  const int qs[3] = {QP_RHO0_RE + 2 * nxt, QP_RHO0_IM + 2 * nxt, QP_RR0 + nxt};
-  write_parts<3>(a, qs, s, w, sh);
-  count_work(a, KC_COCG_B, k, n1 - n0);
-}
-
 // BiCGStab (Hermitian inner products <a, b> = sum conj(a) b), r_hat = r_0.
 // Phase 1: convergence test, beta = (rho_k / rho_{k-1}) (alpha / omega),
 // p = r + beta (p_old - omega v_old), v = (I - cA) p, partial <r_hat, v>.
@@ -603,7 +372,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bicg1(KrylovArgs a, int k) {
   using V = typename cvec<T>::type;
   __shared__ double sh[4 * 8];
-  const int s = blockIdx.y;
+  const int s = a.sys_list[blockIdx.y];
   SysState* st = a.st + s;
   // One read of the flag per workgroup: kernel A may clear it concurrently
   // (workgroup 0, on convergence), and every thread must take the same path.
@@ -680,7 +449,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bicg2(KrylovArgs a, int k) {
   using V = typename cvec<T>::type;
   __shared__ double sh[4 * 8];
-  const int s = blockIdx.y;
+  const int s = a.sys_list[blockIdx.y];
   SysState* st = a.st + s;
   // One read of the flag per workgroup: kernel A may clear it concurrently
   // (workgroup 0, on convergence), and every thread must take the same path.
@@ -735,7 +504,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bicg3(KrylovArgs a, int k) {
   using V = typename cvec<T>::type;
   __shared__ double sh[4 * 8];
-  const int s = blockIdx.y;
+  const int s = a.sys_list[blockIdx.y];
   SysState* st = a.st + s;
   // One read of the flag per workgroup: kernel A may clear it concurrently
   // (workgroup 0, on convergence), and every thread must take the same path.
@@ -795,6 +564,12 @@ __global__ void k_krylov_init(SysState* st, int n) {
     z.rho = mk(1, 0);
     z.alpha = mk(1, 0);
     z.omega = mk(1, 0);
+    z.beta = mk(0, 0);
+    z.gamma = mk(0, 0);
+    z.bb = 0.0;
+    z.rr = 0.0;
+    z.gamma2[0] = z.gamma2[1] = mk(0, 0);
+    z.alpha2[0] = z.alpha2[1] = mk(0, 0);
     st[i] = z;
   }
 }
@@ -981,22 +756,8 @@ hipError_t launch_norms_bn(const double* v, int B, int N, double* part, int npar
   return hipGetLastError();
 }
 
-hipError_t launch_cocg_a(bool f32, const KrylovArgs& a, int k, hipStream_t st) {
-  dim3 grid(a.wps, a.num_sys);
-  if (f32) hipLaunchKernelGGL(k_cocg_a<float>, grid, dim3(kBlock), 0, st, a, k);
-  else hipLaunchKernelGGL(k_cocg_a<double>, grid, dim3(kBlock), 0, st, a, k);
-  return hipGetLastError();
-}
-
-hipError_t launch_cocg_b(bool f32, const KrylovArgs& a, int k, hipStream_t st) {
-  dim3 grid(a.wps, a.num_sys);
-  if (f32) hipLaunchKernelGGL(k_cocg_b<float>, grid, dim3(kBlock), 0, st, a, k);
-  else hipLaunchKernelGGL(k_cocg_b<double>, grid, dim3(kBlock), 0, st, a, k);
-  return hipGetLastError();
-}
-
-hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, hipStream_t st) {
-  dim3 grid(a.wps, a.num_sys);
+hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, int nact, hipStream_t st) {
+  dim3 grid(a.wps, nact);
   switch (phase) {
     case 1:
       if (f32) hipLaunchKernelGGL(k_bicg1<float>, grid, dim3(kBlock), 0, st, a, k);

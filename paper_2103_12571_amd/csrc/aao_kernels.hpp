@@ -29,8 +29,39 @@ struct SysState {
   int flag;       // 0 converged, 1 hit the iteration cap, 2 breakdown
   int breakdown;  // set by an update kernel, consumed by the next matvec kernel
   double2 rho;    // BiCGStab: rho_k
-  double2 alpha;  // BiCGStab: alpha_k
+  double2 alpha;  // BiCGStab, COCG: alpha_k
   double2 omega;  // BiCGStab: omega_k
+  double2 beta;   // COCG: beta_k
+  double2 gamma;  // COCG: gamma_k = r_k^T r_k
+  double bb;      // ||b||^2
+  double rr;      // ||r_k||^2
+  double2 gamma2[2];  // COCG, fused scalar update: gamma_k and alpha_k by parity of k
+  double2 alpha2[2];
+};
+
+// Single-pass COCG over 2D tiles (row a3).  Pass k reads R[k&1], P[(k+1)&1]
+// and X, writes R[(k+1)&1], P[k&1] and X; the LDS tile holds p on a two-hop
+// halo and r_{k+1} on a one-hop halo so that s = (I - cA) p and
+// w = (I - cA) r_{k+1} need no extra global vector.
+struct CgArgs {
+  void* X;
+  void* R[2];
+  void* P[2];
+  const double2* shift;
+  SysState* st;
+  double* part;             // [5][num_sys][ntiles]
+  const int* sys_list;      // active systems of this launch
+  unsigned long long* work;
+  Geo g;
+  Taps taps;
+  int num_sys;
+  int TX, TY, ntx, nty, ntiles, Rx, Ry;
+  // ceil(2^40 / d) for exact division by ntx, TX and the two halo widths
+  unsigned long long m_ntx, m_tx, m_pw, m_qw;
+  int xcd_band;  // ntiles / 8 when tiles are banded per XCD, else 0
+  int fused;     // 1: each pass advances the scalars itself (partials double-buffered)
+  double tol2;
+  int maxit;
 };
 
 // Forward transform + fused residual (rows a1, a2).
@@ -74,6 +105,7 @@ struct KrylovArgs {
   SysState* st;
   double* part;  // [quantity][num_sys][wps]
   unsigned long long* work;  // element counters per kernel class
+  const int* sys_list;       // systems of this launch (grid.y entries)
   Geo g;
   Taps taps;
   int num_sys, wps, chunk;
@@ -104,9 +136,12 @@ hipError_t launch_init_u(double* u, const double* u0, int B, int L, int M, int N
 hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t st);
 hipError_t launch_norms_bn(const double* v, int B, int N, double* part, int nparts,
                            hipStream_t st);
-hipError_t launch_cocg_a(bool f32, const KrylovArgs& a, int k, hipStream_t st);
-hipError_t launch_cocg_b(bool f32, const KrylovArgs& a, int k, hipStream_t st);
-hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, hipStream_t st);
+hipError_t launch_cg_init(bool f32, const CgArgs& a, int nact, hipStream_t st);
+hipError_t launch_cg_pass(bool f32, const CgArgs& a, int k, int nact, hipStream_t st);
+hipError_t launch_cg_scalars(const CgArgs& a, int k, int nact, hipStream_t st);
+size_t cg_lds_bytes(bool f32, const CgArgs& a);
+int cg_points_per_thread(const CgArgs& a);
+hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, int nact, hipStream_t st);
 hipError_t launch_krylov_init(const KrylovArgs& a, hipStream_t st);
 hipError_t launch_count_active(const SysState* st, int n, int* out, hipStream_t s);
 hipError_t launch_copy_c128_in(void* dst, bool f32, const double* src, int64_t n, hipStream_t st);
