@@ -89,6 +89,45 @@ def oracle_solution(w, u0):
                      for b in range(w.batch)])
 
 
+def speedup_block(np, torch, wl, plan_for, with_oracle):
+    """Time to solution of the FP64 and the mixed (complex64 inner) paths on
+    the 2D heat 1024^2, L = 32 workload, each to its own stop rule, with the
+    relative l2 error of each result against the oracle checked after."""
+    base = wl.WORKLOADS["heat2d_1024_mixed"]
+    paths = {
+        # FP64: COCG to 1e-9, Alg. 2; mixed: complex64 COCG to 1e-6, alpha from
+        # the residual-relative balance.  Both stop at ||du_L||_inf <= 5e-8.
+        "fp64": base.with_(precision="fp64", inner_tol=1e-9, tol=5e-8),
+        "mixed": base.with_(precision="mixed", inner_tol=1e-6, tol=5e-8),
+    }
+    u0 = wl.initial_batch(base)
+    ref = None
+    if with_oracle:
+        t0 = time.perf_counter()
+        ref = oracle_solution(base, u0)
+        t_or = time.perf_counter() - t0
+    res = {"workload": base.name, "dof": base.dof, "target_rel_l2": 1e-8}
+    for name, w in paths.items():
+        plan = plan_for(w)
+        plan.set_u0(torch.as_tensor(u0, device="cuda"))
+        u = torch.empty(plan.shape, dtype=torch.float64, device="cuda")
+        print("bench: %s path on %s" % (name, w.name), file=sys.stderr, flush=True)
+        run_solves(plan, u, w, 1, False)  # warm-up
+        el, sw, infos, _ = run_solves(plan, u, w, 2, False)
+        r = {"time_to_solution_s": el / 2, "sweeps": sw / 2, "inner_tol": w.inner_tol,
+             "alphas": [float("%.3e" % a) for a in infos[-1]["alpha"]],
+             "inner_iters_mean": [round(v, 1) for v in infos[-1]["inner_mean"]]}
+        if ref is not None:
+            r["rel_l2_vs_oracle"] = float(np.linalg.norm(u.cpu().numpy() - ref) / np.linalg.norm(ref))
+        res[name] = r
+        del plan, u
+        torch.cuda.empty_cache()
+    res["speedup"] = res["fp64"]["time_to_solution_s"] / res["mixed"]["time_to_solution_s"]
+    if ref is not None:
+        res["oracle_time_s"] = t_or
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -191,6 +230,8 @@ def main():
             "time_to_solution_s": t_or}
         out["parity"] = {"rel_l2_vs_oracle": float(np.linalg.norm(u_gpu - ref) / np.linalg.norm(ref))}
         out["gpu_time_to_solution_s"] = elapsed / args.steps
+    if not args.no_speedup:
+        out["mixed_vs_fp64"] = speedup_block(np, torch, wl, plan_for, not args.no_cpu_baseline)
     print(json.dumps(out), flush=True)
 
 
