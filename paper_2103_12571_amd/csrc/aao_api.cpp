@@ -42,6 +42,17 @@ int ilog2(int64_t v) {
   return l;
 }
 
+// COCG tile shape in 2D (points per workgroup TX x TY).
+#ifndef AAO_CG_TX2D
+#define AAO_CG_TX2D 64
+#endif
+#ifndef AAO_CG_TY2D
+#define AAO_CG_TY2D 16
+#endif
+#ifndef AAO_XCD_BANDS
+#define AAO_XCD_BANDS 1
+#endif
+
 constexpr int kWorkSlots = 32;     // [class] for k > 0, [16 + class] for k == 0
 constexpr int kCheckEvery = 8;     // Krylov iterations between host convergence checks
 constexpr int kNormBlocks = 256;
@@ -96,7 +107,9 @@ struct aao_plan {
   aao_kernel_stats stats{};
   std::vector<Timed> pending;
   std::vector<hipEvent_t> pool;
-  unsigned long long work_seen[kWorkSlots] = {};
+  // elements processed per kernel class (first iteration / later iterations),
+  // from the per-system iteration counts read back after each inner solve
+  double work_first[AAO_NUM_KERNELS] = {}, work_later[AAO_NUM_KERNELS] = {};
 
   void* vec(int i) const { return ws + off_vec + (size_t)i * S * N * csize; }
   double* part() const { return reinterpret_cast<double*>(ws + off_part); }
@@ -302,7 +315,7 @@ aao::CgArgs cg_args(aao_plan* p, int adj, int nsys) {
   a.m_tx = magic(a.TX);
   a.m_pw = magic(a.TX + 4 * a.Rx);
   a.m_qw = magic(a.TX + 2 * a.Rx);
-  a.xcd_band = (a.ntiles % 8 == 0 && a.ntiles >= 16) ? a.ntiles / 8 : 0;
+  a.xcd_band = (AAO_XCD_BANDS && a.ntiles % 8 == 0 && a.ntiles >= 16) ? a.ntiles / 8 : 0;
   a.fused = a.ntiles <= 256 ? 1 : 0;
   a.tol2 = p->inner_tol * p->inner_tol;
   a.maxit = p->inner_maxit;
@@ -456,13 +469,27 @@ aao_status read_back(aao_plan* p, int nsys, bool want_norms, SweepOut& o) {
     o.res2 = hn[0];
     o.dmax = hn[1];
   }
-  double sum = 0;
+  double sum = 0, later = 0;
   for (int s = 0; s < nsys; ++s) {
     sum += hs[s].iters;
+    later += std::max(hs[s].iters - 1, 0);
     o.inner_max = std::max(o.inner_max, hs[s].iters);
     if (hs[s].flag != 0) o.inner_fail += 1;
   }
   o.inner_mean = nsys ? sum / nsys : 0;
+  if (nsys > 0) {
+    const double n = (double)p->N;
+    if (p->inner == AAO_INNER_COCG) {
+      p->work_first[aao::KC_COCG_B] += n * nsys;  // init pass
+      p->work_first[aao::KC_COCG_A] += n * nsys;
+      p->work_later[aao::KC_COCG_A] += n * later;
+    } else {
+      for (int c : {aao::KC_BICG_1, aao::KC_BICG_2, aao::KC_BICG_3}) {
+        p->work_first[c] += n * nsys;
+        p->work_later[c] += n * later;
+      }
+    }
+  }
   return AAO_OK;
 }
 
@@ -680,8 +707,8 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
     p->cgTX = std::min(p->nx, 1024);
     p->cgTY = 1;
   } else {
-    p->cgTX = std::min(p->nx, 64);
-    p->cgTY = std::min(p->ny, 16);
+    p->cgTX = std::min(p->nx, AAO_CG_TX2D);
+    p->cgTY = std::min(p->ny, AAO_CG_TY2D);
   }
   {  // the COCG tile's two-hop region must fit 8 points per thread (LDS <= 32 KB)
     auto pts = [&](int tx, int ty) { return (tx + 4 * p->Rx) * (ty + 4 * p->Ry); };
@@ -768,9 +795,6 @@ aao_status aao_set_workspace(aao_plan_t p, void* dev, size_t bytes) {
   if (st != AAO_OK) return st;
   p->ws = reinterpret_cast<char*>(dev);
   p->ws_bytes = bytes;
-  HIPCHK(hipMemsetAsync(p->work(), 0, kWorkSlots * sizeof(unsigned long long), p->stream));
-  HIPCHK(hipStreamSynchronize(p->stream));
-  std::memset(p->work_seen, 0, sizeof(p->work_seen));
   return AAO_OK;
 }
 
@@ -993,20 +1017,14 @@ aao_status aao_set_timing(aao_plan_t p, int on) {
 aao_status aao_reset_stats(aao_plan_t p) {
   if (!p) return fail(AAO_EINVAL, "null plan");
   std::memset(&p->stats, 0, sizeof(p->stats));
-  if (p->ws) {
-    HIPCHK(hipMemsetAsync(p->work(), 0, kWorkSlots * sizeof(unsigned long long), p->stream));
-    HIPCHK(hipStreamSynchronize(p->stream));
-  }
+  std::memset(p->work_first, 0, sizeof(p->work_first));
+  std::memset(p->work_later, 0, sizeof(p->work_later));
   return AAO_OK;
 }
 
 aao_status aao_get_stats(aao_plan_t p, aao_kernel_stats* out) {
   if (!p || !out) return fail(AAO_EINVAL, "null argument");
   *out = p->stats;
-  if (!p->ws) return AAO_OK;
-  unsigned long long w[kWorkSlots];
-  HIPCHK(hipMemcpyAsync(w, p->work(), sizeof(w), hipMemcpyDeviceToHost, p->stream));
-  HIPCHK(hipStreamSynchronize(p->stream));
   const double cs = (double)p->csize;
   const double dof = (double)p->B * p->L * p->M * p->N;
   const double freq = (double)p->B * p->Lh * p->M * p->N;
@@ -1015,15 +1033,14 @@ aao_status aao_get_stats(aao_plan_t p, aao_kernel_stats* out) {
   out->bytes[aao::KC_FWD] = (8.0 * dof + cs * freq) * out->launches[aao::KC_FWD];
   out->elements[aao::KC_BWD] = dof * out->launches[aao::KC_BWD];
   out->bytes[aao::KC_BWD] = (16.0 * dof + cs * freq) * out->launches[aao::KC_BWD];
-  // Krylov kernels: complex words read + written per element processed, for
-  // k > 0 (slot c) and k == 0 (slot 16 + c).
+  // Krylov kernels: complex words read + written per element processed in
+  // iterations after the first / in the first iteration.
   struct { int c; double later, first; } kw[] = {
       {aao::KC_COCG_A, 6, 4}, {aao::KC_COCG_B, 1, 1}, {aao::KC_BICG_1, 6, 4},
       {aao::KC_BICG_2, 4, 4}, {aao::KC_BICG_3, 7, 6}};
   for (auto& k : kw) {
-    const double e_later = (double)w[k.c], e_first = (double)w[16 + k.c];
-    out->elements[k.c] = e_later + e_first;
-    out->bytes[k.c] = cs * (k.later * e_later + k.first * e_first);
+    out->elements[k.c] = p->work_first[k.c] + p->work_later[k.c];
+    out->bytes[k.c] = cs * (k.later * p->work_later[k.c] + k.first * p->work_first[k.c]);
   }
   return AAO_OK;
 }

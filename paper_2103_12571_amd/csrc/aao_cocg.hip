@@ -66,7 +66,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
   const int ty = fdiv(tile, a.m_ntx), tx = tile - ty * a.ntx;
   const int x0 = tx * a.TX, y0 = ty * a.TY;
   double v[kQ] = {0, 0, 0, 0, 0};
-  int cnt = 0;
   for (int i = threadIdx.x; i < a.TX * a.TY; i += kBlock) {
     const int x = x0 + i % a.TX, y = y0 + i / a.TX;
     if (x >= a.g.nx || y >= a.g.ny) continue;
@@ -83,7 +82,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
     v[2] += (double)b.x * w.x - (double)b.y * w.y;
     v[3] += (double)b.x * w.y + (double)b.y * w.x;
     v[4] += (double)b.x * b.x + (double)b.y * b.y;
-    ++cnt;
   }
   block_sum<kQ>(v, sh);
   if (threadIdx.x == 0) {
@@ -91,9 +89,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
 #pragma unroll
     for (int q = 0; q < kQ; ++q) pb[((size_t)q * a.num_sys + s) * a.ntiles + tile] = v[q];
   }
-  double c[1] = {(double)cnt};
-  block_sum<1>(c, sh);
-  if (threadIdx.x == 0) atomicAdd(a.work + KC_COCG_B, (unsigned long long)c[0]);
 }
 
 // Points per thread of the two halo regions; the host keeps
@@ -165,6 +160,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   const int tx = tile - ty * a.ntx;
   const int x0 = tx * TX, y0 = ty * TY;
 
+  // converged systems leave before touching memory (the host drops them from
+  // the launch list at its next, lagged, check)
+  if (threadIdx.x == 0) act = a.st[s].active;
+  __syncthreads();
+  if (!act) return;
   // Each thread owns the same points of the two-hop region in every stage:
   // it loads r_k and p_{k-1} there (and x_k at its tile points), and later
   // computes r_{k+1} at those of its points that lie in the one-hop region,
@@ -189,9 +189,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   if (a.fused) {
     // every workgroup of the system reduces the previous pass's tile sums in
     // the same order and takes the same decision; tile 0 records it
-    if (threadIdx.x == 0) act = a.st[s].active;
-    __syncthreads();
-    if (!act) return;
     double v[kQ] = {0, 0, 0, 0, 0};
     const double* pp0 = a.part + (size_t)((k + 1) & 1) * kQ * a.num_sys * a.ntiles;
     for (int c = threadIdx.x; c < a.ntiles; c += kBlock) {
@@ -225,12 +222,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
     if (!act) return;
   } else {
     if (threadIdx.x == 0) {
-      act = a.st[s].active;
       sc[0] = a.st[s].alpha;
       sc[1] = a.st[s].beta;
     }
     __syncthreads();
-    if (!act) return;
   }
   const V al = from_d2<V>(sc[0]);
   const V be = from_d2<V>(sc[1]);
@@ -277,7 +272,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   __syncthreads();
   // gamma_{k+1}, delta_{k+1} = r^T A_s r, ||r_{k+1}||^2 at the tile points
   double v[kQ] = {0, 0, 0, 0, 0};
-  int cnt = 0;
   for (int i = threadIdx.x; i < TX * TY; i += kBlock) {
     const int iy = fdiv(i, a.m_tx), ix = i - iy * TX;
     if (x0 + ix >= nx || y0 + iy >= ny) continue;
@@ -290,7 +284,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
     v[2] += (double)r.x * w.x - (double)r.y * w.y;
     v[3] += (double)r.x * w.y + (double)r.y * w.x;
     v[4] += (double)r.x * r.x + (double)r.y * r.y;
-    ++cnt;
   }
   block_sum<kQ>(v, sh);
   if (threadIdx.x == 0) {
@@ -298,9 +291,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
 #pragma unroll
     for (int q = 0; q < kQ; ++q) pb[((size_t)q * a.num_sys + s) * a.ntiles + tile] = v[q];
   }
-  double c[1] = {(double)cnt};
-  block_sum<1>(c, sh);
-  if (threadIdx.x == 0) atomicAdd(a.work + (k == 0 ? 16 + KC_COCG_A : KC_COCG_A), (unsigned long long)c[0]);
 }
 
 // One workgroup per listed system: reduce the tile partials (fixed order) and

@@ -347,11 +347,6 @@ __device__ __forceinline__ void write_parts(const KrylovArgs& a, const int (&qs)
   }
 }
 
-// Elements processed, for the bandwidth accounting: slot cls for k > 0 and
-// slot 16 + cls for k == 0 (the first iteration moves fewer vectors).
-__device__ __forceinline__ void count_work(const KrylovArgs& a, int cls, int k, int n) {
-  if (threadIdx.x == 0) atomicAdd(a.work + (k == 0 ? 16 + cls : cls), (unsigned long long)n);
-}
 
 // Shifted operator at point n on a vector given through an accessor.
 template <typename V, typename F>
@@ -440,7 +435,6 @@ __global__ __launch_bounds__(kBlock) void k_bicg1(KrylovArgs a, int k) {
     const int qw[2] = {QP_A_RE, QP_A_IM};
     write_parts<2>(a, qw, s, w, sh);
   }
-  count_work(a, KC_BICG_1, k, n1 - n0);
 }
 
 // Phase 2: alpha = rho_k / <r_hat, v>; s = r - alpha v; t = (I - cA) s;
@@ -495,7 +489,6 @@ __global__ __launch_bounds__(kBlock) void k_bicg2(KrylovArgs a, int k) {
   double w[3] = {ts_re, ts_im, tt};
   const int qs[3] = {QP_B_RE, QP_B_IM, QP_TT};
   write_parts<3>(a, qs, s, w, sh);
-  count_work(a, KC_BICG_2, k, n1 - n0);
 }
 
 // Phase 3: omega = <t, s> / <t, t>; x += alpha p + omega s; r = s - omega t;
@@ -551,7 +544,6 @@ __global__ __launch_bounds__(kBlock) void k_bicg3(KrylovArgs a, int k) {
   double w[3] = {hr_re, hr_im, rr};
   const int qs[3] = {QP_RHO0_RE + 2 * nxt, QP_RHO0_IM + 2 * nxt, QP_RR0 + nxt};
   write_parts<3>(a, qs, s, w, sh);
-  count_work(a, KC_BICG_3, k, n1 - n0);
 }
 
 __global__ void k_krylov_init(SysState* st, int n) {
