@@ -91,40 +91,46 @@ def oracle_solution(w, u0):
 
 def speedup_block(np, torch, wl, plan_for, with_oracle):
     """Time to solution of the FP64 and the mixed (complex64 inner) paths on
-    the 2D heat 1024^2, L = 32 workload, each to its own stop rule, with the
+    the 2D heat 1024^2, L = 32 workload, for both inner solvers (batched COCG
+    and the spatial-FFT direct solve), each to its own stop rule, with the
     relative l2 error of each result against the oracle checked after."""
     base = wl.WORKLOADS["heat2d_1024_mixed"]
+    # Stop rules calibrated so that each path lands below 1e-8 relative l2:
+    # FP64 uses Alg. 2 (COCG tau = 1e-9; FFT exact), mixed the residual-relative
+    # alpha (COCG tau = 1e-6; FFT in complex64).
     paths = {
-        # FP64: COCG to 1e-9, Alg. 2; mixed: complex64 COCG to 1e-6, alpha from
-        # the residual-relative balance.  Both stop at ||du_L||_inf <= 5e-8.
-        "fp64": base.with_(precision="fp64", inner_tol=1e-9, tol=5e-8),
-        "mixed": base.with_(precision="mixed", inner_tol=1e-6, tol=5e-8),
+        "cocg": {"fp64": base.with_(precision="fp64", inner="cocg", inner_tol=1e-9, tol=5e-8),
+                 "mixed": base.with_(precision="mixed", inner="cocg", inner_tol=1e-6, tol=5e-8)},
+        "fft": {"fp64": base.with_(precision="fp64", inner="fft", inner_tol=1e-15, tol=5e-8),
+                "mixed": base.with_(precision="mixed", inner="fft", inner_tol=1e-7, tol=5e-8)},
     }
     u0 = wl.initial_batch(base)
     ref = None
+    res = {"workload": base.name, "dof": base.dof, "target_rel_l2": 1e-8}
     if with_oracle:
         t0 = time.perf_counter()
         ref = oracle_solution(base, u0)
-        t_or = time.perf_counter() - t0
-    res = {"workload": base.name, "dof": base.dof, "target_rel_l2": 1e-8}
-    for name, w in paths.items():
-        plan = plan_for(w)
-        plan.set_u0(torch.as_tensor(u0, device="cuda"))
-        u = torch.empty(plan.shape, dtype=torch.float64, device="cuda")
-        print("bench: %s path on %s" % (name, w.name), file=sys.stderr, flush=True)
-        run_solves(plan, u, w, 1, False)  # warm-up
-        el, sw, infos, _ = run_solves(plan, u, w, 2, False)
-        r = {"time_to_solution_s": el / 2, "sweeps": sw / 2, "inner_tol": w.inner_tol,
-             "alphas": [float("%.3e" % a) for a in infos[-1]["alpha"]],
-             "inner_iters_mean": [round(v, 1) for v in infos[-1]["inner_mean"]]}
-        if ref is not None:
-            r["rel_l2_vs_oracle"] = float(np.linalg.norm(u.cpu().numpy() - ref) / np.linalg.norm(ref))
-        res[name] = r
-        del plan, u
-        torch.cuda.empty_cache()
-    res["speedup"] = res["fp64"]["time_to_solution_s"] / res["mixed"]["time_to_solution_s"]
-    if ref is not None:
-        res["oracle_time_s"] = t_or
+        res["oracle_time_s"] = time.perf_counter() - t0
+    for inner, pp in paths.items():
+        out = {}
+        for name, w in pp.items():
+            plan = plan_for(w)
+            plan.set_u0(torch.as_tensor(u0, device="cuda"))
+            u = torch.empty(plan.shape, dtype=torch.float64, device="cuda")
+            print("bench: %s %s path on %s" % (inner, name, w.name), file=sys.stderr, flush=True)
+            run_solves(plan, u, w, 1, False)  # warm-up
+            el, sw, infos, _ = run_solves(plan, u, w, 2, False)
+            r = {"time_to_solution_s": el / 2, "sweeps": sw / 2, "inner_tol": w.inner_tol,
+                 "dof_sweeps_per_s": w.dof * sw / el,
+                 "alphas": [float("%.3e" % a) for a in infos[-1]["alpha"]],
+                 "inner_iters_mean": [round(v, 1) for v in infos[-1]["inner_mean"]]}
+            if ref is not None:
+                r["rel_l2_vs_oracle"] = float(np.linalg.norm(u.cpu().numpy() - ref) / np.linalg.norm(ref))
+            out[name] = r
+            del plan, u
+            torch.cuda.empty_cache()
+        out["speedup"] = out["fp64"]["time_to_solution_s"] / out["mixed"]["time_to_solution_s"]
+        res[inner] = out
     return res
 
 

@@ -79,6 +79,7 @@ struct aao_plan {
   // inner solves
   int S = 0, wps = 1, chunk = 256, nvec = 0;
   int cgTX = 1, cgTY = 1, cg_ntx = 1, cg_nty = 1, cg_ntiles = 1, Rx = 0, Ry = 0;
+  int fft_rows = 1, fft_cols = 1;
   int* hlist = nullptr;      // pinned staging of active-system lists (3 x S)
   char* hstate = nullptr;    // pinned copies of the system states (2 x S)
   hipEvent_t chk_ev[2] = {nullptr, nullptr};
@@ -87,7 +88,7 @@ struct aao_plan {
   // library-owned device tables and pinned staging
   char* dtab = nullptr;
   size_t off_tw = 0, off_sf = 0, off_sb = 0, off_m1 = 0, off_m2 = 0, off_sh = 0, off_q = 0,
-         off_hostend = 0, tab_bytes = 0;
+         off_wx = 0, off_wy = 0, off_hostend = 0, tab_bytes = 0;
   char* htab = nullptr;      // pinned mirror of the alpha-dependent tables
   char* hread = nullptr;     // pinned readback area
   size_t hread_bytes = 0;
@@ -128,6 +129,8 @@ struct aao_plan {
   double2* d_m2() const { return reinterpret_cast<double2*>(dtab + off_m2); }
   double2* d_sh() const { return reinterpret_cast<double2*>(dtab + off_sh); }
   double* d_q() const { return reinterpret_cast<double*>(dtab + off_q); }
+  double2* d_wx() const { return reinterpret_cast<double2*>(dtab + off_wx); }
+  double2* d_wy() const { return reinterpret_cast<double2*>(dtab + off_wy); }
 };
 
 namespace {
@@ -416,8 +419,33 @@ aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
 
 // Solve the nsys shifted systems held in R into X.  Fills the per-system
 // iteration counts into p->hread (as SysState) after the final check.
+// Spatial-FFT direct solve of all nsys systems (exact; no iteration).
+aao_status inner_solve_fft(aao_plan* p, int adj, int nsys) {
+  aao::KrylovArgs ka = krylov_args(p, adj, nsys);
+  HIPCHK(aao::launch_krylov_init(ka, p->stream));  // iteration counts read back as 0
+  aao::FftArgs f{};
+  f.R = p->vec(1);
+  f.X = p->vec(0);
+  f.shift = p->d_sh();
+  f.Wx = p->d_wx();
+  f.Wy = p->d_wy();
+  f.taps = adj ? p->tapsT : p->taps;
+  f.nx = p->nx;
+  f.ny = p->ny;
+  f.N = p->N;
+  f.lognx = ilog2(p->nx);
+  f.logny = ilog2(p->ny);
+  f.rows = p->fft_rows;
+  f.cols = p->fft_cols;
+  f.norm = (double)p->N;
+  HIPCHK(timed(p, aao::KC_FFT_INNER, [&] { return aao::launch_fft_solve(p->f32, f, nsys, p->stream); }));
+  p->work_later[aao::KC_FFT_INNER] += (double)nsys * p->N;
+  return AAO_OK;
+}
+
 aao_status inner_solve(aao_plan* p, int adj, int nsys) {
   if (p->inner == AAO_INNER_COCG) return inner_solve_cg(p, adj, nsys);
+  if (p->inner == AAO_INNER_FFT) return inner_solve_fft(p, adj, nsys);
   aao::KrylovArgs a = krylov_args(p, adj, nsys);
   int* lst0 = p->hlist + (size_t)2 * p->S;
   for (int i = 0; i < nsys; ++i) lst0[i] = i;
@@ -479,7 +507,9 @@ aao_status read_back(aao_plan* p, int nsys, bool want_norms, SweepOut& o) {
   o.inner_mean = nsys ? sum / nsys : 0;
   if (nsys > 0) {
     const double n = (double)p->N;
-    if (p->inner == AAO_INNER_COCG) {
+    if (p->inner == AAO_INNER_FFT) {
+      // counted in inner_solve_fft
+    } else if (p->inner == AAO_INNER_COCG) {
       p->work_first[aao::KC_COCG_B] += n * nsys;  // init pass
       p->work_first[aao::KC_COCG_A] += n * nsys;
       p->work_later[aao::KC_COCG_A] += n * later;
@@ -512,6 +542,18 @@ aao_status alloc_tables(aao_plan* p) {
                         p->stream));
   HIPCHK(hipMemcpyAsync(p->dtab + p->off_q, p->Q.data(), p->Q.size() * sizeof(double), hipMemcpyHostToDevice,
                         p->stream));
+  // e^{+2 pi i k / n} for the spatial transforms of the FFT inner solve
+  std::vector<double2> wx(p->nx), wy(p->ny);
+  for (int k = 0; k < p->nx; ++k) {
+    wx[k].x = std::cos(2.0 * M_PI * k / p->nx);
+    wx[k].y = std::sin(2.0 * M_PI * k / p->nx);
+  }
+  for (int k = 0; k < p->ny; ++k) {
+    wy[k].x = std::cos(2.0 * M_PI * k / p->ny);
+    wy[k].y = std::sin(2.0 * M_PI * k / p->ny);
+  }
+  HIPCHK(hipMemcpyAsync(p->dtab + p->off_wx, wx.data(), wx.size() * sizeof(double2), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(p->dtab + p->off_wy, wy.data(), wy.size() * sizeof(double2), hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   p->cached_alpha = -1;
   return AAO_OK;
@@ -606,8 +648,13 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   if (!(cfg->dt > 0) || !std::isfinite(cfg->dt)) return fail(AAO_EINVAL, "dt must be positive");
   if (cfg->batch < 1) return fail(AAO_EINVAL, "batch must be >= 1");
   if (cfg->precision != AAO_FP64 && cfg->precision != AAO_MIXED) return fail(AAO_EINVAL, "bad precision");
-  if (cfg->inner != AAO_INNER_COCG && cfg->inner != AAO_INNER_BICGSTAB)
-    return fail(AAO_EINVAL, "inner solver not available (COCG or BiCGStab)");
+  if (cfg->inner != AAO_INNER_COCG && cfg->inner != AAO_INNER_BICGSTAB && cfg->inner != AAO_INNER_FFT)
+    return fail(AAO_EINVAL, "unknown inner solver");
+  if (cfg->inner == AAO_INNER_FFT) {
+    const int64_t cs = cfg->precision == AAO_MIXED ? 8 : 16;
+    if (!is_pow2(nx) || !is_pow2(ny) || nx * cs > 65536 || ny * cs > 65536)
+      return fail(AAO_EINVAL, "FFT inner solve needs nx, ny powers of two with n * sizeof(complex) <= 64 KiB");
+  }
   if (!(cfg->inner_tol > 0) || cfg->inner_maxit < 1) return fail(AAO_EINVAL, "bad inner tolerance / iteration cap");
 
   aao_plan* p = new aao_plan();
@@ -688,7 +735,12 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
 
   // batched inner solves: S systems, wps workgroups per system
   p->S = p->B * p->Lh * p->M;
-  p->nvec = (p->inner == AAO_INNER_COCG) ? 5 : 9;
+  p->nvec = (p->inner == AAO_INNER_COCG) ? 5 : (p->inner == AAO_INNER_FFT ? 2 : 9);
+  if (p->inner == AAO_INNER_FFT && p->ny > 1) {
+    const int cs = (int)p->csize;
+    p->fft_rows = std::max(1, std::min(p->ny, 65536 / (p->nx * cs)));
+    p->fft_cols = std::max(1, std::min(p->nx, 65536 / (p->ny * cs)));
+  }
   {
     const int target = 4096;
     int wps = (target + p->S - 1) / p->S;
@@ -756,6 +808,10 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   t = align256(t + (size_t)(p->L / 2 + 1) * sizeof(double2));
   p->off_q = t;
   t = align256(t + (size_t)p->M * p->M * sizeof(double));
+  p->off_wx = t;
+  t = align256(t + (size_t)p->nx * sizeof(double2));
+  p->off_wy = t;
+  t = align256(t + (size_t)p->ny * sizeof(double2));
   p->off_sf = t;
   t = align256(t + (size_t)p->L * sizeof(double));
   p->off_sb = t;
@@ -1035,9 +1091,11 @@ aao_status aao_get_stats(aao_plan_t p, aao_kernel_stats* out) {
   out->bytes[aao::KC_BWD] = (16.0 * dof + cs * freq) * out->launches[aao::KC_BWD];
   // Krylov kernels: complex words read + written per element processed in
   // iterations after the first / in the first iteration.
+  // FFT inner solve: read and write the vector once per pass (1 pass in 1D, 3 in 2D)
+  const double fftw = p->ny > 1 ? 6.0 : 2.0;
   struct { int c; double later, first; } kw[] = {
       {aao::KC_COCG_A, 6, 4}, {aao::KC_COCG_B, 1, 1}, {aao::KC_BICG_1, 6, 4},
-      {aao::KC_BICG_2, 4, 4}, {aao::KC_BICG_3, 7, 6}};
+      {aao::KC_BICG_2, 4, 4}, {aao::KC_BICG_3, 7, 6}, {aao::KC_FFT_INNER, fftw, fftw}};
   for (auto& k : kw) {
     out->elements[k.c] = p->work_first[k.c] + p->work_later[k.c];
     out->bytes[k.c] = cs * (k.later * p->work_later[k.c] + k.first * p->work_first[k.c]);

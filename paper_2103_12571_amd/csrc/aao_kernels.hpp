@@ -113,6 +113,19 @@ struct KrylovArgs {
   int maxit;
 };
 
+// Spatial-FFT direct solve (row a3 for periodic constant-coefficient A).
+struct FftArgs {
+  void* R;                // right-hand sides, overwritten (2D)
+  void* X;                // solutions
+  const double2* shift;   // [num_sys]
+  const double2* Wx;      // e^{+2 pi i k / nx}, k < nx
+  const double2* Wy;      // e^{+2 pi i k / ny}, k < ny
+  Taps taps;
+  int nx, ny, N, lognx, logny;
+  int rows, cols;         // rows / columns per workgroup in the 2D passes
+  double norm;            // nx * ny
+};
+
 // Partial-sum quantities of the Krylov kernels: part[q][system][chunk].
 enum PartialQ {
   QP_RHO0_RE = 0, QP_RHO0_IM, QP_RHO1_RE, QP_RHO1_IM, QP_RR0, QP_RR1, QP_A_RE, QP_A_IM,
@@ -143,6 +156,7 @@ size_t cg_lds_bytes(bool f32, const CgArgs& a);
 int cg_points_per_thread(const CgArgs& a);
 hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, int nact, hipStream_t st);
 hipError_t launch_krylov_init(const KrylovArgs& a, hipStream_t st);
+hipError_t launch_fft_solve(bool f32, const FftArgs& a, int nsys, hipStream_t st);
 hipError_t launch_count_active(const SysState* st, int n, int* out, hipStream_t s);
 hipError_t launch_copy_c128_in(void* dst, bool f32, const double* src, int64_t n, hipStream_t st);
 hipError_t launch_copy_c128_out(double* dst, const void* src, bool f32, int64_t n,

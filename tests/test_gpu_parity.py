@@ -206,3 +206,61 @@ def test_solve_errors_and_edges():
     p.set_u0(torch.zeros((1, w.N), dtype=torch.float64, device="cuda"))
     u, info = p.solve(alphas=[1e-3], tol=1e-12, stop="residual", max_iter=5)
     assert float(u.abs().max()) == 0.0
+
+
+FFT_CASES = [
+    ("heat1d_N64_L8_M3", wl.WORKLOADS["heat1d_64"].with_(L=8, inner="fft")),
+    ("heat2d_32x16_L16_M3", wl.WORKLOADS["heat2d_256"].with_(nx=32, ny=16, L=16, inner="fft")),
+    ("adv1d_N128_L32_M2", wl.WORKLOADS["adv1d_4096"].with_(nx=128, L=32, M=2, inner="fft")),
+    ("advdiff_16x32_L8_B2", wl.WORKLOADS["advdiff2d_512_adj"].with_(nx=16, ny=32, L=8, batch=2, inner="fft",
+                                                                      precision="fp64")),
+    ("heat2d_8x8_L1_M1", wl.WORKLOADS["heat2d_256"].with_(nx=8, ny=8, L=1, M=1, inner="fft")),
+]
+
+
+@pytest.mark.parametrize("alpha", [1e-6, 0.3])
+@pytest.mark.parametrize("name,w", FFT_CASES, ids=[c[0] for c in FFT_CASES])
+def test_precond_parity_fft_inner(name, w, alpha):
+    """Rows a2-a4 with the spatial-FFT direct inner solve (exact)."""
+    need_gpu()
+    say("precond fft", name, alpha)
+    p = plan_for(w)
+    r = _rand((w.batch, w.L, w.M, w.N), 5)
+    d = host(p.precond(dev(r), alpha))
+    op, Q = _oracle_op(w), _Q(w.M)
+    for b in range(w.batch):
+        do = oracle.precond_solve(op, Q, w.dt, alpha, r[b])
+        tol = 1e-12 * max(1.0, w.L / alpha) ** 0.5 * 10
+        assert rel_l2(d[b], do) < max(tol, 1e-11), (b, rel_l2(d[b], do))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("mixed", 2e-6)])
+@pytest.mark.parametrize("kind,nx,ny", [("heat2d", 32, 64), ("advdiff2d", 64, 16), ("adv1d_c4", 256, 1)])
+def test_shifted_solve_fft(kind, nx, ny, prec, tol):
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    need_gpu()
+    w = wl.Workload("t", kind, nx, ny, 8, 3, 1e-3, nu=1e-2, vel=(1.0, 0.5), inner="fft", precision=prec)
+    p = plan_for(w)
+    S = 7
+    rng = np.random.default_rng(9)
+    shifts = rng.uniform(0.0, 0.05, S) + 1j * rng.uniform(-0.05, 0.05, S)
+    b = rng.standard_normal((S, w.N)) + 1j * rng.standard_normal((S, w.N))
+    x, its = p.shifted_solve(shifts, torch.as_tensor(b, device="cuda"))
+    x = x.cpu().numpy()
+    A = _oracle_op(w).matrix()
+    for s in range(S):
+        xo = spla.spsolve((sp.identity(w.N) - shifts[s] * A).tocsc(), b[s])
+        assert rel_l2(x[s], xo) < tol
+
+
+@pytest.mark.parametrize("name,w,tol", [
+    ("heat2d_64_L16_fft_alg2", wl.WORKLOADS["heat2d_256"].with_(nx=64, ny=64, L=16, inner="fft"), 1e-10),
+    ("adv1d_512_L32_fft_alg2", wl.WORKLOADS["adv1d_4096"].with_(nx=512, L=32, inner="fft"), 1e-10),
+    ("heat2d_64_L8_fft_mixed", wl.WORKLOADS["heat2d_1024_mixed"].with_(nx=64, ny=64, L=8, inner="fft"), 1e-8),
+])
+def test_solve_fft_inner_parity(name, w, tol):
+    need_gpu()
+    say("solve", name)
+    info, _ = _solve_and_compare(w, tol, tol=w.tol, max_iter=40)
+    assert info["converged"]
