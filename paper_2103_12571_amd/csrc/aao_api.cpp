@@ -49,8 +49,27 @@ int ilog2(int64_t v) {
 #ifndef AAO_CG_TY2D
 #define AAO_CG_TY2D 16
 #endif
+#ifndef AAO_CG_BLOCK
+#define AAO_CG_BLOCK 256
+#endif
+#ifndef AAO_CG_MARCH
+#define AAO_CG_MARCH 0
+#endif
+#ifndef AAO_CG_SY
+#define AAO_CG_SY 16
+#endif
 #ifndef AAO_XCD_BANDS
 #define AAO_XCD_BANDS 1
+#endif
+// LDS budgets (KiB) of the transform over l and of the spatial FFT passes.
+#ifndef AAO_XFORM_LDS_KB
+#define AAO_XFORM_LDS_KB 24
+#endif
+#ifndef AAO_FFT_ROW_LDS_KB
+#define AAO_FFT_ROW_LDS_KB 32
+#endif
+#ifndef AAO_FFT_COL_LDS_KB
+#define AAO_FFT_COL_LDS_KB 32
 #endif
 
 constexpr int kWorkSlots = 32;     // [class] for k > 0, [16 + class] for k == 0
@@ -80,6 +99,7 @@ struct aao_plan {
   int S = 0, wps = 1, chunk = 256, nvec = 0;
   int cgTX = 1, cgTY = 1, cg_ntx = 1, cg_nty = 1, cg_ntiles = 1, Rx = 0, Ry = 0;
   int fft_rows = 1, fft_cols = 1;
+  int cg_march = 0;
   int* hlist = nullptr;      // pinned staging of active-system lists (3 x S)
   char* hstate = nullptr;    // pinned copies of the system states (2 x S)
   hipEvent_t chk_ev[2] = {nullptr, nullptr};
@@ -153,9 +173,9 @@ hipError_t timed(aao_plan* p, int cls, F&& launch) {
   if (!p->timing) return launch();
   hipEvent_t a = get_event(p), b = get_event(p);
   if (!a || !b) return launch();
-  hipEventRecord(a, p->stream);
+  (void)hipEventRecord(a, p->stream);
   hipError_t e = launch();
-  hipEventRecord(b, p->stream);
+  (void)hipEventRecord(b, p->stream);
   p->pending.push_back({cls, a, b});
   return e;
 }
@@ -320,6 +340,10 @@ aao::CgArgs cg_args(aao_plan* p, int adj, int nsys) {
   a.m_qw = magic(a.TX + 2 * a.Rx);
   a.xcd_band = (AAO_XCD_BANDS && a.ntiles % 8 == 0 && a.ntiles >= 16) ? a.ntiles / 8 : 0;
   a.fused = a.ntiles <= 256 ? 1 : 0;
+  a.march = p->cg_march;
+  // larger tiles run with 512 threads (half the points per thread, fewer
+  // registers, more wavefronts in flight per CU)
+  a.block = (AAO_CG_BLOCK == 512 && a.TX * a.TY >= 1024) ? 512 : 256;
   a.tol2 = p->inner_tol * p->inner_tol;
   a.maxit = p->inner_maxit;
   return a;
@@ -728,7 +752,7 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
 
   // tiling of the DFT over l: TN spatial points per workgroup, LDS <= 48 KB
   int TN = 64;
-  while (TN > 2 && (size_t)p->L * p->M * TN * 8 > 48 * 1024) TN >>= 1;
+  while (TN > 2 && (size_t)p->L * p->M * TN * 8 > AAO_XFORM_LDS_KB * 1024) TN >>= 1;
   p->TN = TN;
   p->logTN = ilog2(TN);
   p->ntiles = (p->N + TN - 1) / TN;
@@ -738,8 +762,8 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   p->nvec = (p->inner == AAO_INNER_COCG) ? 5 : (p->inner == AAO_INNER_FFT ? 2 : 9);
   if (p->inner == AAO_INNER_FFT && p->ny > 1) {
     const int cs = (int)p->csize;
-    p->fft_rows = std::max(1, std::min(p->ny, 65536 / (p->nx * cs)));
-    p->fft_cols = std::max(1, std::min(p->nx, 65536 / (p->ny * cs)));
+    p->fft_rows = std::max(1, std::min(p->ny, AAO_FFT_ROW_LDS_KB * 1024 / (p->nx * cs)));
+    p->fft_cols = std::max(1, std::min(p->nx, AAO_FFT_COL_LDS_KB * 1024 / (p->ny * cs)));
   }
   {
     const int target = 4096;
@@ -758,11 +782,16 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   if (p->ny == 1) {
     p->cgTX = std::min(p->nx, 1024);
     p->cgTY = 1;
+  } else if (AAO_CG_MARCH && p->Ry >= 1 && p->Ry <= 2 && p->Rx <= 4) {
+    // row-marching strips: up to 256 columns x AAO_CG_SY rows
+    p->cg_march = 1;
+    p->cgTX = std::min(p->nx, aao::kBlock);
+    p->cgTY = std::min(p->ny, AAO_CG_SY);
   } else {
     p->cgTX = std::min(p->nx, AAO_CG_TX2D);
     p->cgTY = std::min(p->ny, AAO_CG_TY2D);
   }
-  {  // the COCG tile's two-hop region must fit 8 points per thread (LDS <= 32 KB)
+  if (!p->cg_march) {  // the COCG tile's two-hop region must fit 8 points per thread (LDS <= 32 KB)
     auto pts = [&](int tx, int ty) { return (tx + 4 * p->Rx) * (ty + 4 * p->Ry); };
     while (pts(p->cgTX, p->cgTY) > 8 * aao::kBlock && p->cgTY > 1) p->cgTY = (p->cgTY + 1) / 2;
     while (pts(p->cgTX, p->cgTY) > 8 * aao::kBlock && p->cgTX > 8) p->cgTX = (p->cgTX + 1) / 2;
@@ -1136,19 +1165,19 @@ aao_status aao_collocation(aao_plan_t p, double* nodes, double* Q) {
 
 void aao_destroy(aao_plan_t p) {
   if (!p) return;
-  if (p->stream) hipStreamSynchronize(p->stream);
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
   for (auto& t : p->pending) {
-    hipEventDestroy(t.a);
-    hipEventDestroy(t.b);
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
   }
-  for (auto e : p->pool) hipEventDestroy(e);
-  if (p->dtab) hipFree(p->dtab);
-  if (p->htab) hipHostFree(p->htab);
-  if (p->hread) hipHostFree(p->hread);
-  if (p->hlist) hipHostFree(p->hlist);
-  if (p->hstate) hipHostFree(p->hstate);
+  for (auto e : p->pool) (void)hipEventDestroy(e);
+  if (p->dtab) (void)hipFree(p->dtab);
+  if (p->htab) (void)hipHostFree(p->htab);
+  if (p->hread) (void)hipHostFree(p->hread);
+  if (p->hlist) (void)hipHostFree(p->hlist);
+  if (p->hstate) (void)hipHostFree(p->hstate);
   for (auto e : p->chk_ev)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   delete p;
 }
 

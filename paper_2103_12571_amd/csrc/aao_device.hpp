@@ -60,6 +60,32 @@ __device__ __forceinline__ int bitrev(int v, int logL) {
 // Sum of K values over the 256-thread block; every thread receives the result.
 // The butterfly over lanes adds each pair in both orders, which is exact-equal,
 // so all lanes (and every workgroup doing the same reduction) agree bitwise.
+// Same for a block of NW wavefronts (sh holds NW * K doubles).
+template <int K, int NW>
+__device__ __forceinline__ void block_sum_w(double (&v)[K], double* sh) {
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    double x = v[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    v[i] = x;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) sh[wid * K + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += sh[w * K + i];
+    v[i] = t;
+  }
+}
+
 template <int K>
 __device__ __forceinline__ void block_sum(double (&v)[K], double* sh) {
 #pragma unroll

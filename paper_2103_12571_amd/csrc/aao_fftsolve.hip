@@ -102,7 +102,9 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(FftArgs a) {
   V* c = reinterpret_cast<V*>(smem);
   const int s = blockIdx.y;
   const int nx = a.nx, rows = a.rows;
-  const int y0 = blockIdx.x * rows;
+  int grp = blockIdx.x;
+  if ((gridDim.x & 7) == 0) grp = (grp & 7) * (gridDim.x >> 3) + (grp >> 3);
+  const int y0 = grp * rows;
   const V* in = reinterpret_cast<const V*>(a.R) + (size_t)s * a.N + (size_t)y0 * nx;
   V* out = reinterpret_cast<V*>(MODE == 0 ? a.R : a.X) + (size_t)s * a.N + (size_t)y0 * nx;
   const int tot = rows * nx;
@@ -140,7 +142,9 @@ __global__ __launch_bounds__(kBlock) void k_fft_cols(FftArgs a) {
   V* c = reinterpret_cast<V*>(smem);
   const int s = blockIdx.y;
   const int nx = a.nx, ny = a.ny, cols = a.cols;
-  const int x0 = blockIdx.x * cols;
+  int grp = blockIdx.x;  // XCD-banded: neighbouring column groups share cache lines
+  if ((gridDim.x & 7) == 0) grp = (grp & 7) * (gridDim.x >> 3) + (grp >> 3);
+  const int x0 = grp * cols;
   V* base = reinterpret_cast<V*>(a.R) + (size_t)s * a.N + x0;
   const int tot = ny * cols;
   for (int i = threadIdx.x; i < tot; i += kBlock) {

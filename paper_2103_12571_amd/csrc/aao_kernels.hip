@@ -27,7 +27,11 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
   extern __shared__ double lds[];
   const int TN = a.TN, P = TN >> 1, L = a.L, N = a.g.N;
   const int b = blockIdx.y;
-  const int n0 = blockIdx.x * TN;
+  // XCD-banded tile order (workgroup slot b runs on XCD b % 8): a contiguous
+  // range of tiles per XCD keeps the stencil's neighbouring rows in its L2.
+  int tile = blockIdx.x;
+  if ((gridDim.x & 7) == 0) tile = (tile & 7) * (gridDim.x >> 3) + (tile >> 3);
+  const int n0 = tile * TN;
   double2* tw = reinterpret_cast<double2*>(lds + (size_t)L * M * TN);
   __shared__ double sh[4];
   for (int i = threadIdx.x; i < (L >> 1); i += kBlock) tw[i] = a.tw[i];
@@ -135,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
   if (MODE == 0) {
     double v[1] = {res2};
     block_sum<1>(v, sh);
-    if (threadIdx.x == 0) a.part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = v[0];
+    if (threadIdx.x == 0) a.part[(size_t)blockIdx.y * gridDim.x + tile] = v[0];
   }
 }
 
@@ -202,7 +206,11 @@ __global__ __launch_bounds__(kBlock) void k_bwd(BwdArgs a) {
   extern __shared__ double lds[];
   const int TN = a.TN, P = TN >> 1, L = a.L, N = a.g.N;
   const int b = blockIdx.y;
-  const int n0 = blockIdx.x * TN;
+  // XCD-banded tile order (workgroup slot b runs on XCD b % 8): a contiguous
+  // range of tiles per XCD keeps the stencil's neighbouring rows in its L2.
+  int tile = blockIdx.x;
+  if ((gridDim.x & 7) == 0) tile = (tile & 7) * (gridDim.x >> 3) + (tile >> 3);
+  const int n0 = tile * TN;
   double2* tw = reinterpret_cast<double2*>(lds + (size_t)L * M * TN);
   __shared__ double sh[4];
   for (int i = threadIdx.x; i < (L >> 1); i += kBlock) tw[i] = a.tw[i];
@@ -264,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd(BwdArgs a) {
     if (l == lmon) dmax = fmax(dmax, fabs(d));
   }
   dmax = block_max(dmax, sh);
-  if (threadIdx.x == 0) a.part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = dmax;
+  if (threadIdx.x == 0) a.part[(size_t)blockIdx.y * gridDim.x + tile] = dmax;
 }
 
 // ----------------------------------------------------------------------------
