@@ -49,15 +49,6 @@ int ilog2(int64_t v) {
 #ifndef AAO_CG_TY2D
 #define AAO_CG_TY2D 16
 #endif
-#ifndef AAO_CG_BLOCK
-#define AAO_CG_BLOCK 256
-#endif
-#ifndef AAO_CG_MARCH
-#define AAO_CG_MARCH 0
-#endif
-#ifndef AAO_CG_SY
-#define AAO_CG_SY 16
-#endif
 #ifndef AAO_XCD_BANDS
 #define AAO_XCD_BANDS 1
 #endif
@@ -99,7 +90,6 @@ struct aao_plan {
   int S = 0, wps = 1, chunk = 256, nvec = 0;
   int cgTX = 1, cgTY = 1, cg_ntx = 1, cg_nty = 1, cg_ntiles = 1, Rx = 0, Ry = 0;
   int fft_rows = 1, fft_cols = 1;
-  int cg_march = 0;
   int* hlist = nullptr;      // pinned staging of active-system lists (3 x S)
   char* hstate = nullptr;    // pinned copies of the system states (2 x S)
   hipEvent_t chk_ev[2] = {nullptr, nullptr};
@@ -337,13 +327,9 @@ aao::CgArgs cg_args(aao_plan* p, int adj, int nsys) {
   a.m_ntx = magic(a.ntx);
   a.m_tx = magic(a.TX);
   a.m_pw = magic(a.TX + 4 * a.Rx);
-  a.m_qw = magic(a.TX + 2 * a.Rx);
+  a.m_hw = a.Rx > 0 ? magic(4 * a.Rx) : 0;
   a.xcd_band = (AAO_XCD_BANDS && a.ntiles % 8 == 0 && a.ntiles >= 16) ? a.ntiles / 8 : 0;
   a.fused = a.ntiles <= 256 ? 1 : 0;
-  a.march = p->cg_march;
-  // larger tiles run with 512 threads (half the points per thread, fewer
-  // registers, more wavefronts in flight per CU)
-  a.block = (AAO_CG_BLOCK == 512 && a.TX * a.TY >= 1024) ? 512 : 256;
   a.tol2 = p->inner_tol * p->inner_tol;
   a.maxit = p->inner_maxit;
   return a;
@@ -782,20 +768,17 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   if (p->ny == 1) {
     p->cgTX = std::min(p->nx, 1024);
     p->cgTY = 1;
-  } else if (AAO_CG_MARCH && p->Ry >= 1 && p->Ry <= 2 && p->Rx <= 4) {
-    // row-marching strips: up to 256 columns x AAO_CG_SY rows
-    p->cg_march = 1;
-    p->cgTX = std::min(p->nx, aao::kBlock);
-    p->cgTY = std::min(p->ny, AAO_CG_SY);
   } else {
     p->cgTX = std::min(p->nx, AAO_CG_TX2D);
     p->cgTY = std::min(p->ny, AAO_CG_TY2D);
   }
-  if (!p->cg_march) {  // the COCG tile's two-hop region must fit 8 points per thread (LDS <= 32 KB)
+  {  // at most 4 tile points per thread, and the two-hop region within 8 per thread (LDS <= 32 KB)
     auto pts = [&](int tx, int ty) { return (tx + 4 * p->Rx) * (ty + 4 * p->Ry); };
-    while (pts(p->cgTX, p->cgTY) > 8 * aao::kBlock && p->cgTY > 1) p->cgTY = (p->cgTY + 1) / 2;
-    while (pts(p->cgTX, p->cgTY) > 8 * aao::kBlock && p->cgTX > 8) p->cgTX = (p->cgTX + 1) / 2;
-    if (pts(p->cgTX, p->cgTY) > 8 * aao::kBlock) {
+    while ((pts(p->cgTX, p->cgTY) > 8 * aao::kBlock || p->cgTX * p->cgTY > 4 * aao::kBlock) && p->cgTY > 1)
+      p->cgTY = (p->cgTY + 1) / 2;
+    while ((pts(p->cgTX, p->cgTY) > 8 * aao::kBlock || p->cgTX * p->cgTY > 4 * aao::kBlock) && p->cgTX > 8)
+      p->cgTX = (p->cgTX + 1) / 2;
+    if (pts(p->cgTX, p->cgTY) > 8 * aao::kBlock || p->cgTX * p->cgTY > 4 * aao::kBlock) {
       delete p;
       return fail(AAO_EINVAL, "stencil reach too large for the COCG tile");
     }
@@ -803,6 +786,10 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   p->cg_ntx = (p->nx + p->cgTX - 1) / p->cgTX;
   p->cg_nty = (p->ny + p->cgTY - 1) / p->cgTY;
   p->cg_ntiles = p->cg_ntx * p->cg_nty;
+  if (p->inner == AAO_INNER_COCG && p->cg_ntiles >= (1 << 16)) {  // tile indices use 16-bit exact division
+    delete p;
+    return fail(AAO_EINVAL, "grid too large for the COCG tiling (at most 65535 tiles per system)");
+  }
   p->fb_slots = std::max(p->ntiles * p->B, 1024);
   p->grad_blocks = std::max(1, std::min(256, (p->N + aao::kBlock - 1) / aao::kBlock));
 

@@ -14,8 +14,10 @@
 // once more at the tile points for delta_{k+1}.  Global traffic per element
 // and pass: read r_k, p_{k-1}, x_k and write r_{k+1}, p_k, x_{k+1}.
 //
-// Scalars live in SysState; a small per-system kernel reduces the tile
-// partial sums in a fixed order (bitwise reproducible) between passes.
+// Scalars live in SysState.  When a system has at most 256 tiles every pass
+// reduces the previous pass's tile sums itself (fused); otherwise a small
+// per-system kernel does it between passes.  Sums run in a fixed order, so
+// results are bitwise reproducible.
 #include "aao_device.hpp"
 #include "aao_kernels.hpp"
 
@@ -25,7 +27,8 @@ namespace {
 
 using namespace dev;
 
-constexpr int kQ = 5;  // partial quantities: gamma (re, im), delta (re, im), ||r||^2
+constexpr int kQ = 5;       // partial quantities: gamma (re, im), delta (re, im), ||r||^2
+constexpr int kInside = 4;  // tile points per thread: TX * TY <= kInside * kBlock
 
 __device__ __forceinline__ int pmod(int v, int n) {
   if ((n & (n - 1)) == 0) return v & (n - 1);
@@ -41,15 +44,6 @@ __device__ __forceinline__ int fdiv(int i, unsigned long long m) {
 
 __device__ __forceinline__ double* cg_part(const CgArgs& a, int q, int s) {
   return a.part + ((size_t)q * a.num_sys + s) * a.ntiles;
-}
-
-template <int K>
-__device__ __forceinline__ void write_tile_parts(const CgArgs& a, int s, double (&v)[K], double* sh) {
-  block_sum<K>(v, sh);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < K; ++q) cg_part(a, q, s)[blockIdx.x] = v[q];
-  }
 }
 
 // gamma_0 = b^T b, delta_0 = b^T A_s b, ||b||^2 over one tile (neighbours from
@@ -83,17 +77,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
     v[3] += (double)b.x * w.y + (double)b.y * w.x;
     v[4] += (double)b.x * b.x + (double)b.y * b.y;
   }
-  block_sum<kQ>(v, sh);
+  block_sum_wave0<kQ>(v, sh);
   if (threadIdx.x == 0) {
     double* pb = a.part + (a.fused ? (size_t)kQ * a.num_sys * a.ntiles : 0);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) pb[((size_t)q * a.num_sys + s) * a.ntiles + tile] = v[q];
   }
 }
-
-// Points per thread of the two halo regions; the host keeps
-// (TX + 4Rx)(TY + 4Ry) <= kMaxPerThread * kBlock.
-constexpr int kMaxPerThread = 8;
 
 // Taps applied to an LDS tile with row pitch W: NT > 0 unrolls a fixed count.
 template <int NT, typename T, typename V>
@@ -109,89 +99,67 @@ __device__ __forceinline__ V tile_stencil(const CgArgs& a, const V* buf, int c, 
   return acc;
 }
 
-// Advance the COCG scalars of one system from the reduced partial sums of
-// r_{k} (gamma_k, delta_k, ||r_k||^2).  Returns 0 to go on, 1 converged, 2
-// iteration cap, 3 breakdown.  k == 0: the sums are those of b = r_0.
-__device__ __forceinline__ int cg_advance(int k, double2 gam, double2 del, double rr, double bb, double tol2,
-                                          int maxit, double2 gam_prev, double2 al_prev, double2& al, double2& be) {
+// Outcome of advancing the scalars of one system: dec = 0 go on, 1 converged,
+// 2 iteration cap, 3 breakdown; al, be = alpha_k, beta_k when dec = 0.
+struct CgStep {
+  int dec;
+  double2 al, be;
+};
+
+// Advance from the reduced sums of r_k (gamma_k, delta_k, ||r_k||^2).  k == 0:
+// the sums are those of b = r_0.
+__device__ __forceinline__ CgStep cg_advance(int k, double2 gam, double2 del, double rr, double bb, double tol2,
+                                             int maxit, double2 gam_prev, double2 al_prev) {
+  CgStep o{0, mk(0, 0), mk(0, 0)};
   if (k == 0) {
     const double d2 = del.x * del.x + del.y * del.y;
-    al = (rr > 0.0 && d2 > 0.0) ? cdiv(gam, del) : mk(0, 0);  // b = 0: x stays 0
-    be = mk(0, 0);
-    return 0;
+    if (rr > 0.0 && d2 > 0.0) o.al = cdiv(gam, del);  // b = 0: x stays 0
+    return o;
   }
-  if (rr <= tol2 * bb) return 1;
-  if (k >= maxit) return 2;
-  const bool ok0 = (gam_prev.x != 0.0 || gam_prev.y != 0.0) && (al_prev.x != 0.0 || al_prev.y != 0.0);
-  be = ok0 ? cdiv(gam, gam_prev) : mk(0, 0);
-  const double2 den = ok0 ? csub(del, cdiv(cmul(be, gam), al_prev)) : mk(0, 0);
-  if (!ok0 || (den.x == 0.0 && den.y == 0.0) || !isfinite(den.x) || !isfinite(den.y)) return 3;
-  al = cdiv(gam, den);
-  return 0;
+  if (rr <= tol2 * bb) {
+    o.dec = 1;
+    return o;
+  }
+  if (k >= maxit) {
+    o.dec = 2;
+    return o;
+  }
+  if ((gam_prev.x == 0.0 && gam_prev.y == 0.0) || (al_prev.x == 0.0 && al_prev.y == 0.0)) {
+    o.dec = 3;
+    return o;
+  }
+  o.be = cdiv(gam, gam_prev);
+  const double2 den = csub(del, cdiv(cmul(o.be, gam), al_prev));
+  if ((den.x == 0.0 && den.y == 0.0) || !isfinite(den.x) || !isfinite(den.y)) {
+    o.dec = 3;
+    return o;
+  }
+  o.al = cdiv(gam, den);
+  return o;
 }
 
-// Scalars of pass k for system s (identical in every workgroup of the
-// system).  Fused mode: reduce pass k-1's tile sums, advance alpha/beta and
-// the convergence decision (tile 0 records it); else read what the scalar
-// kernel wrote.  Returns false if the system is done.
-template <int BS>
-__device__ __forceinline__ bool cg_prologue(const CgArgs& a, int k, int s, int tile, double* sh, int* act,
-                                            double2* sc) {
-  if (a.fused) {
-    // every workgroup of the system reduces the previous pass's tile sums in
-    // the same order and takes the same decision; tile 0 records it
-    double v[kQ] = {0, 0, 0, 0, 0};
-    const double* pp0 = a.part + (size_t)((k + 1) & 1) * kQ * a.num_sys * a.ntiles;
-    for (int c = threadIdx.x; c < a.ntiles; c += BS) {
-#pragma unroll
-      for (int q = 0; q < kQ; ++q) v[q] += pp0[((size_t)q * a.num_sys + s) * a.ntiles + c];
-    }
-    block_sum_w<kQ, BS / 64>(v, sh);
-    if (threadIdx.x == 0) {
-      SysState* st = a.st + s;
-      const double bb = (k == 0) ? v[4] : st->bb;
-      double2 al = mk(0, 0), be = mk(0, 0);
-      const int dec = cg_advance(k, mk(v[0], v[1]), mk(v[2], v[3]), v[4], bb, a.tol2, a.maxit,
-                                 st->gamma2[(k + 1) & 1], st->alpha2[(k + 1) & 1], al, be);
-      sc[0] = al;
-      sc[1] = be;
-      *act = dec == 0;
-      if (tile == 0) {
-        if (k == 0) st->bb = bb;
-        st->rr = v[4];
-        if (dec == 0) {
-          st->gamma2[k & 1] = mk(v[0], v[1]);
-          st->alpha2[k & 1] = al;
-        } else {
-          st->active = 0;
-          st->iters = k;
-          st->flag = dec - 1;
-        }
-      }
-    }
-    __syncthreads();
-    if (!*act) return false;
-  } else {
-    if (threadIdx.x == 0) {
-      sc[0] = a.st[s].alpha;
-      sc[1] = a.st[s].beta;
-    }
-    __syncthreads();
-  }
-  return true;
+// A workgroup-uniform double (read from LDS) moved to scalar registers.
+__device__ __forceinline__ double2 uniform(double2 v) {
+  auto u = [](double x) {
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(x)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(x)));
+  };
+  return mk(u(v.x), u(v.y));
 }
 
-#ifndef AAO_CG_MIN_WAVES
-#define AAO_CG_MIN_WAVES 1
-#endif
-
-template <typename T, int NP, int NT, int BS>
-__global__ __launch_bounds__(BS, AAO_CG_MIN_WAVES) void k_cg_pass(CgArgs a, int k) {
+// One COCG iteration for one tile of one system.  Thread t owns tile points
+// t + 256 j (j < kInside) and points t + 256 j of the two-hop ring around the
+// tile (j < NH); it keeps r_k and then r_{k+1} of its points in registers across
+// the stages.  NT > 0: the stencil has NT taps (unrolled).
+template <typename T, int NH, int NT>
+__global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   using V = typename cvec<T>::type;
+  constexpr int NI = kInside;
   extern __shared__ char smem[];
-  __shared__ double sh[(BS / 64) * kQ];
+  __shared__ double sh[4 * kQ];
   __shared__ int act;
   __shared__ double2 sc[2];
+  const int t = threadIdx.x;
   const int s = a.sys_list[blockIdx.y];
   // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs
   // (each with its own L2), so slot b goes to XCD b % 8; give each XCD a
@@ -199,282 +167,218 @@ __global__ __launch_bounds__(BS, AAO_CG_MIN_WAVES) void k_cg_pass(CgArgs a, int 
   int tile = blockIdx.x;
   if (a.xcd_band > 0) tile = (tile & 7) * a.xcd_band + (tile >> 3);
   const int Rx = a.Rx, Ry = a.Ry, TX = a.TX, TY = a.TY;
-  const int PW = TX + 4 * Rx, PH = TY + 4 * Ry;
-  const int QW = TX + 2 * Rx, QH = TY + 2 * Ry;
-  V* Pt = reinterpret_cast<V*>(smem);  // p_k on the two-hop halo, then r_{k+1} on the one-hop halo
+  const int PW = TX + 4 * Rx, PH = TY + 4 * Ry, QW = TX + 2 * Rx;
+  const int nx = a.g.nx, ny = a.g.ny;
+  const int ty = fdiv(tile, a.m_ntx), tx = tile - ty * a.ntx;
+  const int x0 = tx * TX, y0 = ty * TY;
   const size_t off = (size_t)s * a.g.N;
   const V* Rin = reinterpret_cast<const V*>(a.R[k & 1]) + off;
   V* Rout = reinterpret_cast<V*>(a.R[(k + 1) & 1]) + off;
   const V* Pold = reinterpret_cast<const V*>(a.P[(k + 1) & 1]) + off;
   V* Pnew = reinterpret_cast<V*>(a.P[k & 1]) + off;
   V* X = reinterpret_cast<V*>(a.X) + off;
-  const int nx = a.g.nx, ny = a.g.ny;
-  const int ty = fdiv(tile, a.m_ntx);
-  const int tx = tile - ty * a.ntx;
-  const int x0 = tx * TX, y0 = ty * TY;
+  V* Pt = reinterpret_cast<V*>(smem);  // p_k on the two-hop region, then r_{k+1} on the one-hop region
 
-  // converged systems leave before touching memory (the host drops them from
-  // the launch list at its next, lagged, check)
-  if (threadIdx.x == 0) act = a.st[s].active;
+  // 1. What decides this pass's scalars is requested first (the previous
+  //    pass's tile sums in fused mode, the system state), so that it arrives
+  //    ahead of the vectors.
+  double pv[kQ] = {0, 0, 0, 0, 0};
+  if (a.fused && t < a.ntiles) {
+    const double* pp0 = a.part + (size_t)((k + 1) & 1) * kQ * a.num_sys * a.ntiles + (size_t)s * a.ntiles + t;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) pv[q] = pp0[(size_t)q * a.num_sys * a.ntiles];
+  }
+  // the state is read with workgroup-uniform addresses (scalar loads)
+  const SysState* st0 = a.st + s;
+  const int act0 = st0->active;
+  const double bb0 = a.fused ? st0->bb : 0.0;
+  const double2 s0 = a.fused ? st0->gamma2[(k + 1) & 1] : st0->alpha;
+  const double2 s1 = a.fused ? st0->alpha2[(k + 1) & 1] : st0->beta;
+
+  // 2. r_k and p_{k-1} at the tile points and on the two-hop ring.  Tile
+  //    points of a ragged last tile that fall outside the grid hold their
+  //    periodic images (used as neighbours, never stored).
+  const int nin = TX * TY, nring = PW * PH - nin;
+  // tile slot j of thread tt: global index g, LDS index l in the two-hop
+  // layout (-1: no point), index q in the one-hop layout, own: stored here
+  auto tile_slot = [&](int tt, int j, int& g, int& l, int& q, bool& own) {
+    const int i = tt + j * kBlock;
+    const bool valid = i < nin;
+    const int ii = valid ? i : 0;
+    const int iy = fdiv(ii, a.m_tx), ix = ii - iy * TX;
+    int ux = x0 + ix, uy = y0 + iy;
+    own = valid && ux < nx && uy < ny;
+    ux -= (ux >= nx) ? nx : 0;  // TX <= nx, TY <= ny
+    uy -= (uy >= ny) ? ny : 0;
+    g = uy * nx + ux;
+    l = valid ? (iy + 2 * Ry) * PW + ix + 2 * Rx : -1;
+    q = (iy + Ry) * QW + ix + Rx;
+  };
+  // ring slot j: 2Ry full rows above, 2Ry full rows below, then the rows of
+  // the tile with 2Rx points on each side; q = -1 outside the one-hop ring
+  auto ring_slot = [&](int tt, int j, int& g, int& l, int& q) {
+    const int h = tt + j * kBlock;
+    const bool valid = h < nring;
+    const int hh = valid ? h : 0;
+    const int band = 2 * Ry * PW;
+    int px, py;
+    if (hh < band) {
+      py = fdiv(hh, a.m_pw);
+      px = hh - py * PW;
+    } else if (hh < 2 * band) {
+      const int h2 = hh - band, r2 = fdiv(h2, a.m_pw);
+      py = PH - 2 * Ry + r2;
+      px = h2 - r2 * PW;
+    } else {
+      const int h3 = hh - 2 * band, r3 = fdiv(h3, a.m_hw), c3 = h3 - r3 * 4 * Rx;
+      py = 2 * Ry + r3;
+      px = (c3 < 2 * Rx) ? c3 : TX + c3;
+    }
+    g = pmod(y0 - 2 * Ry + py, ny) * nx + pmod(x0 - 2 * Rx + px, nx);
+    l = valid ? py * PW + px : -1;
+    q = (valid && px >= Rx && px < PW - Rx && py >= Ry && py < PH - Ry) ? (py - Ry) * QW + (px - Rx) : -1;
+  };
+  V ri[NI], pi[NI], rh[NH], ph[NH];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    int g, l, q;
+    bool own;
+    tile_slot(t, j, g, l, q, own);
+    ri[j] = Rin[g];
+    pi[j] = (k > 0) ? Pold[g] : vzero<V>();
+  }
+#pragma unroll
+  for (int j = 0; j < NH; ++j) {
+    int g, l, q;
+    ring_slot(t, j, g, l, q);
+    rh[j] = Rin[g];
+    ph[j] = (k > 0) ? Pold[g] : vzero<V>();
+  }
+
+  // 3. Scalars of pass k.  Fused: every workgroup of the system reduces the
+  //    tile sums of pass k-1 in the same order and takes the same decision;
+  //    tile 0 records it.  Converged systems leave here.
+  if (a.fused) {
+    block_sum_wave0<kQ>(pv, sh);
+    if (t == 0) {
+      int go = 0;
+      CgStep c{0, mk(0, 0), mk(0, 0)};
+      if (act0) {
+        const double bb = (k == 0) ? pv[4] : bb0;
+        c = cg_advance(k, mk(pv[0], pv[1]), mk(pv[2], pv[3]), pv[4], bb, a.tol2, a.maxit, s0, s1);
+        go = c.dec == 0;
+        if (tile == 0) {
+          SysState* st = a.st + s;
+          if (k == 0) st->bb = bb;
+          st->rr = pv[4];
+          if (go) {
+            st->gamma2[k & 1] = mk(pv[0], pv[1]);
+            st->alpha2[k & 1] = c.al;
+          } else {
+            st->active = 0;
+            st->iters = k;
+            st->flag = c.dec - 1;
+          }
+        }
+      }
+      act = go;
+      sc[0] = c.al;
+      sc[1] = c.be;
+    }
+  } else if (t == 0) {
+    act = act0;
+    sc[0] = s0;
+    sc[1] = s1;
+  }
   __syncthreads();
   if (!act) return;
-  // Each thread owns the same points of the two-hop region in every stage:
-  // it loads r_k and p_{k-1} there (and x_k at its tile points), and later
-  // computes r_{k+1} at those of its points that lie in the one-hop region,
-  // so r_k is read from memory once.  All loads are issued up front; the
-  // state read below does not gate them.
-  V rp[NP], pp[NP];
-  int gq[NP];
-#pragma unroll
-  for (int j = 0; j < NP; ++j) {
-    const int i = threadIdx.x + j * BS;
-    gq[j] = -1;
-    if (i < PW * PH) {
-      const int py = fdiv(i, a.m_pw), px = i - py * PW;
-      const int ux = x0 - 2 * Rx + px, uy = y0 - 2 * Ry + py;
-      const int g = pmod(uy, ny) * nx + pmod(ux, nx);
-      rp[j] = Rin[g];
-      if (k > 0) pp[j] = Pold[g];
-      const bool inside = px >= 2 * Rx && px < 2 * Rx + TX && py >= 2 * Ry && py < 2 * Ry + TY && ux < nx && uy < ny;
-      if (inside) gq[j] = g;
-    }
-  }
-  if (!cg_prologue<BS>(a, k, s, tile, sh, &act, sc)) return;
-  const V al = from_d2<V>(sc[0]);
-  const V be = from_d2<V>(sc[1]);
+  const V al = from_d2<V>(uniform(sc[0]));
+  const V be = from_d2<V>(uniform(sc[1]));
   const V sft = from_d2<V>(a.shift[s]);
+  // Slot indices are recomputed here rather than kept live across the
+  // scalar step (register pressure); the empty asm hides that they equal
+  // the ones computed for the loads.
+  int t2 = t;
+  asm volatile("" : "+v"(t2));
+  int li[NI], qi[NI], gi[NI], lh[NH], qh[NH];
 #pragma unroll
-  for (int j = 0; j < NP; ++j) {
-    const int i = threadIdx.x + j * BS;
-    if (i < PW * PH) Pt[i] = (k > 0) ? vadd(rp[j], vmul(be, pp[j])) : rp[j];
+  for (int j = 0; j < NI; ++j) {
+    int g;
+    bool own;
+    tile_slot(t2, j, g, li[j], qi[j], own);
+    gi[j] = own ? g : -1;
   }
-  // x_k at this thread's tile points, issued before the barrier
-  V xq[NP];
 #pragma unroll
-  for (int j = 0; j < NP; ++j)
-    if (k > 0 && gq[j] >= 0) xq[j] = X[gq[j]];
+  for (int j = 0; j < NH; ++j) {
+    int g;
+    ring_slot(t2, j, g, lh[j], qh[j]);
+  }
+
+  // 4. p_k = r_k + beta_k p_{k-1} on the two-hop region
+#pragma unroll
+  for (int j = 0; j < NI; ++j)
+    if (li[j] >= 0) Pt[li[j]] = (k > 0) ? vadd(ri[j], vmul(be, pi[j])) : ri[j];
+#pragma unroll
+  for (int j = 0; j < NH; ++j)
+    if (lh[j] >= 0) Pt[lh[j]] = (k > 0) ? vadd(rh[j], vmul(be, ph[j])) : rh[j];
+  V xi[NI];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) xi[j] = (k > 0 && gi[j] >= 0) ? X[gi[j]] : vzero<V>();
   __syncthreads();
-  // r_{k+1} = r_k - alpha_k A_s p_k on the one-hop halo (kept in registers
-  // until every thread has read p_k); tile points store r_{k+1}, p_k, x_{k+1}
-  int qi[NP];
+
+  // 5. r_{k+1} = r_k - alpha_k (p_k - c A p_k) on the one-hop region; tile
+  //    points store r_{k+1}, p_k, x_{k+1}
 #pragma unroll
-  for (int j = 0; j < NP; ++j) {
-    const int i = threadIdx.x + j * BS;
-    qi[j] = -1;
-    if (i < PW * PH) {
-      const int py = fdiv(i, a.m_pw), px = i - py * PW;
-      if (px >= Rx && px < PW - Rx && py >= Ry && py < PH - Ry) {
-        qi[j] = (px - Rx) + (py - Ry) * QW;
-        const V acc = tile_stencil<NT, T>(a, Pt, i, PW);
-        const V p = Pt[i];
-        rp[j] = vsub(rp[j], vmul(al, vsub(p, vmul(sft, acc))));  // now r_{k+1}
-        if (gq[j] >= 0) {
-          const int g = gq[j];
-          Rout[g] = rp[j];
-          Pnew[g] = p;
-          X[g] = (k == 0) ? vmul(al, p) : vadd(xq[j], vmul(al, p));
-        }
+  for (int j = 0; j < NI; ++j) {
+    if (li[j] >= 0) {
+      const V acc = tile_stencil<NT, T>(a, Pt, li[j], PW);
+      const V p = Pt[li[j]];
+      ri[j] = vsub(ri[j], vmul(al, vsub(p, vmul(sft, acc))));
+      if (gi[j] >= 0) {
+        Rout[gi[j]] = ri[j];
+        Pnew[gi[j]] = p;
+        X[gi[j]] = vadd(xi[j], vmul(al, p));
       }
     }
     // one point at a time: keeps the stencil operands of different points
     // from being live together (register pressure -> occupancy)
     __builtin_amdgcn_sched_barrier(0);
   }
+#pragma unroll
+  for (int j = 0; j < NH; ++j) {
+    if (qh[j] >= 0) {
+      const V acc = tile_stencil<NT, T>(a, Pt, lh[j], PW);
+      rh[j] = vsub(rh[j], vmul(al, vsub(Pt[lh[j]], vmul(sft, acc))));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
   __syncthreads();
   V* Rt = Pt;
 #pragma unroll
-  for (int j = 0; j < NP; ++j)
-    if (qi[j] >= 0) Rt[qi[j]] = rp[j];
+  for (int j = 0; j < NI; ++j)
+    if (li[j] >= 0) Rt[qi[j]] = ri[j];
+#pragma unroll
+  for (int j = 0; j < NH; ++j)
+    if (qh[j] >= 0) Rt[qh[j]] = rh[j];
   __syncthreads();
-  // gamma_{k+1}, delta_{k+1} = r^T A_s r, ||r_{k+1}||^2 at the tile points
-  double v[kQ] = {0, 0, 0, 0, 0};
-  for (int i = threadIdx.x; i < TX * TY; i += BS) {
-    const int iy = fdiv(i, a.m_tx), ix = i - iy * TX;
-    if (x0 + ix >= nx || y0 + iy >= ny) continue;
-    const int cr = (ix + Rx) + (iy + Ry) * QW;
-    const V acc = tile_stencil<NT, T>(a, Rt, cr, QW);
-    const V r = Rt[cr];
-    const V w = vsub(r, vmul(sft, acc));
-    v[0] += (double)r.x * r.x - (double)r.y * r.y;
-    v[1] += 2.0 * (double)r.x * r.y;
-    v[2] += (double)r.x * w.x - (double)r.y * w.y;
-    v[3] += (double)r.x * w.y + (double)r.y * w.x;
-    v[4] += (double)r.x * r.x + (double)r.y * r.y;
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  block_sum_w<kQ, BS / 64>(v, sh);
-  if (threadIdx.x == 0) {
-    double* pb = a.part + (a.fused ? (size_t)(k & 1) * kQ * a.num_sys * a.ntiles : 0);
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) pb[((size_t)q * a.num_sys + s) * a.ntiles + tile] = v[q];
-  }
-}
 
-// Row-marching pass (2D, stencil reach RY <= 2 in y): a workgroup owns a strip
-// of SX = TX columns and SY = TY rows and walks down it one row per step.
-// Step i brings in row y0 - 2RY + i of r_k and p_{k-1} (prefetched two steps
-// ahead) and forms p_k there in an LDS ring of 2RY+1 rows; one row behind it
-// applies A_s to p_k and forms r_{k+1} in a second ring; another row behind,
-// A_s r_{k+1} gives the dot products.  r_k of the last RY+1 rows stays in
-// registers.  The y halo is paid only at the strip ends.
-template <typename T, int RY, int NT>
-__global__ __launch_bounds__(kBlock) void k_cg_march(CgArgs a, int k) {
-  using V = typename cvec<T>::type;
-  extern __shared__ char smem[];
-  __shared__ double sh[4 * kQ];
-  __shared__ int act;
-  __shared__ double2 sc[2];
-  constexpr int NR = 2 * RY + 1;
-  const int s = a.sys_list[blockIdx.y];
-  int tile = blockIdx.x;
-  if (a.xcd_band > 0) tile = (tile & 7) * a.xcd_band + (tile >> 3);
-  if (threadIdx.x == 0) act = a.st[s].active;
-  __syncthreads();
-  if (!act) return;
-  if (!cg_prologue<kBlock>(a, k, s, tile, sh, &act, sc)) return;
-  const V al = from_d2<V>(sc[0]);
-  const V be = from_d2<V>(sc[1]);
-  const V sft = from_d2<V>(a.shift[s]);
-  const int Rx = a.Rx, SX = a.TX, SY = a.TY;
-  const int PWr = SX + 4 * Rx, QWr = SX + 2 * Rx;
-  V* Pr = reinterpret_cast<V*>(smem);  // [NR][PWr]: p_k rows
-  V* Qr = Pr + NR * PWr;                // [NR][QWr]: r_{k+1} rows
-  const int nx = a.g.nx, ny = a.g.ny;
-  const int ty = fdiv(tile, a.m_ntx), tx = tile - ty * a.ntx;
-  const int x0 = tx * SX, y0 = ty * SY;
-  const size_t off = (size_t)s * a.g.N;
-  const V* Rin = reinterpret_cast<const V*>(a.R[k & 1]) + off;
-  V* Rout = reinterpret_cast<V*>(a.R[(k + 1) & 1]) + off;
-  const V* Pold = reinterpret_cast<const V*>(a.P[(k + 1) & 1]) + off;
-  V* Pnew = reinterpret_cast<V*>(a.P[k & 1]) + off;
-  V* X = reinterpret_cast<V*>(a.X) + off;
-
-  // this thread's positions in a P row: pos = tid and tid + 256
-  int pos[2], gx[2];
-  bool valid[2], inner[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    pos[j] = threadIdx.x + j * kBlock;
-    valid[j] = pos[j] < PWr;
-    const int ux = x0 - 2 * Rx + pos[j];
-    gx[j] = pmod(ux, nx);
-    inner[j] = valid[j] && pos[j] >= 2 * Rx && pos[j] < 2 * Rx + SX && ux < nx;
-  }
-  const int nsteps = SY + 4 * RY;
-  auto load_row = [&](int i, V (&r)[2], V (&p)[2]) {
-    const int gy = pmod(y0 - 2 * RY + i, ny) * nx;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      if (valid[j]) {
-        r[j] = Rin[gy + gx[j]];
-        if (k > 0) p[j] = Pold[gy + gx[j]];
-      }
-    }
-  };
-  V qr0[2], qp0[2], qr1[2], qp1[2];
-  load_row(0, qr0, qp0);
-  if (nsteps > 1) load_row(1, qr1, qp1);
-  V rr[RY + 1][2];
+  // 6. gamma_{k+1}, delta_{k+1} = r^T A_s r and ||r_{k+1}||^2 over the tile
   double v[kQ] = {0, 0, 0, 0, 0};
-  for (int i = 0; i < nsteps; ++i) {
-    V cr[2], cp[2];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      cr[j] = qr0[j];
-      cp[j] = qp0[j];
-      qr0[j] = qr1[j];
-      qp0[j] = qp1[j];
-    }
-    if (i + 2 < nsteps) load_row(i + 2, qr1, qp1);
-    const int yq = y0 - 3 * RY + i;  // row whose r_{k+1} this step forms
-    const bool doq = i >= 2 * RY;
-    const bool storeq = doq && yq >= y0 && yq < y0 + SY && yq < ny;
-    V xq[2];
-    if (storeq && k > 0) {
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        if (inner[j]) xq[j] = X[(size_t)yq * nx + gx[j]];
-    }
-    // (a) p_k on the incoming row
-    const int slot_in = i % NR;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      if (valid[j]) {
-        Pr[slot_in * PWr + pos[j]] = (k > 0) ? vadd(cr[j], vmul(be, cp[j])) : cr[j];
-      }
-      // shift register of r_k: rr[d] holds the row brought in d steps ago
-#pragma unroll
-      for (int d = RY; d > 0; --d) rr[d][j] = rr[d - 1][j];
-      rr[0][j] = cr[j];
-    }
-    __syncthreads();
-    // (b) r_{k+1} = r_k - alpha A_s p_k on row yq (one-hop halo in x)
-    if (doq) {
-      const int iq = i - RY;
-      const int sq = iq % NR;
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        if (valid[j] && pos[j] >= Rx && pos[j] < PWr - Rx) {
-          V acc = vzero<V>();
-          if (NT > 0) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-              const int sl = (iq + a.taps.dy[t] + NR) % NR;
-              acc = vadd(acc, vscale(Pr[sl * PWr + pos[j] + a.taps.dx[t]], (T)a.taps.c[t]));
-            }
-          } else {
-            for (int t = 0; t < a.taps.n; ++t) {
-              const int sl = (iq + a.taps.dy[t] + NR) % NR;
-              acc = vadd(acc, vscale(Pr[sl * PWr + pos[j] + a.taps.dx[t]], (T)a.taps.c[t]));
-            }
-          }
-          const V p = Pr[sq * PWr + pos[j]];
-          const V rn = vsub(rr[RY][j], vmul(al, vsub(p, vmul(sft, acc))));
-          Qr[sq * QWr + pos[j] - Rx] = rn;
-          if (storeq && inner[j]) {
-            const size_t g = (size_t)yq * nx + gx[j];
-            Rout[g] = rn;
-            Pnew[g] = p;
-            X[g] = (k == 0) ? vmul(al, p) : vadd(xq[j], vmul(al, p));
-          }
-        }
-      }
-    }
-    __syncthreads();
-    // (c) gamma, delta = r^T A_s r and ||r||^2 on row yw = yq - RY
-    const int yw = yq - RY;
-    if (i >= 3 * RY && yw >= y0 && yw < y0 + SY && yw < ny) {
-      const int iw = i - 2 * RY;
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        if (inner[j]) {
-          const int q = pos[j] - Rx;
-          V acc = vzero<V>();
-          if (NT > 0) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-              const int sl = (iw + a.taps.dy[t] + NR) % NR;
-              acc = vadd(acc, vscale(Qr[sl * QWr + q + a.taps.dx[t]], (T)a.taps.c[t]));
-            }
-          } else {
-            for (int t = 0; t < a.taps.n; ++t) {
-              const int sl = (iw + a.taps.dy[t] + NR) % NR;
-              acc = vadd(acc, vscale(Qr[sl * QWr + q + a.taps.dx[t]], (T)a.taps.c[t]));
-            }
-          }
-          const V r = Qr[(iw % NR) * QWr + q];
-          const V w = vsub(r, vmul(sft, acc));
-          v[0] += (double)r.x * r.x - (double)r.y * r.y;
-          v[1] += 2.0 * (double)r.x * r.y;
-          v[2] += (double)r.x * w.x - (double)r.y * w.y;
-          v[3] += (double)r.x * w.y + (double)r.y * w.x;
-          v[4] += (double)r.x * r.x + (double)r.y * r.y;
-        }
-      }
+  for (int j = 0; j < NI; ++j) {
+    if (gi[j] >= 0) {
+      const V acc = tile_stencil<NT, T>(a, Rt, qi[j], QW);
+      const V r = ri[j];
+      const V w = vsub(r, vmul(sft, acc));
+      v[0] += (double)r.x * r.x - (double)r.y * r.y;
+      v[1] += 2.0 * (double)r.x * r.y;
+      v[2] += (double)r.x * w.x - (double)r.y * w.y;
+      v[3] += (double)r.x * w.y + (double)r.y * w.x;
+      v[4] += (double)r.x * r.x + (double)r.y * r.y;
     }
   }
-  block_sum<kQ>(v, sh);
-  if (threadIdx.x == 0) {
+  block_sum_wave0<kQ>(v, sh);
+  if (t == 0) {
     double* pb = a.part + (a.fused ? (size_t)(k & 1) * kQ * a.num_sys * a.ntiles : 0);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) pb[((size_t)q * a.num_sys + s) * a.ntiles + tile] = v[q];
@@ -493,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_scalars(CgArgs a, int k) {
 #pragma unroll
     for (int q = 0; q < kQ; ++q) v[q] += cg_part(a, q, s)[c];
   }
-  block_sum<kQ>(v, sh);
+  block_sum_wave0<kQ>(v, sh);
   if (threadIdx.x != 0) return;
   const double2 gam = mk(v[0], v[1]);
   const double2 del = mk(v[2], v[3]);
@@ -541,9 +445,9 @@ size_t cg_lds_bytes(bool f32, const CgArgs& a) {
   return pw * ph * cs;  // the one-hop region reuses the same buffer
 }
 
-int cg_points_per_thread(const CgArgs& a) {
-  const int np = (a.TX + 4 * a.Rx) * (a.TY + 4 * a.Ry);
-  return (np + a.block - 1) / a.block;
+int cg_ring_slots(const CgArgs& a) {
+  const int nring = (a.TX + 4 * a.Rx) * (a.TY + 4 * a.Ry) - a.TX * a.TY;
+  return (nring + kBlock - 1) / kBlock;
 }
 
 hipError_t launch_cg_init(bool f32, const CgArgs& a, int nact, hipStream_t st) {
@@ -553,61 +457,29 @@ hipError_t launch_cg_init(bool f32, const CgArgs& a, int nact, hipStream_t st) {
   return hipGetLastError();
 }
 
-size_t cg_march_lds_bytes(bool f32, const CgArgs& a) {
-  const size_t cs = f32 ? sizeof(float2) : sizeof(double2);
-  const size_t nr = 2 * a.Ry + 1;
-  return nr * ((size_t)(a.TX + 4 * a.Rx) + (size_t)(a.TX + 2 * a.Rx)) * cs;
-}
-
 hipError_t launch_cg_pass(bool f32, const CgArgs& a, int k, int nact, hipStream_t st) {
+  if (a.TX * a.TY > kInside * kBlock) return hipErrorInvalidValue;
   dim3 grid(a.ntiles, nact);
-  if (a.march) {
-    const size_t lds = cg_march_lds_bytes(f32, a);
-    const int nt = (a.taps.n == 5) ? 5 : 0;
-#define AAO_CGM(RY, NT)                                                                         \
-  do {                                                                                          \
-    if (f32) hipLaunchKernelGGL((k_cg_march<float, RY, NT>), grid, dim3(kBlock), lds, st, a, k); \
-    else hipLaunchKernelGGL((k_cg_march<double, RY, NT>), grid, dim3(kBlock), lds, st, a, k);   \
-  } while (0)
-    if (a.Ry == 1) {
-      if (nt == 5) AAO_CGM(1, 5);
-      else AAO_CGM(1, 0);
-    } else if (a.Ry == 2) {
-      AAO_CGM(2, 0);
-    } else {
-      return hipErrorInvalidValue;
-    }
-#undef AAO_CGM
-    return hipGetLastError();
-  }
   const size_t lds = cg_lds_bytes(f32, a);
-  const int np = cg_points_per_thread(a);
+  const int nh = cg_ring_slots(a);
   const int nt = (a.taps.n == 3 || a.taps.n == 5) ? a.taps.n : 0;
-  const int bs = a.block;
-#define AAO_CGP4(NP, NT, BS)                                                                        \
-  do {                                                                                              \
-    if (f32) hipLaunchKernelGGL((k_cg_pass<float, NP, NT, BS>), grid, dim3(BS), lds, st, a, k);     \
-    else hipLaunchKernelGGL((k_cg_pass<double, NP, NT, BS>), grid, dim3(BS), lds, st, a, k);       \
+#define AAO_CGP2(NH, NT)                                                                          \
+  do {                                                                                            \
+    if (f32) hipLaunchKernelGGL((k_cg_pass<float, NH, NT>), grid, dim3(kBlock), lds, st, a, k);   \
+    else hipLaunchKernelGGL((k_cg_pass<double, NH, NT>), grid, dim3(kBlock), lds, st, a, k);      \
   } while (0)
-#define AAO_CGP3(NP, NT)                     \
-  do {                                       \
-    if (bs == 512) AAO_CGP4(NP, NT, 512);    \
-    else AAO_CGP4(NP, NT, 256);              \
+#define AAO_CGP(NH)                  \
+  do {                               \
+    if (nt == 3) AAO_CGP2(NH, 3);    \
+    else if (nt == 5) AAO_CGP2(NH, 5); \
+    else AAO_CGP2(NH, 0);            \
   } while (0)
-#define AAO_CGP(NP)                 \
-  do {                              \
-    if (nt == 3) AAO_CGP3(NP, 3);   \
-    else if (nt == 5) AAO_CGP3(NP, 5); \
-    else AAO_CGP3(NP, 0);           \
-  } while (0)
-  if (np <= 2) AAO_CGP(2);
-  else if (np <= 3) AAO_CGP(3);
-  else if (np <= 4) AAO_CGP(4);
-  else if (np <= 6) AAO_CGP(6);
-  else if (np <= kMaxPerThread) AAO_CGP(8);
+  if (nh <= 1) AAO_CGP(1);
+  else if (nh <= 2) AAO_CGP(2);
+  else if (nh <= 4) AAO_CGP(4);
+  else if (nh <= 8) AAO_CGP(8);
   else return hipErrorInvalidValue;
-#undef AAO_CGP4
-#undef AAO_CGP3
+#undef AAO_CGP2
 #undef AAO_CGP
   return hipGetLastError();
 }

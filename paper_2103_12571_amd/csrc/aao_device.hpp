@@ -23,8 +23,8 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a * conj(b)
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return mk(a.x, -a.y); }
 __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
-  double d = b.x * b.x + b.y * b.y;
-  return mk((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+  const double inv = 1.0 / (b.x * b.x + b.y * b.y);  // one division per quotient
+  return mk((a.x * b.x + a.y * b.y) * inv, (a.y * b.x - a.x * b.y) * inv);
 }
 __device__ __forceinline__ double2 to_d2(double2 a) { return a; }
 __device__ __forceinline__ double2 to_d2(float2 a) { return mk(a.x, a.y); }
@@ -57,47 +57,50 @@ __device__ __forceinline__ int bitrev(int v, int logL) {
   return logL == 0 ? 0 : (int)(__brev((unsigned)v) >> (32 - logL));
 }
 
-// Sum of K values over the 256-thread block; every thread receives the result.
-// The butterfly over lanes adds each pair in both orders, which is exact-equal,
-// so all lanes (and every workgroup doing the same reduction) agree bitwise.
-// Same for a block of NW wavefronts (sh holds NW * K doubles).
-template <int K, int NW>
-__device__ __forceinline__ void block_sum_w(double (&v)[K], double* sh) {
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    double x = v[i];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    v[i] = x;
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < K; ++i) sh[wid * K + i] = v[i];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) t += sh[w * K + i];
-    v[i] = t;
-  }
+// Lane permutations inside each row of 16 lanes (DPP), on a double split into
+// its two 32-bit halves.  CTRL: 0xB1 swaps neighbours, 0x4E swaps pairs,
+// 0x141 mirrors each half-row, 0x140 mirrors the row.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ double lane_f64(double x, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), lane),
+                          __builtin_amdgcn_readlane(__double2loint(x), lane));
+}
+
+// Sum over the 64 lanes of a wavefront (all lanes active).  The four in-row
+// steps add each pair in both orders, so all 16 lanes of a row hold the same
+// bits; the four row sums are then added in a fixed order.  Wave-uniform.
+__device__ __forceinline__ double wave_sum(double x) {
+  x += dpp_f64<0xB1>(x);
+  x += dpp_f64<0x4E>(x);
+  x += dpp_f64<0x141>(x);
+  x += dpp_f64<0x140>(x);
+  return (lane_f64(x, 0) + lane_f64(x, 16)) + (lane_f64(x, 32) + lane_f64(x, 48));
+}
+
+__device__ __forceinline__ double wave_max(double x) {
+  x = fmax(x, dpp_f64<0xB1>(x));
+  x = fmax(x, dpp_f64<0x4E>(x));
+  x = fmax(x, dpp_f64<0x141>(x));
+  x = fmax(x, dpp_f64<0x140>(x));
+  return fmax(fmax(lane_f64(x, 0), lane_f64(x, 16)), fmax(lane_f64(x, 32), lane_f64(x, 48)));
+}
+
+// Sum of K values over the 256-thread block (4 wavefronts); every thread
+// receives the result, and every workgroup doing the same reduction gets the
+// same bits.  sh holds 4 * K doubles; called by all threads.
 template <int K>
 __device__ __forceinline__ void block_sum(double (&v)[K], double* sh) {
 #pragma unroll
-  for (int i = 0; i < K; ++i) {
-    double x = v[i];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    v[i] = x;
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i = 0; i < K; ++i) v[i] = wave_sum(v[i]);
+  const int wid = threadIdx.x >> 6;
   __syncthreads();
-  if (lane == 0) {
+  if ((threadIdx.x & 63) == 0) {
 #pragma unroll
     for (int i = 0; i < K; ++i) sh[wid * K + i] = v[i];
   }
@@ -106,12 +109,34 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* sh) {
   for (int i = 0; i < K; ++i) v[i] = (sh[i] + sh[K + i]) + (sh[2 * K + i] + sh[3 * K + i]);
 }
 
-__device__ __forceinline__ double block_max(double v, double* sh) {
+// Same sums, delivered to wavefront 0 only (lane q of wavefront 0 adds the
+// four wavefront sums of quantity q, then every lane of wavefront 0 reads all
+// K totals): fewer registers than every thread reading every partial.
+template <int K>
+__device__ __forceinline__ void block_sum_wave0(double (&v)[K], double* sh) {
+  static_assert(K <= 64, "one lane per quantity");
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i = 0; i < K; ++i) v[i] = wave_sum(v[i]);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __syncthreads();
-  if (lane == 0) sh[wid] = v;
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) sh[wid * K + i] = v[i];
+  }
+  __syncthreads();
+  if (wid == 0) {
+    const int q = lane < K ? lane : 0;
+    const double tq = (sh[q] + sh[K + q]) + (sh[2 * K + q] + sh[3 * K + q]);
+#pragma unroll
+    for (int i = 0; i < K; ++i) v[i] = lane_f64(tq, i);
+  }
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  v = wave_max(v);
+  const int wid = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[wid] = v;
   __syncthreads();
   return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }

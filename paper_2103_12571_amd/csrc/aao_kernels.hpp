@@ -56,12 +56,11 @@ struct CgArgs {
   Taps taps;
   int num_sys;
   int TX, TY, ntx, nty, ntiles, Rx, Ry;
-  // ceil(2^40 / d) for exact division by ntx, TX and the two halo widths
-  unsigned long long m_ntx, m_tx, m_pw, m_qw;
+  // ceil(2^40 / d) for exact division by ntx, TX, the two-hop width
+  // TX + 4 Rx and the side-ring width 4 Rx (0 when Rx = 0)
+  unsigned long long m_ntx, m_tx, m_pw, m_hw;
   int xcd_band;  // ntiles / 8 when tiles are banded per XCD, else 0
   int fused;     // 1: each pass advances the scalars itself (partials double-buffered)
-  int march;     // 1: row-marching strips of TX columns x TY rows (2D, Ry <= 2)
-  int block;     // threads per workgroup of the tile pass (256 or 512)
   double tol2;
   int maxit;
 };
@@ -155,8 +154,7 @@ hipError_t launch_cg_init(bool f32, const CgArgs& a, int nact, hipStream_t st);
 hipError_t launch_cg_pass(bool f32, const CgArgs& a, int k, int nact, hipStream_t st);
 hipError_t launch_cg_scalars(const CgArgs& a, int k, int nact, hipStream_t st);
 size_t cg_lds_bytes(bool f32, const CgArgs& a);
-size_t cg_march_lds_bytes(bool f32, const CgArgs& a);
-int cg_points_per_thread(const CgArgs& a);
+int cg_ring_slots(const CgArgs& a);
 hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, int nact, hipStream_t st);
 hipError_t launch_krylov_init(const KrylovArgs& a, hipStream_t st);
 hipError_t launch_fft_solve(bool f32, const FftArgs& a, int nsys, hipStream_t st);
