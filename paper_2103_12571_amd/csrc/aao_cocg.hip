@@ -85,16 +85,37 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
   }
 }
 
+// A complex tile in LDS.  complex128 is kept as two planes (real parts, then
+// imaginary parts) so that every access is an 8-byte LDS operation, which the
+// LDS serves at a higher rate than 16-byte ones; complex64 stays interleaved.
+template <typename V> struct LdsTile;
+template <> struct LdsTile<double2> {
+  double* re;
+  double* im;
+  __device__ LdsTile(void* base, int n) : re(static_cast<double*>(base)), im(static_cast<double*>(base) + n) {}
+  __device__ double2 ld(int i) const { return mk(re[i], im[i]); }
+  __device__ void st(int i, double2 v) const {
+    re[i] = v.x;
+    im[i] = v.y;
+  }
+};
+template <> struct LdsTile<float2> {
+  float2* p;
+  __device__ LdsTile(void* base, int) : p(static_cast<float2*>(base)) {}
+  __device__ float2 ld(int i) const { return p[i]; }
+  __device__ void st(int i, float2 v) const { p[i] = v; }
+};
+
 // Taps applied to an LDS tile with row pitch W: NT > 0 unrolls a fixed count.
 template <int NT, typename T, typename V>
-__device__ __forceinline__ V tile_stencil(const CgArgs& a, const V* buf, int c, int W) {
+__device__ __forceinline__ V tile_stencil(const CgArgs& a, const LdsTile<V>& buf, int c, int W) {
   V acc = vzero<V>();
   if (NT > 0) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc = vadd(acc, vscale(buf[c + a.taps.dx[t] + a.taps.dy[t] * W], (T)a.taps.c[t]));
+    for (int t = 0; t < NT; ++t) acc = vadd(acc, vscale(buf.ld(c + a.taps.dx[t] + a.taps.dy[t] * W), (T)a.taps.c[t]));
   } else {
     for (int t = 0; t < a.taps.n; ++t)
-      acc = vadd(acc, vscale(buf[c + a.taps.dx[t] + a.taps.dy[t] * W], (T)a.taps.c[t]));
+      acc = vadd(acc, vscale(buf.ld(c + a.taps.dx[t] + a.taps.dy[t] * W), (T)a.taps.c[t]));
   }
   return acc;
 }
@@ -177,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   const V* Pold = reinterpret_cast<const V*>(a.P[(k + 1) & 1]) + off;
   V* Pnew = reinterpret_cast<V*>(a.P[k & 1]) + off;
   V* X = reinterpret_cast<V*>(a.X) + off;
-  V* Pt = reinterpret_cast<V*>(smem);  // p_k on the two-hop region, then r_{k+1} on the one-hop region
+  const LdsTile<V> Pt(smem, PW * PH);  // p_k on the two-hop region, then r_{k+1} on the one-hop region
 
   // 1. What decides this pass's scalars is requested first (the previous
   //    pass's tile sums in fused mode, the system state), so that it arrives
@@ -317,10 +338,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   // 4. p_k = r_k + beta_k p_{k-1} on the two-hop region
 #pragma unroll
   for (int j = 0; j < NI; ++j)
-    if (li[j] >= 0) Pt[li[j]] = (k > 0) ? vadd(ri[j], vmul(be, pi[j])) : ri[j];
+    if (li[j] >= 0) Pt.st(li[j], (k > 0) ? vadd(ri[j], vmul(be, pi[j])) : ri[j]);
 #pragma unroll
   for (int j = 0; j < NH; ++j)
-    if (lh[j] >= 0) Pt[lh[j]] = (k > 0) ? vadd(rh[j], vmul(be, ph[j])) : rh[j];
+    if (lh[j] >= 0) Pt.st(lh[j], (k > 0) ? vadd(rh[j], vmul(be, ph[j])) : rh[j]);
   V xi[NI];
 #pragma unroll
   for (int j = 0; j < NI; ++j) xi[j] = (k > 0 && gi[j] >= 0) ? X[gi[j]] : vzero<V>();
@@ -332,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   for (int j = 0; j < NI; ++j) {
     if (li[j] >= 0) {
       const V acc = tile_stencil<NT, T>(a, Pt, li[j], PW);
-      const V p = Pt[li[j]];
+      const V p = Pt.ld(li[j]);
       ri[j] = vsub(ri[j], vmul(al, vsub(p, vmul(sft, acc))));
       if (gi[j] >= 0) {
         Rout[gi[j]] = ri[j];
@@ -348,18 +369,18 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   for (int j = 0; j < NH; ++j) {
     if (qh[j] >= 0) {
       const V acc = tile_stencil<NT, T>(a, Pt, lh[j], PW);
-      rh[j] = vsub(rh[j], vmul(al, vsub(Pt[lh[j]], vmul(sft, acc))));
+      rh[j] = vsub(rh[j], vmul(al, vsub(Pt.ld(lh[j]), vmul(sft, acc))));
     }
     __builtin_amdgcn_sched_barrier(0);
   }
   __syncthreads();
-  V* Rt = Pt;
+  const LdsTile<V>& Rt = Pt;
 #pragma unroll
   for (int j = 0; j < NI; ++j)
-    if (li[j] >= 0) Rt[qi[j]] = ri[j];
+    if (li[j] >= 0) Rt.st(qi[j], ri[j]);
 #pragma unroll
   for (int j = 0; j < NH; ++j)
-    if (qh[j] >= 0) Rt[qh[j]] = rh[j];
+    if (qh[j] >= 0) Rt.st(qh[j], rh[j]);
   __syncthreads();
 
   // 6. gamma_{k+1}, delta_{k+1} = r^T A_s r and ||r_{k+1}||^2 over the tile
