@@ -152,8 +152,10 @@ hipEvent_t get_event(aao_plan* p) {
     p->pool.pop_back();
     return e;
   }
+  // timing only (elapsed times are read after a stream synchronisation): no
+  // system-scope fence, so recording does not write back and invalidate caches
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 

@@ -85,30 +85,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
   }
 }
 
-// A complex tile in LDS.  complex128 is kept as two planes (real parts, then
-// imaginary parts) so that every access is an 8-byte LDS operation, which the
-// LDS serves at a higher rate than 16-byte ones; complex64 stays interleaved.
-template <typename V> struct LdsTile;
-template <> struct LdsTile<double2> {
-  double* re;
-  double* im;
-  __device__ LdsTile(void* base, int n) : re(static_cast<double*>(base)), im(static_cast<double*>(base) + n) {}
-  __device__ double2 ld(int i) const { return mk(re[i], im[i]); }
-  __device__ void st(int i, double2 v) const {
-    re[i] = v.x;
-    im[i] = v.y;
-  }
-};
-template <> struct LdsTile<float2> {
-  float2* p;
-  __device__ LdsTile(void* base, int) : p(static_cast<float2*>(base)) {}
-  __device__ float2 ld(int i) const { return p[i]; }
-  __device__ void st(int i, float2 v) const { p[i] = v; }
-};
-
 // Taps applied to an LDS tile with row pitch W: NT > 0 unrolls a fixed count.
 template <int NT, typename T, typename V>
-__device__ __forceinline__ V tile_stencil(const CgArgs& a, const LdsTile<V>& buf, int c, int W) {
+__device__ __forceinline__ V tile_stencil(const CgArgs& a, const LdsCplx<V>& buf, int c, int W) {
   V acc = vzero<V>();
   if (NT > 0) {
 #pragma unroll
@@ -198,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   const V* Pold = reinterpret_cast<const V*>(a.P[(k + 1) & 1]) + off;
   V* Pnew = reinterpret_cast<V*>(a.P[k & 1]) + off;
   V* X = reinterpret_cast<V*>(a.X) + off;
-  const LdsTile<V> Pt(smem, PW * PH);  // p_k on the two-hop region, then r_{k+1} on the one-hop region
+  const LdsCplx<V> Pt(smem, PW * PH);  // p_k on the two-hop region, then r_{k+1} on the one-hop region
 
   // 1. What decides this pass's scalars is requested first (the previous
   //    pass's tile sums in fused mode, the system state), so that it arrives
@@ -374,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
     __builtin_amdgcn_sched_barrier(0);
   }
   __syncthreads();
-  const LdsTile<V>& Rt = Pt;
+  const LdsCplx<V>& Rt = Pt;
 #pragma unroll
   for (int j = 0; j < NI; ++j)
     if (li[j] >= 0) Rt.st(qi[j], ri[j]);
@@ -461,9 +440,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_scalars(CgArgs a, int k) {
 }  // namespace
 
 size_t cg_lds_bytes(bool f32, const CgArgs& a) {
-  const size_t cs = f32 ? sizeof(float2) : sizeof(double2);
-  const size_t pw = a.TX + 4 * a.Rx, ph = a.TY + 4 * a.Ry;
-  return pw * ph * cs;  // the one-hop region reuses the same buffer
+  const int n = (a.TX + 4 * a.Rx) * (a.TY + 4 * a.Ry);  // the one-hop region reuses the same buffer
+  return f32 ? LdsCplx<float2>::bytes(n) : LdsCplx<double2>::bytes(n);
 }
 
 int cg_ring_slots(const CgArgs& a) {

@@ -141,10 +141,43 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
   return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
-// In-place radix-2 DIT FFT over the row index of c[L][ncol] (bit-reversed
-// input order, natural output order).  INV selects e^{+2 pi i ...}.
+// LDS arrays of complex128 are kept as two planes of doubles (real parts,
+// then imaginary parts): 8-byte LDS accesses avoid the stalls that 16-byte
+// accesses at arbitrary element offsets incur.  The imaginary plane starts
+// kPlanePad doubles after the real one ends, which puts the two halves of a
+// wavefront's access on different banks.
+constexpr int kPlanePad = 8;
+
+// A complex array of n elements in LDS: complex128 as planes (re, im, padded
+// as above), complex64 interleaved (8-byte elements already).
+template <typename V> struct LdsCplx;
+template <> struct LdsCplx<double2> {
+  double* re;
+  double* im;
+  // the pad is dropped where it would push the array past 64 KiB
+  static constexpr int stride(int n) { return 2 * (n + kPlanePad) * 8 <= 65536 ? n + kPlanePad : n; }
+  static constexpr size_t bytes(int n) { return 2 * (size_t)stride(n) * sizeof(double); }
+  __device__ LdsCplx(void* base, int n) : re(static_cast<double*>(base)), im(static_cast<double*>(base) + stride(n)) {}
+  __device__ double2 ld(int i) const { return mk(re[i], im[i]); }
+  __device__ void st(int i, double2 v) const {
+    re[i] = v.x;
+    im[i] = v.y;
+  }
+};
+template <> struct LdsCplx<float2> {
+  float2* p;
+  __device__ LdsCplx(void* base, int) : p(static_cast<float2*>(base)) {}
+  static constexpr size_t bytes(int n) { return (size_t)n * sizeof(float2); }
+  __device__ float2 ld(int i) const { return p[i]; }
+  __device__ void st(int i, float2 v) const { p[i] = v; }
+};
+
+// In-place radix-2 DIT FFT over the row index of the complex array c[L][ncol]
+// held as planes (re, im): bit-reversed input order, natural output order.
+// (twr, twi) = e^{-2 pi i k / L}, k < L/2; INV uses the conjugates.
 template <bool INV>
-__device__ __forceinline__ void lds_fft(double2* c, const double2* tw, int L, int logL, int ncol) {
+__device__ __forceinline__ void lds_fft(double* re, double* im, const double* twr, const double* twi, int L,
+                                        int logL, int ncol) {
   for (int s = 0; s < logL; ++s) {
     const int half = 1 << s;
     const int tstride = L >> (s + 1);
@@ -155,13 +188,14 @@ __device__ __forceinline__ void lds_fft(double2* c, const double2* tw, int L, in
       const int k = idx / ncol;
       const int pos = k & (half - 1);
       const int i0 = ((k >> s) << (s + 1)) + pos;
-      const int i1 = i0 + half;
-      double2 w = tw[pos * tstride];
-      if (INV) w.y = -w.y;
-      const double2 a = c[i0 * ncol + col];
-      const double2 b = cmul(w, c[i1 * ncol + col]);
-      c[i0 * ncol + col] = cadd(a, b);
-      c[i1 * ncol + col] = csub(a, b);
+      const int o0 = i0 * ncol + col, o1 = o0 + half * ncol;
+      const double2 w = mk(twr[pos * tstride], INV ? -twi[pos * tstride] : twi[pos * tstride]);
+      const double2 x0 = mk(re[o0], im[o0]);
+      const double2 x1 = cmul(w, mk(re[o1], im[o1]));
+      re[o0] = x0.x + x1.x;
+      im[o0] = x0.y + x1.y;
+      re[o1] = x0.x - x1.x;
+      im[o1] = x0.y - x1.y;
     }
   }
   __syncthreads();

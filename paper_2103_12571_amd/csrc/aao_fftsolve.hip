@@ -22,10 +22,11 @@ template <typename V> struct scal;
 template <> struct scal<double2> { using type = double; };
 template <> struct scal<float2> { using type = float; };
 
-// Element (b, i) of a batch of transforms lives at c[b * sb + i * se].  The
-// table W holds e^{+2 pi i k / n}, k < n.
+// Element (b, i) of a batch of transforms lives at c[b * sb + i * se] (an LDS
+// complex array).  The table W holds e^{+2 pi i k / n}, k < n.
 template <typename V, bool INV, bool FASTB>
-__device__ __forceinline__ void fft_dit(V* c, const double2* W, int n, int logn, int nb, int sb, int se) {
+__device__ __forceinline__ void fft_dit(const LdsCplx<V>& c, const double2* W, int n, int logn, int nb, int sb,
+                                        int se) {
   using T = typename scal<V>::type;
   const int half_n = n >> 1;
   for (int s = 0; s < logn; ++s) {
@@ -41,19 +42,19 @@ __device__ __forceinline__ void fft_dit(V* c, const double2* W, int n, int logn,
       V w;
       w.x = (T)wd.x;
       w.y = INV ? (T)wd.y : (T)-wd.y;
-      V* p0 = c + b * sb + i0 * se;
-      V* p1 = p0 + half * se;
-      const V a = *p0;
-      const V t = vmul(w, *p1);
-      *p0 = vadd(a, t);
-      *p1 = vsub(a, t);
+      const int o0 = b * sb + i0 * se, o1 = o0 + half * se;
+      const V a = c.ld(o0);
+      const V t = vmul(w, c.ld(o1));
+      c.st(o0, vadd(a, t));
+      c.st(o1, vsub(a, t));
     }
   }
   __syncthreads();
 }
 
 template <typename V, bool INV, bool FASTB>
-__device__ __forceinline__ void fft_dif(V* c, const double2* W, int n, int logn, int nb, int sb, int se) {
+__device__ __forceinline__ void fft_dif(const LdsCplx<V>& c, const double2* W, int n, int logn, int nb, int sb,
+                                        int se) {
   using T = typename scal<V>::type;
   const int half_n = n >> 1;
   for (int s = logn - 1; s >= 0; --s) {
@@ -69,12 +70,11 @@ __device__ __forceinline__ void fft_dif(V* c, const double2* W, int n, int logn,
       V w;
       w.x = (T)wd.x;
       w.y = INV ? (T)wd.y : (T)-wd.y;
-      V* p0 = c + b * sb + i0 * se;
-      V* p1 = p0 + half * se;
-      const V a = *p0;
-      const V d = *p1;
-      *p0 = vadd(a, d);
-      *p1 = vmul(vsub(a, d), w);
+      const int o0 = b * sb + i0 * se, o1 = o0 + half * se;
+      const V a = c.ld(o0);
+      const V d = c.ld(o1);
+      c.st(o0, vadd(a, d));
+      c.st(o1, vmul(vsub(a, d), w));
     }
   }
   __syncthreads();
@@ -99,9 +99,9 @@ __device__ __forceinline__ double2 inv_symbol(const FftArgs& a, double2 c, int k
 template <typename V, int MODE>
 __global__ __launch_bounds__(kBlock) void k_fft_rows(FftArgs a) {
   extern __shared__ char smem[];
-  V* c = reinterpret_cast<V*>(smem);
   const int s = blockIdx.y;
   const int nx = a.nx, rows = a.rows;
+  const LdsCplx<V> c(smem, rows * nx);
   int grp = blockIdx.x;
   if ((gridDim.x & 7) == 0) grp = (grp & 7) * (gridDim.x >> 3) + (grp >> 3);
   const int y0 = grp * rows;
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(FftArgs a) {
   for (int i = threadIdx.x; i < tot; i += kBlock) {
     const int r = i / nx, x = i - r * nx;
     const int dst = (MODE == 1) ? i : r * nx + dev::bitrev(x, a.lognx);
-    c[dst] = in[i];
+    c.st(dst, in[i]);
   }
   if (MODE == 1) {
     fft_dif<V, true, false>(c, a.Wx, nx, a.lognx, rows, nx, 1);
@@ -123,14 +123,14 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(FftArgs a) {
     for (int i = threadIdx.x; i < nx; i += kBlock) {
       const double2 f = inv_symbol(a, sh, i, 0);
       const V fv = from_d2<V>(f);
-      c[i] = vmul(c[i], fv);
+      c.st(i, vmul(c.ld(i), fv));
     }
     fft_dif<V, true, false>(c, a.Wx, nx, a.lognx, 1, nx, 1);
   }
   for (int i = threadIdx.x; i < tot; i += kBlock) {
     const int r = i / nx, x = i - r * nx;
     const int src = (MODE == 0) ? i : r * nx + dev::bitrev(x, a.lognx);
-    out[i] = c[src];
+    out[i] = c.ld(src);
   }
 }
 
@@ -139,9 +139,9 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(FftArgs a) {
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_fft_cols(FftArgs a) {
   extern __shared__ char smem[];
-  V* c = reinterpret_cast<V*>(smem);
   const int s = blockIdx.y;
   const int nx = a.nx, ny = a.ny, cols = a.cols;
+  const LdsCplx<V> c(smem, ny * cols);
   int grp = blockIdx.x;  // XCD-banded: neighbouring column groups share cache lines
   if ((gridDim.x & 7) == 0) grp = (grp & 7) * (gridDim.x >> 3) + (grp >> 3);
   const int x0 = grp * cols;
@@ -149,35 +149,35 @@ __global__ __launch_bounds__(kBlock) void k_fft_cols(FftArgs a) {
   const int tot = ny * cols;
   for (int i = threadIdx.x; i < tot; i += kBlock) {
     const int y = i / cols, col = i - y * cols;
-    c[dev::bitrev(y, a.logny) * cols + col] = base[(size_t)y * nx + col];
+    c.st(dev::bitrev(y, a.logny) * cols + col, base[(size_t)y * nx + col]);
   }
   fft_dit<V, false, true>(c, a.Wy, ny, a.logny, cols, 1, cols);
   const double2 sh = a.shift[s];
   for (int i = threadIdx.x; i < tot; i += kBlock) {
     const int y = i / cols, col = i - y * cols;
     const V fv = from_d2<V>(inv_symbol(a, sh, x0 + col, y));
-    c[i] = vmul(c[i], fv);
+    c.st(i, vmul(c.ld(i), fv));
   }
   fft_dif<V, true, true>(c, a.Wy, ny, a.logny, cols, 1, cols);
   for (int i = threadIdx.x; i < tot; i += kBlock) {
     const int y = i / cols, col = i - y * cols;
-    base[(size_t)y * nx + col] = c[dev::bitrev(y, a.logny) * cols + col];
+    base[(size_t)y * nx + col] = c.ld(dev::bitrev(y, a.logny) * cols + col);
   }
 }
 
 }  // namespace
 
 hipError_t launch_fft_solve(bool f32, const FftArgs& a, int nsys, hipStream_t st) {
-  const size_t cs = f32 ? sizeof(float2) : sizeof(double2);
+  auto lbytes = [&](int n) { return f32 ? LdsCplx<float2>::bytes(n) : LdsCplx<double2>::bytes(n); };
   if (a.ny == 1) {
     dim3 grid(1, nsys);
-    const size_t lds = (size_t)a.nx * cs;
+    const size_t lds = lbytes(a.nx);
     if (f32) hipLaunchKernelGGL((k_fft_rows<float2, 2>), grid, dim3(kBlock), lds, st, a);
     else hipLaunchKernelGGL((k_fft_rows<double2, 2>), grid, dim3(kBlock), lds, st, a);
     return hipGetLastError();
   }
   dim3 grow(a.ny / a.rows, nsys), gcol(a.nx / a.cols, nsys);
-  const size_t lrow = (size_t)a.rows * a.nx * cs, lcol = (size_t)a.cols * a.ny * cs;
+  const size_t lrow = lbytes(a.rows * a.nx), lcol = lbytes(a.cols * a.ny);
   if (f32) {
     hipLaunchKernelGGL((k_fft_rows<float2, 0>), grow, dim3(kBlock), lrow, st, a);
     hipLaunchKernelGGL((k_fft_cols<float2>), gcol, dim3(kBlock), lcol, st, a);

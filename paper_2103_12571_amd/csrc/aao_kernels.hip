@@ -32,9 +32,18 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
   int tile = blockIdx.x;
   if ((gridDim.x & 7) == 0) tile = (tile & 7) * (gridDim.x >> 3) + (tile >> 3);
   const int n0 = tile * TN;
-  double2* tw = reinterpret_cast<double2*>(lds + (size_t)L * M * TN);
+  // planes: real columns n0 + 2p in cre, n0 + 2p + 1 in cim ([L][M][P] each,
+  // l in bit-reversed order), then the twiddles
+  const int plane = L * M * P + kPlanePad;
+  double* cre = lds;
+  double* cim = lds + plane;
+  double* twr = lds + 2 * plane;
+  double* twi = twr + (L >> 1);
   __shared__ double sh[4];
-  for (int i = threadIdx.x; i < (L >> 1); i += kBlock) tw[i] = a.tw[i];
+  for (int i = threadIdx.x; i < (L >> 1); i += kBlock) {
+    twr[i] = a.tw[i].x;
+    twi[i] = a.tw[i].y;
+  }
 
   double res2 = 0.0;
   for (int idx = threadIdx.x; idx < L * TN; idx += kBlock) {
@@ -95,13 +104,13 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
     }
     const double sc = a.scale[l];
     const int lr = bitrev(l, a.logL);
+    double* dst = ((nl & 1) ? cim : cre) + (nl >> 1);
 #pragma unroll
-    for (int m = 0; m < M; ++m) lds[((size_t)lr * M + m) * TN + nl] = rv[m] * sc;
+    for (int m = 0; m < M; ++m) dst[((size_t)lr * M + m) * P] = rv[m] * sc;
   }
 
-  double2* c = reinterpret_cast<double2*>(lds);
   const int ncol = M * P;
-  lds_fft<false>(c, tw, L, a.logL, ncol);
+  lds_fft<false>(cre, cim, twr, twi, L, a.logL, ncol);
 
   OutV* out = reinterpret_cast<OutV*>(a.out);
   for (int idx = threadIdx.x; idx < a.Lh * P; idx += kBlock) {
@@ -111,8 +120,9 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
     double2 A[M], Bv[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-      const double2 Z = c[j * ncol + m * P + p];
-      const double2 Zc = c[jm * ncol + m * P + p];
+      const int oz = j * ncol + m * P + p, ozc = jm * ncol + m * P + p;
+      const double2 Z = mk(cre[oz], cim[oz]);
+      const double2 Zc = mk(cre[ozc], cim[ozc]);
       A[m] = mk(0.5 * (Z.x + Zc.x), 0.5 * (Z.y - Zc.y));
       Bv[m] = mk(0.5 * (Z.y + Zc.y), -0.5 * (Z.x - Zc.x));
       if (ADJ) {
@@ -211,10 +221,16 @@ __global__ __launch_bounds__(kBlock) void k_bwd(BwdArgs a) {
   int tile = blockIdx.x;
   if ((gridDim.x & 7) == 0) tile = (tile & 7) * (gridDim.x >> 3) + (tile >> 3);
   const int n0 = tile * TN;
-  double2* tw = reinterpret_cast<double2*>(lds + (size_t)L * M * TN);
+  const int plane = L * M * P + kPlanePad;  // as in k_fwd
+  double* cre = lds;
+  double* cim = lds + plane;
+  double* twr = lds + 2 * plane;
+  double* twi = twr + (L >> 1);
   __shared__ double sh[4];
-  for (int i = threadIdx.x; i < (L >> 1); i += kBlock) tw[i] = a.tw[i];
-  double2* c = reinterpret_cast<double2*>(lds);
+  for (int i = threadIdx.x; i < (L >> 1); i += kBlock) {
+    twr[i] = a.tw[i].x;
+    twi[i] = a.tw[i].y;
+  }
   const int ncol = M * P;
   const InV* in = reinterpret_cast<const InV*>(a.in);
 
@@ -250,11 +266,17 @@ __global__ __launch_bounds__(kBlock) void k_bwd(BwdArgs a) {
         ya.y = 0.0;
         yb.y = 0.0;
       }
-      c[jr * ncol + m * P + p] = mk(ya.x - yb.y, ya.y + yb.x);
-      if (!selfconj) c[jmr * ncol + m * P + p] = mk(ya.x + yb.y, yb.x - ya.y);
+      const int o = jr * ncol + m * P + p;
+      cre[o] = ya.x - yb.y;
+      cim[o] = ya.y + yb.x;
+      if (!selfconj) {
+        const int oc = jmr * ncol + m * P + p;
+        cre[oc] = ya.x + yb.y;
+        cim[oc] = yb.x - ya.y;
+      }
     }
   }
-  lds_fft<true>(c, tw, L, a.logL, ncol);
+  lds_fft<true>(cre, cim, twr, twi, L, a.logL, ncol);
 
   const int lmon = ADJ ? 0 : L - 1;
   double dmax = 0.0;
@@ -265,7 +287,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd(BwdArgs a) {
     const int l = lm / M;
     const int n = n0 + nl;
     if (n >= N) continue;
-    const double d = lds[idx] * a.scale[l];
+    const double d = ((nl & 1) ? cim : cre)[lm * P + (nl >> 1)] * a.scale[l];
     const size_t o = (((size_t)b * L + l) * M + m) * (size_t)N + n;
     if (MODE == 0) a.u[o] += d;
     else a.u[o] = d;
@@ -657,10 +679,15 @@ int grid_for(int64_t n, int per = kBlock, int cap = 8192) {
   return (int)g;
 }
 
+// two planes of L * M * TN/2 doubles (plus the pad) and the L/2 twiddles
+size_t xform_lds_bytes(int M, int L, int TN) {
+  return (2 * ((size_t)L * M * (TN / 2) + kPlanePad) + (size_t)L) * sizeof(double);
+}
+
 template <int M>
 hipError_t fwd_m(bool adj, bool from_r, bool out_f32, const FwdArgs& a, int B, hipStream_t st) {
   dim3 grid((a.g.N + a.TN - 1) / a.TN, B);
-  size_t lds = (size_t)a.L * M * a.TN * sizeof(double) + (size_t)(a.L / 2 + 1) * sizeof(double2);
+  size_t lds = xform_lds_bytes(M, a.L, a.TN);
 #define AAO_FWD(ADJ, MODE, OV) hipLaunchKernelGGL((k_fwd<M, ADJ, MODE, OV>), grid, dim3(kBlock), lds, st, a)
   if (!adj) {
     if (!from_r) { if (out_f32) AAO_FWD(false, 0, float2); else AAO_FWD(false, 0, double2); }
@@ -676,7 +703,7 @@ hipError_t fwd_m(bool adj, bool from_r, bool out_f32, const FwdArgs& a, int B, h
 template <int M>
 hipError_t bwd_m(bool adj, bool to_delta, bool in_f32, const BwdArgs& a, int B, hipStream_t st) {
   dim3 grid((a.g.N + a.TN - 1) / a.TN, B);
-  size_t lds = (size_t)a.L * M * a.TN * sizeof(double) + (size_t)(a.L / 2 + 1) * sizeof(double2);
+  size_t lds = xform_lds_bytes(M, a.L, a.TN);
 #define AAO_BWD(ADJ, MODE, IV) hipLaunchKernelGGL((k_bwd<M, ADJ, MODE, IV>), grid, dim3(kBlock), lds, st, a)
   if (!adj) {
     if (!to_delta) { if (in_f32) AAO_BWD(false, 0, float2); else AAO_BWD(false, 0, double2); }
