@@ -90,8 +90,7 @@ struct aao_plan {
   int S = 0, wps = 1, chunk = 256, nvec = 0;
   int cgTX = 1, cgTY = 1, cg_ntx = 1, cg_nty = 1, cg_ntiles = 1, Rx = 0, Ry = 0;
   int fft_rows = 1, fft_cols = 1;
-  int* hlist = nullptr;      // pinned staging of active-system lists (3 x S)
-  char* hstate = nullptr;    // pinned copies of the system states (2 x S)
+  int* hlist = nullptr;      // pinned: counts of active systems written by the device (2 ints)
   hipEvent_t chk_ev[2] = {nullptr, nullptr};
   bool f32 = false;
   size_t csize = 16;
@@ -131,7 +130,7 @@ struct aao_plan {
   unsigned long long* work() const { return reinterpret_cast<unsigned long long*>(ws + off_work); }
   double* gpart() const { return reinterpret_cast<double*>(ws + off_gpart); }
   double* npart() const { return reinterpret_cast<double*>(ws + off_npart); }
-  int* dlist() const { return reinterpret_cast<int*>(ws + off_list); }
+  int* dlist(int i = 2) const { return reinterpret_cast<int*>(ws + off_list) + (size_t)i * S; }
   double2* d_tw() const { return reinterpret_cast<double2*>(dtab + off_tw); }
   double* d_sf() const { return reinterpret_cast<double*>(dtab + off_sf); }
   double* d_sb() const { return reinterpret_cast<double*>(dtab + off_sb); }
@@ -342,39 +341,37 @@ aao::CgArgs cg_args(aao_plan* p, int adj, int nsys) {
 // earlier is inspected; the launch queue never drains on a host round trip.
 // Iterations launched after a system converged exit at once (its state says
 // inactive).  Returns the final states in p->hread + 128.
+// Lagged convergence checks: every few iterations a one-workgroup kernel
+// lists the still-active systems into one of two device buffers and writes
+// their count to pinned host memory behind an event; at the next check the
+// host waits for that event (one interval late, so the launch queue never
+// drains on a host round trip), switches the launches to that list and sizes
+// their grids by its count.  Iterations launched after a system converged
+// exit at once (its state says inactive).
 struct LagCheck {
   aao_plan* p;
   int nsys;
   hipEvent_t ev[2] = {nullptr, nullptr};
   int pending = -1, cur = 0;
-  aao::SysState* buf(int i) const {
-    return reinterpret_cast<aao::SysState*>(p->hstate + (size_t)i * p->S * sizeof(aao::SysState));
-  }
 };
 
-// Enqueue a state copy; if an earlier one is outstanding, wait for it and
-// return the number of systems still active in it (else -1).  Active systems
-// are listed in p->hlist[cur] and uploaded when the set shrank.
-aao_status lag_check(LagCheck& c, int& nact, int& n_out, bool final_check) {
+// Start a new snapshot; if an earlier one is outstanding, wait for it first
+// and make its list current (n_out = its count, else -1).
+aao_status lag_check(LagCheck& c, int& nact, const int*& list, int& n_out, bool final_check) {
   aao_plan* p = c.p;
   n_out = -1;
   if (c.pending >= 0) {
     HIPCHK(hipEventSynchronize(c.ev[c.pending]));
-    const aao::SysState* hs = c.buf(c.pending);
-    int* lst = p->hlist + (size_t)c.pending * p->S;
-    int n = 0;
-    for (int i = 0; i < c.nsys; ++i)
-      if (hs[i].active) lst[n++] = i;
+    const int n = p->hlist[c.pending];
     n_out = n;
-    c.pending = -1;
-    if (n > 0 && n < nact) {
-      HIPCHK(hipMemcpyAsync(p->dlist(), lst, (size_t)n * sizeof(int), hipMemcpyHostToDevice, p->stream));
+    if (n > 0) {
+      list = p->dlist(c.pending);
       nact = n;
     }
+    c.pending = -1;
     if (n == 0 || final_check) return AAO_OK;
   }
-  HIPCHK(hipMemcpyAsync(c.buf(c.cur), p->st(), (size_t)c.nsys * sizeof(aao::SysState), hipMemcpyDeviceToHost,
-                        p->stream));
+  HIPCHK(aao::launch_compact_active(p->st(), c.nsys, p->dlist(c.cur), p->hlist + c.cur, p->stream));
   HIPCHK(hipEventRecord(c.ev[c.cur], p->stream));
   c.pending = c.cur;
   c.cur ^= 1;
@@ -395,10 +392,8 @@ aao_status lag_begin(aao_plan* p, LagCheck& c, int nsys) {
 aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
   aao::CgArgs a = cg_args(p, adj, nsys);
   aao::KrylovArgs ka = krylov_args(p, adj, nsys);
-  int* lst0 = p->hlist + (size_t)2 * p->S;
-  for (int i = 0; i < nsys; ++i) lst0[i] = i;
-  HIPCHK(hipMemcpyAsync(p->dlist(), lst0, (size_t)nsys * sizeof(int), hipMemcpyHostToDevice, p->stream));
-  HIPCHK(aao::launch_krylov_init(ka, p->stream));
+  HIPCHK(aao::launch_krylov_init(ka, p->stream));  // all active: the initial list is 0 .. nsys-1
+  HIPCHK(aao::launch_compact_active(p->st(), nsys, p->dlist(2), nullptr, p->stream));
   int nact = nsys;
   HIPCHK(timed(p, aao::KC_COCG_B, [&] { return aao::launch_cg_init(p->f32, a, nact, p->stream); }));
   if (!a.fused) HIPCHK(timed(p, aao::KC_MISC, [&] { return aao::launch_cg_scalars(a, -1, nact, p->stream); }));
@@ -416,14 +411,14 @@ aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
     if (k + 1 == next_check) {
       next_check += (k < 16) ? 4 : 8;
       int n;
-      aao_status s = lag_check(c, nact, n, false);
+      aao_status s = lag_check(c, nact, a.sys_list, n, false);
       if (s != AAO_OK) return s;
       if (n == 0) break;
     }
   }
-  if (c.pending >= 0) {  // drain the last outstanding copy
+  if (c.pending >= 0) {  // drain the last outstanding snapshot
     int n;
-    aao_status s = lag_check(c, nact, n, true);
+    aao_status s = lag_check(c, nact, a.sys_list, n, true);
     if (s != AAO_OK) return s;
   }
   return AAO_OK;
@@ -459,10 +454,8 @@ aao_status inner_solve(aao_plan* p, int adj, int nsys) {
   if (p->inner == AAO_INNER_COCG) return inner_solve_cg(p, adj, nsys);
   if (p->inner == AAO_INNER_FFT) return inner_solve_fft(p, adj, nsys);
   aao::KrylovArgs a = krylov_args(p, adj, nsys);
-  int* lst0 = p->hlist + (size_t)2 * p->S;
-  for (int i = 0; i < nsys; ++i) lst0[i] = i;
-  HIPCHK(hipMemcpyAsync(p->dlist(), lst0, (size_t)nsys * sizeof(int), hipMemcpyHostToDevice, p->stream));
   HIPCHK(aao::launch_krylov_init(a, p->stream));
+  HIPCHK(aao::launch_compact_active(p->st(), nsys, p->dlist(2), nullptr, p->stream));
   int nact = nsys;
   LagCheck c;
   aao_status ls = lag_begin(p, c, nsys);
@@ -477,14 +470,14 @@ aao_status inner_solve(aao_plan* p, int adj, int nsys) {
     if (k + 1 == next_check) {
       next_check += (k < 16) ? 4 : 8;
       int n;
-      aao_status s = lag_check(c, nact, n, false);
+      aao_status s = lag_check(c, nact, a.sys_list, n, false);
       if (s != AAO_OK) return s;
       if (n == 0) break;
     }
   }
   if (c.pending >= 0) {
     int n;
-    aao_status s = lag_check(c, nact, n, true);
+    aao_status s = lag_check(c, nact, a.sys_list, n, true);
     if (s != AAO_OK) return s;
   }
   return AAO_OK;
@@ -542,8 +535,7 @@ aao_status alloc_tables(aao_plan* p) {
   HIPCHK(hipMalloc(&p->dtab, p->tab_bytes));
   HIPCHK(hipHostMalloc(&p->htab, p->tab_bytes, hipHostMallocDefault));
   HIPCHK(hipHostMalloc(&p->hread, p->hread_bytes, hipHostMallocDefault));
-  HIPCHK(hipHostMalloc(&p->hlist, (size_t)3 * p->S * sizeof(int), hipHostMallocDefault));
-  HIPCHK(hipHostMalloc(&p->hstate, (size_t)2 * p->S * sizeof(aao::SysState), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc(&p->hlist, 64, hipHostMallocDefault));
   std::vector<double2> tw(p->L / 2 + 1);
   for (int k = 0; k < (int)tw.size(); ++k) {
     const double ang = -2.0 * M_PI * (double)k / (double)p->L;
@@ -802,8 +794,8 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   p->off_part = off;
   off = align256(off + std::max((size_t)aao::QP_COUNT * p->S * p->wps, (size_t)2 * 5 * p->S * p->cg_ntiles) *
                            sizeof(double));
-  p->off_list = off;
-  off = align256(off + (size_t)p->S * sizeof(int));
+  p->off_list = off;  // three lists of active systems (two alternating snapshots, the initial one)
+  off = align256(off + (size_t)3 * p->S * sizeof(int));
   p->off_st = off;
   off = align256(off + (size_t)p->S * sizeof(aao::SysState));
   p->off_fb = off;
@@ -1164,7 +1156,6 @@ void aao_destroy(aao_plan_t p) {
   if (p->htab) (void)hipHostFree(p->htab);
   if (p->hread) (void)hipHostFree(p->hread);
   if (p->hlist) (void)hipHostFree(p->hlist);
-  if (p->hstate) (void)hipHostFree(p->hstate);
   for (auto e : p->chk_ev)
     if (e) (void)hipEventDestroy(e);
   delete p;

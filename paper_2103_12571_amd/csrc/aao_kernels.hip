@@ -596,13 +596,28 @@ __global__ void k_krylov_init(SysState* st, int n) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_count_active(const SysState* st, int n, int* out) {
-  __shared__ double sh[4];
-  double c = 0;
-  for (int i = threadIdx.x; i < n; i += kBlock) c += st[i].active;
-  double v[1] = {c};
-  block_sum<1>(v, sh);
-  if (threadIdx.x == 0) out[0] = (int)v[0];
+// List the still-active systems among the first n, in index order (one
+// workgroup): thread t scans a contiguous chunk, a scan over the chunk counts
+// gives each thread its output offset.  The count goes to *count (may be host
+// memory, read after an event that follows this kernel) if count != nullptr.
+__global__ __launch_bounds__(kBlock) void k_compact_active(const SysState* st, int n, int* list, int* count) {
+  __shared__ int off[kBlock + 1];
+  const int t = threadIdx.x;
+  const int chunk = (n + kBlock - 1) / kBlock;
+  const int i0 = t * chunk, i1 = min(n, i0 + chunk);
+  int c = 0;
+  for (int i = i0; i < i1; ++i) c += st[i].active != 0;
+  off[t + 1] = c;
+  __syncthreads();
+  if (t == 0) {
+    off[0] = 0;
+    for (int j = 1; j <= kBlock; ++j) off[j] += off[j - 1];
+  }
+  __syncthreads();
+  int o = off[t];
+  for (int i = i0; i < i1; ++i)
+    if (st[i].active) list[o++] = i;
+  if (t == 0 && count) *count = off[kBlock];
 }
 
 template <typename V>
@@ -807,8 +822,8 @@ hipError_t launch_krylov_init(const KrylovArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_count_active(const SysState* st, int n, int* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_count_active, dim3(1), dim3(kBlock), 0, s, st, n, out);
+hipError_t launch_compact_active(const SysState* st, int n, int* list, int* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact_active, dim3(1), dim3(kBlock), 0, s, st, n, list, count);
   return hipGetLastError();
 }
 
