@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -90,7 +91,8 @@ struct aao_plan {
   int S = 0, wps = 1, chunk = 256, nvec = 0;
   int cgTX = 1, cgTY = 1, cg_ntx = 1, cg_nty = 1, cg_ntiles = 1, Rx = 0, Ry = 0;
   int fft_rows = 1, fft_cols = 1;
-  int* hlist = nullptr;      // pinned: counts of active systems written by the device (2 ints)
+  int* hlist = nullptr;      // pinned: (count, tag) of the active-system snapshots, per slot
+  int snap_tag = 0;          // tag of the latest snapshot
   hipEvent_t chk_ev[2] = {nullptr, nullptr};
   bool f32 = false;
   size_t csize = 16;
@@ -98,11 +100,16 @@ struct aao_plan {
   char* dtab = nullptr;
   size_t off_tw = 0, off_sf = 0, off_sb = 0, off_m1 = 0, off_m2 = 0, off_sh = 0, off_q = 0,
          off_wx = 0, off_wy = 0, off_hostend = 0, tab_bytes = 0;
-  char* htab = nullptr;      // pinned mirror of the alpha-dependent tables
+  char* htab = nullptr;      // pinned mirror of the alpha-dependent tables (two slots)
   char* hread = nullptr;     // pinned readback area
   size_t hread_bytes = 0;
-  double cached_alpha = -1;
-  int cached_adj = -1;
+  // two slots of alpha-dependent tables: the sweep in flight reads one while
+  // the next sweep's tables are built and uploaded into the other
+  size_t atab_stride = 0;  // bytes of one slot (sf .. sh)
+  int cur_slot = 0;
+  double slot_alpha[2] = {-1, -1};
+  int slot_adj[2] = {-1, -1};
+  hipEvent_t slot_ev[2] = {nullptr, nullptr};  // recorded after each slot's upload
   // caller workspace
   char* ws = nullptr;
   size_t ws_bytes = 0, ws_need = 0;
@@ -132,11 +139,11 @@ struct aao_plan {
   double* npart() const { return reinterpret_cast<double*>(ws + off_npart); }
   int* dlist(int i = 2) const { return reinterpret_cast<int*>(ws + off_list) + (size_t)i * S; }
   double2* d_tw() const { return reinterpret_cast<double2*>(dtab + off_tw); }
-  double* d_sf() const { return reinterpret_cast<double*>(dtab + off_sf); }
-  double* d_sb() const { return reinterpret_cast<double*>(dtab + off_sb); }
-  double2* d_m1() const { return reinterpret_cast<double2*>(dtab + off_m1); }
-  double2* d_m2() const { return reinterpret_cast<double2*>(dtab + off_m2); }
-  double2* d_sh() const { return reinterpret_cast<double2*>(dtab + off_sh); }
+  double* d_sf() const { return reinterpret_cast<double*>(dtab + off_sf + (size_t)cur_slot * atab_stride); }
+  double* d_sb() const { return reinterpret_cast<double*>(dtab + off_sb + (size_t)cur_slot * atab_stride); }
+  double2* d_m1() const { return reinterpret_cast<double2*>(dtab + off_m1 + (size_t)cur_slot * atab_stride); }
+  double2* d_m2() const { return reinterpret_cast<double2*>(dtab + off_m2 + (size_t)cur_slot * atab_stride); }
+  double2* d_sh() const { return reinterpret_cast<double2*>(dtab + off_sh + (size_t)cur_slot * atab_stride); }
   double* d_q() const { return reinterpret_cast<double*>(dtab + off_q); }
   double2* d_wx() const { return reinterpret_cast<double2*>(dtab + off_wx); }
   double2* d_wy() const { return reinterpret_cast<double2*>(dtab + off_wy); }
@@ -186,16 +193,22 @@ void collect_timing(aao_plan* p) {
 // alpha-dependent tables for the primal (adj = 0) or transposed (adj = 1)
 // sweep: scale before/after the DFT over l, the node transforms of each
 // frequency and the shifts dT d_jm of the inner systems.
-aao_status upload_tables(aao_plan* p, double alpha, int adj) {
+// Build the tables of alpha into slot `slot` (host, pinned) and enqueue their
+// upload into the same device slot.  The host copy of a slot is rewritten
+// only after the stream has been synchronised since its last upload.
+aao_status build_tables(aao_plan* p, double alpha, int adj, int slot) {
   if (!(alpha > 0.0 && alpha < 1.0))
     return fail(AAO_EINVAL, "alpha must lie in (0, 1), got " + std::to_string(alpha));
-  if (alpha == p->cached_alpha && adj == p->cached_adj) return AAO_OK;
   const int M = p->M, L = p->L, Lh = p->Lh;
-  double* sf = reinterpret_cast<double*>(p->htab + (p->off_sf - p->off_sf));
-  double* sb = reinterpret_cast<double*>(p->htab + (p->off_sb - p->off_sf));
-  cd* m1 = reinterpret_cast<cd*>(p->htab + (p->off_m1 - p->off_sf));
-  cd* m2 = reinterpret_cast<cd*>(p->htab + (p->off_m2 - p->off_sf));
-  cd* sh = reinterpret_cast<cd*>(p->htab + (p->off_sh - p->off_sf));
+  if (!p->slot_ev[slot]) HIPCHK(hipEventCreateWithFlags(&p->slot_ev[slot], hipEventDisableTiming));
+  else HIPCHK(hipEventSynchronize(p->slot_ev[slot]));  // the slot's previous upload has been read
+  char* h = p->htab + (size_t)slot * p->atab_stride;
+  double* sf = reinterpret_cast<double*>(h + (p->off_sf - p->off_sf));
+  double* sb = reinterpret_cast<double*>(h + (p->off_sb - p->off_sf));
+  cd* m1 = reinterpret_cast<cd*>(h + (p->off_m1 - p->off_sf));
+  cd* m2 = reinterpret_cast<cd*>(h + (p->off_m2 - p->off_sf));
+  cd* sh = reinterpret_cast<cd*>(h + (p->off_sh - p->off_sf));
+  p->slot_alpha[slot] = -1;
   // Lemma 1: J^{-1} = diag(alpha^{(l-1)/L}) before the DFT, J and the 1/L of the
   // inverse DFT after it.  Transposed (V^T = (1/L) F J, V^{-T} = J^{-1} F^*):
   // J and 1/L before an inverse DFT, J^{-1} after a forward DFT.
@@ -230,11 +243,39 @@ aao_status upload_tables(aao_plan* p, double alpha, int adj) {
     for (int b = 0; b < p->B; ++b)
       for (int m = 0; m < M; ++m) sh[((size_t)b * Lh + j) * M + m] = p->dt * ft.lam[m];
   }
-  const size_t bytes = p->off_hostend - p->off_sf;
-  HIPCHK(hipMemcpyAsync(p->dtab + p->off_sf, p->htab, bytes, hipMemcpyHostToDevice, p->stream));
-  p->cached_alpha = alpha;
-  p->cached_adj = adj;
+  HIPCHK(hipMemcpyAsync(p->dtab + p->off_sf + (size_t)slot * p->atab_stride, h, p->atab_stride,
+                        hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipEventRecord(p->slot_ev[slot], p->stream));
+  p->slot_alpha[slot] = alpha;
+  p->slot_adj[slot] = adj;
   return AAO_OK;
+}
+
+int slot_of(const aao_plan* p, double alpha, int adj) {
+  for (int i = 0; i < 2; ++i)
+    if (p->slot_alpha[i] == alpha && p->slot_adj[i] == adj) return i;
+  return -1;
+}
+
+// Make the tables of alpha current (built into the other slot if neither
+// holds them).
+aao_status upload_tables(aao_plan* p, double alpha, int adj) {
+  int i = slot_of(p, alpha, adj);
+  if (i < 0) {
+    i = p->cur_slot ^ 1;
+    aao_status s = build_tables(p, alpha, adj, i);
+    if (s != AAO_OK) return s;
+  }
+  p->cur_slot = i;
+  return AAO_OK;
+}
+
+// Build the tables of the next sweep's alpha into the idle slot while the
+// current sweep runs (failures are left to the sweep that needs them).
+void prefetch_tables(aao_plan* p, double alpha, int adj) {
+  if (!(alpha > 0.0 && alpha < 1.0) || slot_of(p, alpha, adj) >= 0) return;
+  const std::string keep = g_err;
+  if (build_tables(p, alpha, adj, p->cur_slot ^ 1) != AAO_OK) g_err = keep;
 }
 
 aao::FwdArgs fwd_args(aao_plan* p, const double* in, int adj) {
@@ -352,6 +393,7 @@ struct LagCheck {
   aao_plan* p;
   int nsys;
   hipEvent_t ev[2] = {nullptr, nullptr};
+  int tag[2] = {0, 0};
   int pending = -1, cur = 0;
 };
 
@@ -362,7 +404,15 @@ aao_status lag_check(LagCheck& c, int& nact, const int*& list, int& n_out, bool 
   n_out = -1;
   if (c.pending >= 0) {
     HIPCHK(hipEventSynchronize(c.ev[c.pending]));
-    const int n = p->hlist[c.pending];
+    // the event carries no system-scope fence: the kernel's own fence orders
+    // count before tag, so wait (bounded) for this snapshot's tag
+    volatile int* ct = p->hlist + 2 * c.pending;
+    const auto t0 = std::chrono::steady_clock::now();
+    while (ct[1] != c.tag[c.pending]) {
+      if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(5))
+        return fail(AAO_EHIP, "active-system snapshot did not reach host memory");
+    }
+    const int n = ct[0];
     n_out = n;
     if (n > 0) {
       list = p->dlist(c.pending);
@@ -371,7 +421,9 @@ aao_status lag_check(LagCheck& c, int& nact, const int*& list, int& n_out, bool 
     c.pending = -1;
     if (n == 0 || final_check) return AAO_OK;
   }
-  HIPCHK(aao::launch_compact_active(p->st(), c.nsys, p->dlist(c.cur), p->hlist + c.cur, p->stream));
+  c.tag[c.cur] = ++p->snap_tag;
+  HIPCHK(aao::launch_compact_active(p->st(), c.nsys, p->dlist(c.cur), p->hlist + 2 * c.cur, c.tag[c.cur],
+                                    p->stream));
   HIPCHK(hipEventRecord(c.ev[c.cur], p->stream));
   c.pending = c.cur;
   c.cur ^= 1;
@@ -382,7 +434,8 @@ aao_status lag_begin(aao_plan* p, LagCheck& c, int nsys) {
   c.p = p;
   c.nsys = nsys;
   for (int i = 0; i < 2; ++i) {
-    if (!p->chk_ev[i]) HIPCHK(hipEventCreateWithFlags(&p->chk_ev[i], hipEventDisableTiming));
+    if (!p->chk_ev[i])
+      HIPCHK(hipEventCreateWithFlags(&p->chk_ev[i], hipEventDisableTiming | hipEventDisableSystemFence));
     c.ev[i] = p->chk_ev[i];
   }
   return AAO_OK;
@@ -393,7 +446,7 @@ aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
   aao::CgArgs a = cg_args(p, adj, nsys);
   aao::KrylovArgs ka = krylov_args(p, adj, nsys);
   HIPCHK(aao::launch_krylov_init(ka, p->stream));  // all active: the initial list is 0 .. nsys-1
-  HIPCHK(aao::launch_compact_active(p->st(), nsys, p->dlist(2), nullptr, p->stream));
+  HIPCHK(aao::launch_compact_active(p->st(), nsys, p->dlist(2), nullptr, 0, p->stream));
   int nact = nsys;
   HIPCHK(timed(p, aao::KC_COCG_B, [&] { return aao::launch_cg_init(p->f32, a, nact, p->stream); }));
   if (!a.fused) HIPCHK(timed(p, aao::KC_MISC, [&] { return aao::launch_cg_scalars(a, -1, nact, p->stream); }));
@@ -455,7 +508,7 @@ aao_status inner_solve(aao_plan* p, int adj, int nsys) {
   if (p->inner == AAO_INNER_FFT) return inner_solve_fft(p, adj, nsys);
   aao::KrylovArgs a = krylov_args(p, adj, nsys);
   HIPCHK(aao::launch_krylov_init(a, p->stream));
-  HIPCHK(aao::launch_compact_active(p->st(), nsys, p->dlist(2), nullptr, p->stream));
+  HIPCHK(aao::launch_compact_active(p->st(), nsys, p->dlist(2), nullptr, 0, p->stream));
   int nact = nsys;
   LagCheck c;
   aao_status ls = lag_begin(p, c, nsys);
@@ -533,9 +586,10 @@ aao_status read_back(aao_plan* p, int nsys, bool want_norms, SweepOut& o) {
 aao_status alloc_tables(aao_plan* p) {
   if (p->dtab) return AAO_OK;
   HIPCHK(hipMalloc(&p->dtab, p->tab_bytes));
-  HIPCHK(hipHostMalloc(&p->htab, p->tab_bytes, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc(&p->htab, 2 * p->atab_stride, hipHostMallocDefault));
   HIPCHK(hipHostMalloc(&p->hread, p->hread_bytes, hipHostMallocDefault));
   HIPCHK(hipHostMalloc(&p->hlist, 64, hipHostMallocDefault));
+  std::memset(p->hlist, 0, 64);  // tags start at 1
   std::vector<double2> tw(p->L / 2 + 1);
   for (int k = 0; k < (int)tw.size(); ++k) {
     const double ang = -2.0 * M_PI * (double)k / (double)p->L;
@@ -559,7 +613,7 @@ aao_status alloc_tables(aao_plan* p) {
   HIPCHK(hipMemcpyAsync(p->dtab + p->off_wx, wx.data(), wx.size() * sizeof(double2), hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipMemcpyAsync(p->dtab + p->off_wy, wy.data(), wy.size() * sizeof(double2), hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
-  p->cached_alpha = -1;
+  p->slot_alpha[0] = p->slot_alpha[1] = -1;
   return AAO_OK;
 }
 
@@ -571,7 +625,9 @@ aao_status need_ready(aao_plan* p, bool need_u0) {
 }
 
 // One sweep; res_stop > 0 stops before the update if ||r||/||w|| <= res_stop.
-aao_status do_sweep(aao_plan* p, double* u, double alpha, int adj, double res_stop,
+// One sweep with alpha; next_alpha > 0: the tables of the next sweep are
+// built while this one runs.
+aao_status do_sweep(aao_plan* p, double* u, double alpha, int adj, double res_stop, double next_alpha,
                     SweepOut& o, bool& stopped) {
   stopped = false;
   aao_status s = upload_tables(p, alpha, adj);
@@ -599,6 +655,7 @@ aao_status do_sweep(aao_plan* p, double* u, double alpha, int adj, double res_st
   HIPCHK(timed(p, aao::KC_MISC, [&] {
     return aao::launch_finalize(p->fb(), nt, p->fb() + p->fb_slots, nt, p->norms(), p->stream);
   }));
+  if (next_alpha > 0) prefetch_tables(p, next_alpha, adj);
   double keep = o.res2;
   s = read_back(p, p->S, true, o);
   if (s != AAO_OK) return s;
@@ -833,7 +890,8 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   p->off_sh = t;
   t = align256(t + (size_t)p->S * sizeof(double2));
   p->off_hostend = t;
-  p->tab_bytes = t;
+  p->atab_stride = p->off_hostend - p->off_sf;
+  p->tab_bytes = t + p->atab_stride;  // second slot of the alpha-dependent tables
   p->hread_bytes = 128 + (size_t)p->S * sizeof(aao::SysState) + 64;
   *out = p;
   return AAO_OK;
@@ -921,7 +979,7 @@ aao_status aao_sweep(aao_plan_t p, double* u, double alpha, double* res_rel, dou
   if (!u) return fail(AAO_EINVAL, "null u");
   SweepOut o;
   bool stopped;
-  s = do_sweep(p, u, alpha, 0, 0.0, o, stopped);
+  s = do_sweep(p, u, alpha, 0, 0.0, 0.0, o, stopped);
   if (s != AAO_OK) return s;
   if (res_rel) *res_rel = std::sqrt(o.res2) / std::sqrt(p->w2);
   if (dlast_inf) *dlast_inf = o.dmax;
@@ -945,31 +1003,47 @@ static aao_status run_solve(aao_plan_t p, double* u, const double* alphas, int n
   double m = m0 > 0 ? m0 : (adj ? wi : p->L * p->dt * p->Anorm_inf * p->winf);
   info->gamma = gamma;
   info->m0 = m;
-  for (int k = 0; k < max_iter; ++k) {
-    double alpha;
-    if (alphas) {
-      alpha = alphas[std::min(k, n_alphas - 1)];
-    } else if (p->f32) {
+  // alpha of sweep k and the error model after it (mm updated); the sequence
+  // depends on gamma and m0 only, so the next sweep's alpha is known while
+  // the current one runs.  done: Alg. 2's loop condition ended the iteration.
+  auto alpha_at = [&](int k, double& mm, bool& done) {
+    done = false;
+    if (alphas) return alphas[std::min(k, n_alphas - 1)];
+    if (p->f32) {
       // Complex64 inner solves: in the defect-correction form the error of a
       // sweep is relative to the current residual, m_{k+1} = alpha m_k +
       // (gamma_r / alpha) m_k with gamma_r = L (3 eps + tau); minimising over
       // alpha as in eq. (minimeq) gives the constant alpha = sqrt(gamma_r).
       const double gr = p->L * (3 * eps + p->inner_tol);
-      alpha = std::min(std::sqrt(gr), 0.5);
-      m = m * (alpha + gr / alpha);
-    } else {
-      if (m <= tol) {  // Alg. 2 loop condition: the error model is below tol
-        info->converged = 1;
-        return AAO_OK;
-      }
-      alpha = std::min(std::sqrt(gamma / m), 0.5);
-      m = 2 * std::sqrt(m * gamma);
+      const double a = std::min(std::sqrt(gr), 0.5);
+      mm = mm * (a + gr / a);
+      return a;
+    }
+    if (mm <= tol) {  // Alg. 2 loop condition: the error model is below tol
+      done = true;
+      return 0.0;
+    }
+    const double a = std::min(std::sqrt(gamma / mm), 0.5);
+    mm = 2 * std::sqrt(mm * gamma);
+    return a;
+  };
+  for (int k = 0; k < max_iter; ++k) {
+    bool done;
+    double alpha = alpha_at(k, m, done);
+    if (done) {
+      info->converged = 1;
+      return AAO_OK;
+    }
+    double m_next = m, next_alpha = 0.0;
+    if (k + 1 < max_iter) {
+      next_alpha = alpha_at(k + 1, m_next, done);
+      if (done) next_alpha = 0.0;
     }
     SweepOut o;
     bool stopped = false;
     aao_status s = AAO_ENODIAG;
     for (int tries = 0; tries < 6 && s == AAO_ENODIAG; ++tries) {
-      s = do_sweep(p, u, alpha, adj, stop_rule == AAO_STOP_RESIDUAL ? tol : 0.0, o, stopped);
+      s = do_sweep(p, u, alpha, adj, stop_rule == AAO_STOP_RESIDUAL ? tol : 0.0, next_alpha, o, stopped);
       if (s == AAO_ENODIAG && alphas) return s;
       if (s == AAO_ENODIAG) alpha = std::min(alpha * 1.05, 0.5);  // step off a non-diagonalisable alpha
     }
@@ -1055,10 +1129,11 @@ aao_status aao_shifted_solve(aao_plan_t p, int S, const double* shifts, const do
   if (s != AAO_OK) return s;
   if (S < 1 || S > p->S) return fail(AAO_EINVAL, "S must be in 1..B*(L/2+1)*M");
   if (!shifts || !b || !x) return fail(AAO_EINVAL, "null argument");
-  cd* sh = reinterpret_cast<cd*>(p->htab + (p->off_sh - p->off_sf));
+  HIPCHK(hipStreamSynchronize(p->stream));  // the host slot may still be in an upload
+  cd* sh = reinterpret_cast<cd*>(p->htab + (size_t)p->cur_slot * p->atab_stride + (p->off_sh - p->off_sf));
   for (int i = 0; i < S; ++i) sh[i] = cd(shifts[2 * i], shifts[2 * i + 1]);
   HIPCHK(hipMemcpyAsync(p->d_sh(), sh, (size_t)S * sizeof(double2), hipMemcpyHostToDevice, p->stream));
-  p->cached_alpha = -1;
+  p->slot_alpha[0] = p->slot_alpha[1] = -1;
   const int64_t n = (int64_t)S * p->N;
   HIPCHK(aao::launch_copy_c128_in(p->vec(1), p->f32, b, n, p->stream));
   s = inner_solve(p, 0, S);
@@ -1156,6 +1231,8 @@ void aao_destroy(aao_plan_t p) {
   if (p->htab) (void)hipHostFree(p->htab);
   if (p->hread) (void)hipHostFree(p->hread);
   if (p->hlist) (void)hipHostFree(p->hlist);
+  for (auto e : p->slot_ev)
+    if (e) (void)hipEventDestroy(e);
   for (auto e : p->chk_ev)
     if (e) (void)hipEventDestroy(e);
   delete p;

@@ -22,7 +22,9 @@ using namespace dev;
 // Forward transform with the fused all-at-once residual.
 // MODE 0: r = w - C u computed on the fly; MODE 1: r read from memory.
 // ADJ: residual of C^T (coupling from step l+1 into the last node, Q^T, A^T).
-template <int M, bool ADJ, int MODE, typename OutV>
+// NT > 0: the stencil has NT taps (unrolled, so all neighbour loads of a
+// point are in flight together).
+template <int M, bool ADJ, int MODE, typename OutV, int NT>
 __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
   extern __shared__ double lds[];
   const int TN = a.TN, P = TN >> 1, L = a.L, N = a.g.N;
@@ -64,11 +66,17 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
         double v[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) v[m] = 0.0;
-        for (int t = 0; t < a.taps.n; ++t) {
+        auto tap = [&](int t) {
           const int nb = wrap_index(x, y, a.taps.dx[t], a.taps.dy[t], a.g);
           const double ct = a.taps.c[t];
 #pragma unroll
           for (int m = 0; m < M; ++m) v[m] = fma(ct, ul[(size_t)m * N + nb], v[m]);
+        };
+        if (NT > 0) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) tap(t);
+        } else {
+          for (int t = 0; t < a.taps.n; ++t) tap(t);
         }
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -598,9 +606,11 @@ __global__ void k_krylov_init(SysState* st, int n) {
 
 // List the still-active systems among the first n, in index order (one
 // workgroup): thread t scans a contiguous chunk, a scan over the chunk counts
-// gives each thread its output offset.  The count goes to *count (may be host
-// memory, read after an event that follows this kernel) if count != nullptr.
-__global__ __launch_bounds__(kBlock) void k_compact_active(const SysState* st, int n, int* list, int* count) {
+// gives each thread its output offset.  If count_tag != nullptr (pinned host
+// memory) the count is stored to count_tag[0], then, after a system-scope
+// fence, tag to count_tag[1]: a reader that sees the tag sees the count.
+__global__ __launch_bounds__(kBlock) void k_compact_active(const SysState* st, int n, int* list, int* count_tag,
+                                                           int tag) {
   __shared__ int off[kBlock + 1];
   const int t = threadIdx.x;
   const int chunk = (n + kBlock - 1) / kBlock;
@@ -617,7 +627,11 @@ __global__ __launch_bounds__(kBlock) void k_compact_active(const SysState* st, i
   int o = off[t];
   for (int i = i0; i < i1; ++i)
     if (st[i].active) list[o++] = i;
-  if (t == 0 && count) *count = off[kBlock];
+  if (t == 0 && count_tag) {
+    count_tag[0] = off[kBlock];
+    __threadfence_system();
+    count_tag[1] = tag;
+  }
 }
 
 template <typename V>
@@ -703,14 +717,22 @@ template <int M>
 hipError_t fwd_m(bool adj, bool from_r, bool out_f32, const FwdArgs& a, int B, hipStream_t st) {
   dim3 grid((a.g.N + a.TN - 1) / a.TN, B);
   size_t lds = xform_lds_bytes(M, a.L, a.TN);
-#define AAO_FWD(ADJ, MODE, OV) hipLaunchKernelGGL((k_fwd<M, ADJ, MODE, OV>), grid, dim3(kBlock), lds, st, a)
+  const int nt = (a.taps.n == 3 || a.taps.n == 5) ? a.taps.n : 0;
+#define AAO_FWD(ADJ, MODE, OV, NT) hipLaunchKernelGGL((k_fwd<M, ADJ, MODE, OV, NT>), grid, dim3(kBlock), lds, st, a)
+#define AAO_FWD0(ADJ, OV)                \
+  do {                                   \
+    if (nt == 5) AAO_FWD(ADJ, 0, OV, 5); \
+    else if (nt == 3) AAO_FWD(ADJ, 0, OV, 3); \
+    else AAO_FWD(ADJ, 0, OV, 0);         \
+  } while (0)
   if (!adj) {
-    if (!from_r) { if (out_f32) AAO_FWD(false, 0, float2); else AAO_FWD(false, 0, double2); }
-    else { if (out_f32) AAO_FWD(false, 1, float2); else AAO_FWD(false, 1, double2); }
+    if (!from_r) { if (out_f32) AAO_FWD0(false, float2); else AAO_FWD0(false, double2); }
+    else { if (out_f32) AAO_FWD(false, 1, float2, 0); else AAO_FWD(false, 1, double2, 0); }
   } else {
-    if (!from_r) { if (out_f32) AAO_FWD(true, 0, float2); else AAO_FWD(true, 0, double2); }
-    else { if (out_f32) AAO_FWD(true, 1, float2); else AAO_FWD(true, 1, double2); }
+    if (!from_r) { if (out_f32) AAO_FWD0(true, float2); else AAO_FWD0(true, double2); }
+    else { if (out_f32) AAO_FWD(true, 1, float2, 0); else AAO_FWD(true, 1, double2, 0); }
   }
+#undef AAO_FWD0
 #undef AAO_FWD
   return hipGetLastError();
 }
@@ -822,8 +844,8 @@ hipError_t launch_krylov_init(const KrylovArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_compact_active(const SysState* st, int n, int* list, int* count, hipStream_t s) {
-  hipLaunchKernelGGL(k_compact_active, dim3(1), dim3(kBlock), 0, s, st, n, list, count);
+hipError_t launch_compact_active(const SysState* st, int n, int* list, int* count_tag, int tag, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact_active, dim3(1), dim3(kBlock), 0, s, st, n, list, count_tag, tag);
   return hipGetLastError();
 }
 

@@ -158,7 +158,7 @@ int cg_ring_slots(const CgArgs& a);
 hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, int nact, hipStream_t st);
 hipError_t launch_krylov_init(const KrylovArgs& a, hipStream_t st);
 hipError_t launch_fft_solve(bool f32, const FftArgs& a, int nsys, hipStream_t st);
-hipError_t launch_compact_active(const SysState* st, int n, int* list, int* count, hipStream_t s);
+hipError_t launch_compact_active(const SysState* st, int n, int* list, int* count_tag, int tag, hipStream_t s);
 hipError_t launch_copy_c128_in(void* dst, bool f32, const double* src, int64_t n, hipStream_t st);
 hipError_t launch_copy_c128_out(double* dst, const void* src, bool f32, int64_t n,
                                 hipStream_t st);
