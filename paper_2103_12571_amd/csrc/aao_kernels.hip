@@ -605,30 +605,41 @@ __global__ void k_krylov_init(SysState* st, int n) {
 }
 
 // List the still-active systems among the first n, in index order (one
-// workgroup): thread t scans a contiguous chunk, a scan over the chunk counts
-// gives each thread its output offset.  If count_tag != nullptr (pinned host
-// memory) the count is stored to count_tag[0], then, after a system-scope
-// fence, tag to count_tag[1]: a reader that sees the tag sees the count.
+// workgroup): in rounds of 64 systems per thread, each thread reads the flags
+// of its 64 once into a bit mask, a scan over the counts gives its output
+// offset.  Each flag is read once, so a pass running concurrently that clears
+// flags can only drop systems, never leave the list and its count
+// inconsistent.  If count_tag != nullptr (pinned host memory) the count is
+// stored to count_tag[0], then, after a system-scope fence, tag to
+// count_tag[1]: a reader that sees the tag sees the count.
 __global__ __launch_bounds__(kBlock) void k_compact_active(const SysState* st, int n, int* list, int* count_tag,
                                                            int tag) {
   __shared__ int off[kBlock + 1];
   const int t = threadIdx.x;
-  const int chunk = (n + kBlock - 1) / kBlock;
-  const int i0 = t * chunk, i1 = min(n, i0 + chunk);
-  int c = 0;
-  for (int i = i0; i < i1; ++i) c += st[i].active != 0;
-  off[t + 1] = c;
-  __syncthreads();
-  if (t == 0) {
-    off[0] = 0;
-    for (int j = 1; j <= kBlock; ++j) off[j] += off[j - 1];
+  int total = 0;
+  for (int base = 0; base < n; base += kBlock * 64) {
+    const int i0 = base + t * 64, i1 = min(n, i0 + 64);
+    unsigned long long mask = 0;
+    for (int i = i0; i < i1; ++i)
+      if (st[i].active) mask |= 1ull << (i - i0);
+    off[t + 1] = __popcll(mask);
+    __syncthreads();
+    if (t == 0) {
+      off[0] = total;
+      for (int j = 1; j <= kBlock; ++j) off[j] += off[j - 1];
+    }
+    __syncthreads();
+    int o = off[t];
+    while (mask) {
+      const int b = __ffsll((long long)mask) - 1;
+      list[o++] = i0 + b;
+      mask &= mask - 1;
+    }
+    total = off[kBlock];
+    __syncthreads();
   }
-  __syncthreads();
-  int o = off[t];
-  for (int i = i0; i < i1; ++i)
-    if (st[i].active) list[o++] = i;
   if (t == 0 && count_tag) {
-    count_tag[0] = off[kBlock];
+    count_tag[0] = total;
     __threadfence_system();
     count_tag[1] = tag;
   }
