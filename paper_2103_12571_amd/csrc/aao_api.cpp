@@ -124,6 +124,8 @@ struct aao_plan {
   aao_kernel_stats stats{};
   std::vector<Timed> pending;
   std::vector<hipEvent_t> pool;
+  int run_cls = -1;            // class of the open timing run (-1: none)
+  hipEvent_t run_a = nullptr;  // its start event
   // elements processed per kernel class (first iteration / later iterations),
   // from the per-system iteration counts read back after each inner solve
   double work_first[AAO_NUM_KERNELS] = {}, work_later[AAO_NUM_KERNELS] = {};
@@ -165,17 +167,35 @@ hipEvent_t get_event(aao_plan* p) {
   return e;
 }
 
+// Timing brackets runs of consecutive launches of one kernel class with one
+// pair of events (fewer event packets between kernels than one pair per
+// launch); any other work enqueued on the stream first closes the open run.
+void close_run(aao_plan* p) {
+  if (p->run_cls < 0) return;
+  hipEvent_t b = get_event(p);
+  if (b) {
+    (void)hipEventRecord(b, p->stream);
+    p->pending.push_back({p->run_cls, p->run_a, b});
+  } else {
+    p->pool.push_back(p->run_a);
+  }
+  p->run_cls = -1;
+  p->run_a = nullptr;
+}
+
 template <typename F>
 hipError_t timed(aao_plan* p, int cls, F&& launch) {
   p->stats.launches[cls] += 1;
   if (!p->timing) return launch();
-  hipEvent_t a = get_event(p), b = get_event(p);
-  if (!a || !b) return launch();
-  (void)hipEventRecord(a, p->stream);
-  hipError_t e = launch();
-  (void)hipEventRecord(b, p->stream);
-  p->pending.push_back({cls, a, b});
-  return e;
+  if (p->run_cls != cls) {
+    close_run(p);
+    hipEvent_t a = get_event(p);
+    if (!a) return launch();
+    (void)hipEventRecord(a, p->stream);
+    p->run_cls = cls;
+    p->run_a = a;
+  }
+  return launch();
 }
 
 // Call after the stream has been synchronised.
@@ -243,6 +263,7 @@ aao_status build_tables(aao_plan* p, double alpha, int adj, int slot) {
     for (int b = 0; b < p->B; ++b)
       for (int m = 0; m < M; ++m) sh[((size_t)b * Lh + j) * M + m] = p->dt * ft.lam[m];
   }
+  close_run(p);
   HIPCHK(hipMemcpyAsync(p->dtab + p->off_sf + (size_t)slot * p->atab_stride, h, p->atab_stride,
                         hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipEventRecord(p->slot_ev[slot], p->stream));
@@ -422,6 +443,7 @@ aao_status lag_check(LagCheck& c, int& nact, const int*& list, int& n_out, bool 
     if (n == 0 || final_check) return AAO_OK;
   }
   c.tag[c.cur] = ++p->snap_tag;
+  close_run(p);
   HIPCHK(aao::launch_compact_active(p->st(), c.nsys, p->dlist(c.cur), p->hlist + 2 * c.cur, c.tag[c.cur],
                                     p->stream));
   HIPCHK(hipEventRecord(c.ev[c.cur], p->stream));
@@ -445,7 +467,9 @@ aao_status lag_begin(aao_plan* p, LagCheck& c, int nsys) {
 aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
   aao::CgArgs a = cg_args(p, adj, nsys);
   aao::KrylovArgs ka = krylov_args(p, adj, nsys);
+  close_run(p);
   HIPCHK(aao::launch_krylov_init(ka, p->stream));  // all active: the initial list is 0 .. nsys-1
+  close_run(p);
   HIPCHK(aao::launch_compact_active(p->st(), nsys, p->dlist(2), nullptr, 0, p->stream));
   int nact = nsys;
   HIPCHK(timed(p, aao::KC_COCG_B, [&] { return aao::launch_cg_init(p->f32, a, nact, p->stream); }));
@@ -482,6 +506,7 @@ aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
 // Spatial-FFT direct solve of all nsys systems (exact; no iteration).
 aao_status inner_solve_fft(aao_plan* p, int adj, int nsys) {
   aao::KrylovArgs ka = krylov_args(p, adj, nsys);
+  close_run(p);
   HIPCHK(aao::launch_krylov_init(ka, p->stream));  // iteration counts read back as 0
   aao::FftArgs f{};
   f.R = p->vec(1);
@@ -507,7 +532,9 @@ aao_status inner_solve(aao_plan* p, int adj, int nsys) {
   if (p->inner == AAO_INNER_COCG) return inner_solve_cg(p, adj, nsys);
   if (p->inner == AAO_INNER_FFT) return inner_solve_fft(p, adj, nsys);
   aao::KrylovArgs a = krylov_args(p, adj, nsys);
+  close_run(p);
   HIPCHK(aao::launch_krylov_init(a, p->stream));
+  close_run(p);
   HIPCHK(aao::launch_compact_active(p->st(), nsys, p->dlist(2), nullptr, 0, p->stream));
   int nact = nsys;
   LagCheck c;
@@ -544,11 +571,14 @@ struct SweepOut {
 
 // Read norms and per-system Krylov statistics (synchronises the stream).
 aao_status read_back(aao_plan* p, int nsys, bool want_norms, SweepOut& o) {
+  close_run(p);
   double* hn = reinterpret_cast<double*>(p->hread + 64);
   aao::SysState* hs = reinterpret_cast<aao::SysState*>(p->hread + 128);
   if (want_norms) HIPCHK(hipMemcpyAsync(hn, p->norms(), 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   if (nsys > 0)
+    close_run(p);
     HIPCHK(hipMemcpyAsync(hs, p->st(), (size_t)nsys * sizeof(aao::SysState), hipMemcpyDeviceToHost, p->stream));
+  close_run(p);
   HIPCHK(hipStreamSynchronize(p->stream));
   collect_timing(p);
   if (want_norms) {
@@ -596,8 +626,10 @@ aao_status alloc_tables(aao_plan* p) {
     tw[k].x = std::cos(ang);
     tw[k].y = std::sin(ang);
   }
+  close_run(p);
   HIPCHK(hipMemcpyAsync(p->dtab + p->off_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice,
                         p->stream));
+  close_run(p);
   HIPCHK(hipMemcpyAsync(p->dtab + p->off_q, p->Q.data(), p->Q.size() * sizeof(double), hipMemcpyHostToDevice,
                         p->stream));
   // e^{+2 pi i k / n} for the spatial transforms of the FFT inner solve
@@ -610,8 +642,11 @@ aao_status alloc_tables(aao_plan* p) {
     wy[k].x = std::cos(2.0 * M_PI * k / p->ny);
     wy[k].y = std::sin(2.0 * M_PI * k / p->ny);
   }
+  close_run(p);
   HIPCHK(hipMemcpyAsync(p->dtab + p->off_wx, wx.data(), wx.size() * sizeof(double2), hipMemcpyHostToDevice, p->stream));
+  close_run(p);
   HIPCHK(hipMemcpyAsync(p->dtab + p->off_wy, wy.data(), wy.size() * sizeof(double2), hipMemcpyHostToDevice, p->stream));
+  close_run(p);
   HIPCHK(hipStreamSynchronize(p->stream));
   p->slot_alpha[0] = p->slot_alpha[1] = -1;
   return AAO_OK;
@@ -926,9 +961,12 @@ aao_status aao_set_u0(aao_plan_t p, const double* u0) {
   aao_status s = need_ready(p, false);
   if (s != AAO_OK) return s;
   if (!u0) return fail(AAO_EINVAL, "null u0");
+  close_run(p);
   HIPCHK(aao::launch_norms_bn(u0, p->B, p->N, p->npart(), kNormBlocks, p->stream));
   std::vector<double> h(2 * kNormBlocks);
+  close_run(p);
   HIPCHK(hipMemcpyAsync(h.data(), p->npart(), h.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  close_run(p);
   HIPCHK(hipStreamSynchronize(p->stream));
   double s2 = 0, mx = 0;
   for (int i = 0; i < kNormBlocks; ++i) {
@@ -949,6 +987,7 @@ aao_status aao_residual(aao_plan_t p, const double* u, double* r, double* res_no
   aao::FwdArgs fa = fwd_args(p, u, 0);
   const int nblk = std::min(1024, std::max(1, (int)(((int64_t)p->B * p->L * p->N + 255) / 256)));
   HIPCHK(timed(p, aao::KC_RESIDUAL, [&] { return aao::launch_residual(p->M, false, fa, r, p->B, p->stream); }));
+  close_run(p);
   HIPCHK(aao::launch_finalize(p->fb(), nblk, p->fb(), 0, p->norms(), p->stream));
   SweepOut o;
   s = read_back(p, 0, true, o);
@@ -1085,9 +1124,12 @@ aao_status aao_adjoint_solve(aao_plan_t p, const double* g_last, double* lam, co
   aao_status s = need_ready(p, false);
   if (s != AAO_OK) return s;
   if (!g_last || !lam) return fail(AAO_EINVAL, "null array");
+  close_run(p);
   HIPCHK(aao::launch_norms_bn(g_last, p->B, p->N, p->npart(), kNormBlocks, p->stream));
   std::vector<double> h(2 * kNormBlocks);
+  close_run(p);
   HIPCHK(hipMemcpyAsync(h.data(), p->npart(), h.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  close_run(p);
   HIPCHK(hipStreamSynchronize(p->stream));
   double gi = 0, g2 = 0;
   for (int i = 0; i < kNormBlocks; ++i) {
@@ -1118,7 +1160,9 @@ aao_status aao_grad(aao_plan_t p, const double* u, const double* lam, double* gu
     return aao::launch_grad(p->M, u, lam, gu0, p->gpart(), p->dtaps, p->d_q(), p->dt, g, p->B, p->L,
                             p->grad_blocks, p->stream);
   }));
+  close_run(p);
   HIPCHK(aao::launch_grad_finalize(p->gpart(), p->grad_blocks, p->B, gnu, p->stream));
+  close_run(p);
   HIPCHK(hipStreamSynchronize(p->stream));
   collect_timing(p);
   return AAO_OK;
@@ -1129,15 +1173,19 @@ aao_status aao_shifted_solve(aao_plan_t p, int S, const double* shifts, const do
   if (s != AAO_OK) return s;
   if (S < 1 || S > p->S) return fail(AAO_EINVAL, "S must be in 1..B*(L/2+1)*M");
   if (!shifts || !b || !x) return fail(AAO_EINVAL, "null argument");
+  close_run(p);
   HIPCHK(hipStreamSynchronize(p->stream));  // the host slot may still be in an upload
   cd* sh = reinterpret_cast<cd*>(p->htab + (size_t)p->cur_slot * p->atab_stride + (p->off_sh - p->off_sf));
   for (int i = 0; i < S; ++i) sh[i] = cd(shifts[2 * i], shifts[2 * i + 1]);
+  close_run(p);
   HIPCHK(hipMemcpyAsync(p->d_sh(), sh, (size_t)S * sizeof(double2), hipMemcpyHostToDevice, p->stream));
   p->slot_alpha[0] = p->slot_alpha[1] = -1;
   const int64_t n = (int64_t)S * p->N;
+  close_run(p);
   HIPCHK(aao::launch_copy_c128_in(p->vec(1), p->f32, b, n, p->stream));
   s = inner_solve(p, 0, S);
   if (s != AAO_OK) return s;
+  close_run(p);
   HIPCHK(aao::launch_copy_c128_out(x, p->vec(0), p->f32, n, p->stream));
   SweepOut o;
   s = read_back(p, S, false, o);
@@ -1151,6 +1199,7 @@ aao_status aao_shifted_solve(aao_plan_t p, int S, const double* shifts, const do
 
 aao_status aao_set_timing(aao_plan_t p, int on) {
   if (!p) return fail(AAO_EINVAL, "null plan");
+  close_run(p);
   p->timing = on != 0;
   return AAO_OK;
 }
@@ -1227,6 +1276,7 @@ void aao_destroy(aao_plan_t p) {
     (void)hipEventDestroy(t.b);
   }
   for (auto e : p->pool) (void)hipEventDestroy(e);
+  if (p->run_a) (void)hipEventDestroy(p->run_a);
   if (p->dtab) (void)hipFree(p->dtab);
   if (p->htab) (void)hipHostFree(p->htab);
   if (p->hread) (void)hipHostFree(p->hread);
