@@ -605,37 +605,27 @@ __global__ void k_krylov_init(SysState* st, int n) {
 }
 
 // List the still-active systems among the first n, in index order (one
-// workgroup): in rounds of 64 systems per thread, each thread reads the flags
-// of its 64 once into a bit mask, a scan over the counts gives its output
-// offset.  Each flag is read once, so a pass running concurrently that clears
-// flags can only drop systems, never leave the list and its count
-// inconsistent.  If count_tag != nullptr (pinned host memory) the count is
-// stored to count_tag[0], then, after a system-scope fence, tag to
-// count_tag[1]: a reader that sees the tag sees the count.
+// workgroup): in rounds of 256 systems each thread reads one flag, a ballot
+// per wavefront and the four wavefront counts give each listed system its
+// position.  Each flag is read once, so the list always matches its count.
+// If count_tag != nullptr (pinned host memory) the count is stored to
+// count_tag[0], then, after a system-scope fence, tag to count_tag[1]: a
+// reader that sees the tag sees the count.
 __global__ __launch_bounds__(kBlock) void k_compact_active(const SysState* st, int n, int* list, int* count_tag,
                                                            int tag) {
-  __shared__ int off[kBlock + 1];
-  const int t = threadIdx.x;
+  __shared__ int wcnt[kBlock / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   int total = 0;
-  for (int base = 0; base < n; base += kBlock * 64) {
-    const int i0 = base + t * 64, i1 = min(n, i0 + 64);
-    unsigned long long mask = 0;
-    for (int i = i0; i < i1; ++i)
-      if (st[i].active) mask |= 1ull << (i - i0);
-    off[t + 1] = __popcll(mask);
+  for (int base = 0; base < n; base += kBlock) {
+    const int i = base + t;
+    const bool act = i < n && st[i].active != 0;
+    const unsigned long long bal = __ballot(act);
+    if (lane == 0) wcnt[w] = __popcll(bal);
     __syncthreads();
-    if (t == 0) {
-      off[0] = total;
-      for (int j = 1; j <= kBlock; ++j) off[j] += off[j - 1];
-    }
-    __syncthreads();
-    int o = off[t];
-    while (mask) {
-      const int b = __ffsll((long long)mask) - 1;
-      list[o++] = i0 + b;
-      mask &= mask - 1;
-    }
-    total = off[kBlock];
+    int o = total;
+    for (int j = 0; j < w; ++j) o += wcnt[j];
+    if (act) list[o + __popcll(bal & ((1ull << lane) - 1))] = i;
+    total += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
     __syncthreads();
   }
   if (t == 0 && count_tag) {
