@@ -151,6 +151,14 @@ aao_status aao_workspace_size(aao_plan_t plan, size_t* bytes);
  * caller keeps ownership and must keep it alive while the plan uses it. */
 aao_status aao_set_workspace(aao_plan_t plan, void* dev_ptr, size_t bytes);
 
+/* Replace the stencil weights of A (ntaps host doubles, same offsets as at
+ * setup), e.g. a new diffusion coefficient nu, without re-planning (Sec. 2.1:
+ * A enters the sweep only through C_coll = I - dT Q (x) A).  dcoef_dnu
+ * (nullable) replaces dA/dnu for aao_grad.  Launches enqueued earlier keep the
+ * old weights.  AAO_EINVAL for null or non-finite input, or for weights that
+ * make A non-symmetric when the inner solver is COCG (nothing is changed). */
+aao_status aao_set_stencil_coef(aao_plan_t plan, const double* coef, const double* dcoef_dnu);
+
 /* Set the initial value u0_dev [B][N]; defines w = (1_M (x) u0, 0, ..., 0)
  * (eq. (globalsys) with b = 0).  The pointer is kept (not copied): u0 must stay
  * valid and unchanged while the plan uses it. */

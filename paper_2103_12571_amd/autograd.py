@@ -7,20 +7,25 @@ dJ/du0 = sum_m lambda_{1,m} and dJ/dnu = dT sum_l lambda_l^T (Q (x) dA/dnu) U_l.
 """
 import torch
 
-from .stencil import plan_for
+from .stencil import plan_for, taps_for
 
 _PLANS = {}
 
 
 def _plan(workload, nu):
-    key = (workload, float(nu))
+    """One plan per workload shape; nu only changes the stencil weights
+    (aao_set_stencil_coef), so a new nu does not re-plan."""
+    key = workload.with_(nu=0.0)
     p = _PLANS.get(key)
     if p is None:
         if len(_PLANS) > 8:
             _PLANS.clear()
         p = plan_for(workload.with_(nu=float(nu)))
         _PLANS[key] = p
-    return p
+    w = workload
+    _, _, coef, dcoef = taps_for(w.kind, w.nx, w.ny, nu=float(nu), vel=w.vel)
+    p.set_stencil_coef(coef, dcoef)
+    return p, coef, dcoef
 
 
 class AAOSolve(torch.autograd.Function):
@@ -28,11 +33,12 @@ class AAOSolve(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, u0, nu, workload, tol, adj_tol, max_iter):
-        plan = _plan(workload, nu.item())
+        plan, coef, dcoef = _plan(workload, nu.item())
         plan.set_u0(u0.detach())
         u, info = plan.solve(tol=tol, stop=workload.stop, max_iter=max_iter,
                              alphas=[workload.alpha] if workload.alpha > 0 else None)
         ctx.plan = plan
+        ctx.coef, ctx.dcoef = coef, dcoef
         ctx.u = u
         ctx.adj_tol = adj_tol
         ctx.max_iter = max_iter
@@ -43,6 +49,7 @@ class AAOSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         plan = ctx.plan
+        plan.set_stencil_coef(ctx.coef, ctx.dcoef)  # another forward may have changed nu
         lam, _ = plan.adjoint_solve(g.detach().to(torch.float64).contiguous(), tol=ctx.adj_tol,
                                     max_iter=ctx.max_iter)
         gu0, gnu = plan.grad(ctx.u, lam)

@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "AAO_OK", -1: "AAO_EINVAL", -2: "AAO_EHIP", -3: "AAO_ENODIAG"
                 -5: "AAO_ESTAGNATE", -6: "AAO_EWORKSPACE", -7: "AAO_ENAN", -8: "AAO_ESTATE"}
 
 EXPORTS = ["aao_setup", "aao_set_stream", "aao_workspace_size", "aao_set_workspace", "aao_set_u0",
+           "aao_set_stencil_coef",
            "aao_residual", "aao_precond", "aao_sweep", "aao_solve", "aao_adjoint_solve", "aao_grad",
            "aao_shifted_solve", "aao_set_timing", "aao_get_stats", "aao_reset_stats", "aao_kernel_name",
            "aao_tables", "aao_collocation", "aao_last_error", "aao_destroy"]
@@ -85,6 +86,7 @@ def lib():
         "aao_workspace_size": [P, C.POINTER(C.c_size_t)],
         "aao_set_workspace": [P, P, C.c_size_t],
         "aao_set_u0": [P, P],
+        "aao_set_stencil_coef": [P, D, D],
         "aao_residual": [P, P, P, D],
         "aao_precond": [P, P, P, C.c_double],
         "aao_sweep": [P, P, C.c_double, D, D],
@@ -205,6 +207,20 @@ class Plan:
         return cplx(d), cplx(r), cplx(djm).reshape(Lh, self.M), cond.value
 
     # -- C-ABI calls
+    def set_stencil_coef(self, coef, dcoef=None):
+        """New stencil weights (same offsets), e.g. another nu, without re-planning."""
+        c = np.ascontiguousarray(coef, dtype=np.float64)
+        if c.shape != self._c.shape:
+            raise ValueError("expected %d weights" % self._c.size)
+        d = None if dcoef is None else np.ascontiguousarray(dcoef, dtype=np.float64)
+        if d is not None and d.shape != c.shape:
+            raise ValueError("dcoef must match coef")
+        self._sync_stream()
+        check(lib().aao_set_stencil_coef(self._h, _dptr(c), _dptr(d) if d is not None else None))
+        self._c = c
+        if d is not None:
+            self._dc = d
+
     def set_u0(self, u0):
         self._u0 = self._f64(u0, (self.B, self.N))
         self._sync_stream()

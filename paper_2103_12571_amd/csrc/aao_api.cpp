@@ -699,6 +699,20 @@ aao_status do_sweep(aao_plan* p, double* u, double alpha, int adj, double res_st
   return AAO_OK;
 }
 
+// A = A^T for a periodic stencil: the weight at offset d equals the weight at
+// -d (needed by COCG, where I - c A must be complex-symmetric).
+bool symmetric_taps(const aao::Taps& t) {
+  for (int i = 0; i < t.n; ++i) {
+    double c = 0, ci = 0;
+    for (int k = 0; k < t.n; ++k) {
+      if (t.dx[k] == -t.dx[i] && t.dy[k] == -t.dy[i]) c += t.c[k];
+      if (t.dx[k] == t.dx[i] && t.dy[k] == t.dy[i]) ci += t.c[k];
+    }
+    if (std::abs(c - ci) > 1e-14 * std::max(1.0, std::abs(ci))) return false;
+  }
+  return true;
+}
+
 aao_status fill_taps(aao::Taps& t, int n, const int32_t* dx, const int32_t* dy, const double* c, int ndim) {
   t.n = n;
   for (int i = 0; i < n; ++i) {
@@ -802,20 +816,7 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   fill_taps(p->tapsT, A->ntaps, rdx.data(), rdy.data(), A->coef, A->ndim);
   p->has_dnu = A->dcoef_dnu != nullptr;
   if (p->has_dnu) fill_taps(p->dtaps, A->ntaps, A->dx, A->dy, A->dcoef_dnu, A->ndim);
-  // symmetry of A (needed by COCG: I - c A complex-symmetric)
-  {
-    bool sym = true;
-    for (int i = 0; i < A->ntaps && sym; ++i) {
-      double c = 0;
-      for (int k = 0; k < A->ntaps; ++k)
-        if (p->taps.dx[k] == -p->taps.dx[i] && p->taps.dy[k] == -p->taps.dy[i]) c += p->taps.c[k];
-      double ci = 0;
-      for (int k = 0; k < A->ntaps; ++k)
-        if (p->taps.dx[k] == p->taps.dx[i] && p->taps.dy[k] == p->taps.dy[i]) ci += p->taps.c[k];
-      if (std::abs(c - ci) > 1e-14 * std::max(1.0, std::abs(ci))) sym = false;
-    }
-    p->symmetric = sym;
-  }
+  p->symmetric = symmetric_taps(p->taps);
   if (p->inner == AAO_INNER_COCG && !p->symmetric) {
     delete p;
     return fail(AAO_EINVAL, "COCG needs a symmetric stencil (A = A^T); use BiCGStab");
@@ -935,6 +936,36 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
 aao_status aao_set_stream(aao_plan_t p, void* s) {
   if (!p) return fail(AAO_EINVAL, "null plan");
   p->stream = reinterpret_cast<hipStream_t>(s);
+  return AAO_OK;
+}
+
+aao_status aao_set_stencil_coef(aao_plan_t p, const double* coef, const double* dcoef_dnu) {
+  if (!p || !coef) return fail(AAO_EINVAL, "null argument");
+  aao::Taps t = p->taps;
+  double an = 0;
+  for (int i = 0; i < t.n; ++i) {
+    if (!std::isfinite(coef[i]) || (dcoef_dnu && !std::isfinite(dcoef_dnu[i])))
+      return fail(AAO_EINVAL, "stencil coefficients must be finite");
+    t.c[i] = coef[i];
+    an += std::abs(coef[i]);
+  }
+  const bool sym = symmetric_taps(t);
+  if (p->inner == AAO_INNER_COCG && !sym)
+    return fail(AAO_EINVAL, "COCG needs a symmetric stencil (A = A^T); use BiCGStab");
+  // kernels take the taps by value: launches enqueued earlier keep the old ones
+  p->taps = t;
+  for (int i = 0; i < t.n; ++i) p->tapsT.c[i] = coef[i];
+  p->symmetric = sym;
+  p->Anorm_inf = an;
+  if (dcoef_dnu) {
+    for (int i = 0; i < t.n; ++i) {
+      p->dtaps.dx[i] = t.dx[i];
+      p->dtaps.dy[i] = t.dy[i];
+      p->dtaps.c[i] = dcoef_dnu[i];
+    }
+    p->dtaps.n = t.n;
+    p->has_dnu = true;
+  }
   return AAO_OK;
 }
 

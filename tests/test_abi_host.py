@@ -161,3 +161,23 @@ def test_nondiagonalisable_alpha_is_rejected():
     assert "diagonalisable" in bd.lib().aao_last_error().decode()
     assert _tables(h, a_star * 1.2, L, 2)[0] == bd.AAO_OK
     bd.lib().aao_destroy(h)
+
+
+def test_set_stencil_coef_checks():
+    lib = bd.lib()
+    s, h = _setup(kind="heat1d", nx=16, nu=0.1)
+    assert s == bd.AAO_OK
+    _, _, c2, d2 = taps_for("heat1d", 16, nu=0.3)
+    cp = np.ascontiguousarray(c2).ctypes.data_as(C.POINTER(C.c_double))
+    assert lib.aao_set_stencil_coef(h, cp, None) == bd.AAO_OK            # host-only, no GPU needed
+    assert lib.aao_set_stencil_coef(None, cp, None) == bd.AAO_EINVAL
+    assert lib.aao_set_stencil_coef(h, None, None) == bd.AAO_EINVAL
+    bad = np.array([1.0, float("nan"), 1.0])
+    assert lib.aao_set_stencil_coef(h, bad.ctypes.data_as(C.POINTER(C.c_double)), None) == bd.AAO_EINVAL
+    skew = np.array([1.0, 0.0, -1.0])                                     # A != A^T: refused under COCG
+    assert lib.aao_set_stencil_coef(h, skew.ctypes.data_as(C.POINTER(C.c_double)), None) == bd.AAO_EINVAL
+    assert "symmetric" in lib.aao_last_error().decode()
+    lib.aao_destroy(h)
+    s, h = _setup(kind="heat1d", nx=16, nu=0.1, inner=bd.AAO_INNER_BICGSTAB)
+    assert lib.aao_set_stencil_coef(h, skew.ctypes.data_as(C.POINTER(C.c_double)), None) == bd.AAO_OK
+    lib.aao_destroy(h)

@@ -74,3 +74,28 @@ def test_gradients_vs_oracle_and_fd(prec, tol):
     h = 1e-6 * w.nu
     fd = (J(w.nu + h) - J(w.nu - h)) / (2 * h)
     assert abs(gnu - fd) < 1e-5 * abs(fd)
+
+
+def test_set_stencil_coef_matches_fresh_plan():
+    """A plan moved to another nu by aao_set_stencil_coef solves like a plan
+    set up at that nu (same launches, same weights) and matches the oracle."""
+    need_gpu()
+    from paper_2103_12571_amd.stencil import taps_for
+    w0 = wl.WORKLOADS["advdiff2d_512_adj"].with_(nx=32, ny=16, L=8, batch=2, precision="fp64",
+                                                 inner_tol=1e-13, tol=1e-13)
+    w1 = w0.with_(nu=2.5e-2)
+    say("set_stencil_coef", w0.nu, "->", w1.nu)
+    u0 = wl.initial_batch(w0)
+    pa = plan_for(w0)
+    _, _, c1, d1 = taps_for(w1.kind, w1.nx, w1.ny, nu=w1.nu, vel=w1.vel)
+    pa.set_stencil_coef(c1, d1)
+    pa.set_u0(dev(u0))
+    ua, _ = pa.solve(tol=w1.tol, max_iter=40)
+    pb = plan_for(w1)
+    pb.set_u0(dev(u0))
+    ub, _ = pb.solve(tol=w1.tol, max_iter=40)
+    assert np.array_equal(host(ua), host(ub))
+    op, Q = _setup(w1)
+    for b in range(w1.batch):
+        ref = oracle.sequential_solve(op, Q, w1.dt, u0[b], w1.L, backend="spectral")
+        assert rel_l2(host(ua)[b], ref) < 1e-10
