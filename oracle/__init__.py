@@ -11,7 +11,10 @@ What it computes (Caklovic, Speck, Frank, arXiv 2103.12571):
 
 * Radau-right collocation nodes and the integration matrix Q (Sec. 2.1, eq.
   (collocation); node polynomial P_{M-1}+P_M, Sec. 2.3).
-* The composite collocation solution of C u = w, by sequential step-by-step
+* Periodic finite-difference operators, including central (order 2, 4, 6) and
+  upwind (order 1..5) differences from their moment conditions (Sec. 5).
+* The composite collocation solution of C u = w (with an optional source b(t)
+  at the collocation times), by sequential step-by-step
   collocation solves (Sec. 2.1, eq. (seq_collocation_problem)) with three
   interchangeable spatial back-ends (dense, sparse LU, per-Fourier-mode), and
   by brute force on the assembled all-at-once matrix (eq. (globalsys)).
@@ -26,7 +29,7 @@ the paper, except where a docstring says "parity unpinned".
 """
 
 from .collocation import radau_right_nodes, collocation_matrix, node_polynomial
-from .operators import PeriodicStencil, stencil_for
+from .operators import PeriodicStencil, stencil_for, fd_weights, central_d2, upwind_d1
 from .sequential import sequential_solve
 from .allatonce import (assemble_C, assemble_C_alpha, assemble_w, residual,
                         precond_solve, brute_force_solve)
@@ -35,7 +38,7 @@ from .alpha import alpha_schedule
 
 __all__ = [
     "radau_right_nodes", "collocation_matrix", "node_polynomial",
-    "PeriodicStencil", "stencil_for", "sequential_solve",
+    "PeriodicStencil", "stencil_for", "fd_weights", "central_d2", "upwind_d1", "sequential_solve",
     "assemble_C", "assemble_C_alpha", "assemble_w", "residual",
     "precond_solve", "brute_force_solve", "adjoint_solve", "gradients",
     "alpha_schedule",
