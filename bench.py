@@ -85,10 +85,16 @@ def run_solves(plan, u, w, n, timing):
 def oracle_solution(w, u0):
     import numpy as np
     import oracle
-    op = oracle.stencil_for(w.kind, w.nx, w.ny, nu=w.nu, c=w.vel)
-    Q = oracle.collocation_matrix(oracle.radau_right_nodes(w.M))
-    return np.stack([oracle.sequential_solve(op, Q, w.dt, u0[b], w.L, backend="spectral")
-                     for b in range(w.batch)])
+    from paper_2103_12571_amd import workloads as wl
+    op = oracle.stencil_for(w.kind, w.nx, w.ny, nu=w.nu, c=w.vel, order=w.order)
+    tau = oracle.radau_right_nodes(w.M)
+    Q = oracle.collocation_matrix(tau)
+    b = None
+    if w.source:
+        b = wl.source_values(w, w.t0 + (np.arange(w.L)[:, None] + tau[None, :]) * w.dt)
+    return np.stack([oracle.sequential_solve(op, Q, w.dt, u0[i], w.L, backend="spectral",
+                                             forcing=None if b is None else b[i])
+                     for i in range(w.batch)])
 
 
 def speedup_block(np, torch, wl, plan_for, with_oracle):
@@ -160,11 +166,19 @@ def all_configs(np, torch, wl, plan_for):
     """Every workload once: GPU time to solution (best of 2 after a warm-up),
     sweeps, error against the oracle, and the oracle's time."""
     out = {}
+    runs = []
     for name, w in wl.WORKLOADS.items():
+        runs.append((name, w))
+        pow2 = (w.nx & (w.nx - 1)) == 0 and (w.ny & (w.ny - 1)) == 0
+        if pow2 and w.inner != "fft":  # the spatial-FFT direct inner solve on the same problem
+            runs.append((name + "+fft", w.with_(inner="fft", inner_tol=1e-15 if w.precision == "fp64" else 1e-7)))
+    for name, w in runs:
         print("bench: config %s" % name, file=sys.stderr, flush=True)
         u0 = wl.initial_batch(w)
         plan = plan_for(w)
         plan.set_u0(torch.as_tensor(u0, device="cuda"))
+        if w.source:
+            plan.set_forcing(torch.as_tensor(wl.source_values(w, plan.node_times(w.t0)), device="cuda"))
         u = torch.empty(plan.shape, dtype=torch.float64, device="cuda")
         run_solves(plan, u, w, 1, False)
         best = None
@@ -178,6 +192,9 @@ def all_configs(np, torch, wl, plan_for):
                      "gpu_time_to_solution_s": best, "dof_sweeps_per_s": w.dof * sw / best,
                      "rel_l2_vs_oracle": float(np.linalg.norm(u.cpu().numpy() - ref) / np.linalg.norm(ref)),
                      "oracle_time_s": t_or, "speedup_vs_oracle": t_or / best}
+        if w.init in ("heat_exact", "adv_exact"):
+            out[name]["max_err_vs_exact"] = float(np.max(np.abs(u[0, -1, -1].cpu().numpy()
+                                                               - wl.exact_solution(w, w.t0 + w.L * w.dt))))
         del plan, u
         torch.cuda.empty_cache()
     return out

@@ -160,9 +160,16 @@ aao_status aao_set_workspace(aao_plan_t plan, void* dev_ptr, size_t bytes);
 aao_status aao_set_stencil_coef(aao_plan_t plan, const double* coef, const double* dcoef_dnu);
 
 /* Set the initial value u0_dev [B][N]; defines w = (1_M (x) u0, 0, ..., 0)
- * (eq. (globalsys) with b = 0).  The pointer is kept (not copied): u0 must stay
+ * (eq. (globalsys); plus the source term if aao_set_forcing gave one).  The pointer is kept (not copied): u0 must stay
  * valid and unchanged while the plan uses it. */
 aao_status aao_set_u0(aao_plan_t plan, const double* u0_dev);
+
+/* Source term of eq. (collocation): b_dev [B][L][M][N] holds b(t) at the
+ * collocation times t_{l-1} + tau_m dT of every step (device, caller-owned,
+ * kept like u0), so that w_l gains dT (Q (x) I) b_l; NULL removes it.  The
+ * transposed (adjoint) system is unaffected.  Recomputes ||w|| if u0 is set;
+ * AAO_ENAN if w is not finite (the previous source is kept). */
+aao_status aao_set_forcing(aao_plan_t plan, const double* b_dev);
 
 /* Row a1: r = w - C u (eq. (globalsys)), r_dev [B][L][M][N].  res_norm
  * (nullable host out) = ||r||_2 / ||w||_2. */

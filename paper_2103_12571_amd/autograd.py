@@ -23,7 +23,7 @@ def _plan(workload, nu):
         p = plan_for(workload.with_(nu=float(nu)))
         _PLANS[key] = p
     w = workload
-    _, _, coef, dcoef = taps_for(w.kind, w.nx, w.ny, nu=float(nu), vel=w.vel)
+    _, _, coef, dcoef = taps_for(w.kind, w.nx, w.ny, nu=float(nu), vel=w.vel, order=w.order)
     p.set_stencil_coef(coef, dcoef)
     return p, coef, dcoef
 

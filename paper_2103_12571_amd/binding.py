@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "AAO_OK", -1: "AAO_EINVAL", -2: "AAO_EHIP", -3: "AAO_ENODIAG"
                 -5: "AAO_ESTAGNATE", -6: "AAO_EWORKSPACE", -7: "AAO_ENAN", -8: "AAO_ESTATE"}
 
 EXPORTS = ["aao_setup", "aao_set_stream", "aao_workspace_size", "aao_set_workspace", "aao_set_u0",
-           "aao_set_stencil_coef",
+           "aao_set_stencil_coef", "aao_set_forcing",
            "aao_residual", "aao_precond", "aao_sweep", "aao_solve", "aao_adjoint_solve", "aao_grad",
            "aao_shifted_solve", "aao_set_timing", "aao_get_stats", "aao_reset_stats", "aao_kernel_name",
            "aao_tables", "aao_collocation", "aao_last_error", "aao_destroy"]
@@ -87,6 +87,7 @@ def lib():
         "aao_set_workspace": [P, P, C.c_size_t],
         "aao_set_u0": [P, P],
         "aao_set_stencil_coef": [P, D, D],
+        "aao_set_forcing": [P, P],
         "aao_residual": [P, P, P, D],
         "aao_precond": [P, P, P, C.c_double],
         "aao_sweep": [P, P, C.c_double, D, D],
@@ -169,6 +170,7 @@ class Plan:
             off = (-base) % 256
             check(lib().aao_set_workspace(self._h, C.c_void_p(base + off), size.value))
         self._u0 = None
+        self._frc = None
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -220,6 +222,23 @@ class Plan:
         self._c = c
         if d is not None:
             self._dc = d
+
+    def set_forcing(self, b):
+        """Source b at the collocation times, [B, L, M, N] (None removes it)."""
+        if b is None:
+            self._frc = None
+            self._sync_stream()
+            check(lib().aao_set_forcing(self._h, None))
+            return
+        frc = self._f64(self.torch.as_tensor(b), (self.B, self.L, self.M, self.N))
+        self._sync_stream()
+        check(lib().aao_set_forcing(self._h, _ptr(frc)))
+        self._frc = frc  # keep the device buffer alive while the plan uses it
+
+    def node_times(self, t0=0.0):
+        """Absolute collocation times t0 + (l + tau_m) dT, array [L, M]."""
+        tau, _ = self.collocation()
+        return t0 + (np.arange(self.L)[:, None] + np.asarray(tau)[None, :]) * self.dt
 
     def set_u0(self, u0):
         self._u0 = self._f64(u0, (self.B, self.N))

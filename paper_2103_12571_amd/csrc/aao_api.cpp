@@ -118,6 +118,7 @@ struct aao_plan {
   int fb_slots = 0, grad_blocks = 0;
   // state
   const double* u0 = nullptr;
+  const double* frc = nullptr;  // source at the collocation times [B][L][M][N] (caller-owned)
   double w2 = 0, winf = 0;
   // stats
   bool timing = false;
@@ -303,6 +304,7 @@ aao::FwdArgs fwd_args(aao_plan* p, const double* in, int adj) {
   aao::FwdArgs a{};
   a.u = in;
   a.w0 = p->u0;
+  a.frc = adj ? nullptr : p->frc;
   a.out = p->vec(1);  // the Krylov right-hand side / residual buffer R
   a.scale = p->d_sf();
   a.tw = p->d_tw();
@@ -988,26 +990,54 @@ aao_status aao_set_workspace(aao_plan_t p, void* dev, size_t bytes) {
   return AAO_OK;
 }
 
-aao_status aao_set_u0(aao_plan_t p, const double* u0) {
-  aao_status s = need_ready(p, false);
-  if (s != AAO_OK) return s;
-  if (!u0) return fail(AAO_EINVAL, "null u0");
+// ||w||_2^2 and ||w||_inf of the all-at-once right-hand side (Alg. 2 uses
+// ||w||_inf, the residual stop ||w||_2); w = (1_M (x) u0 + dT Q b_1, dT Q b_2, ...).
+static aao_status update_wnorms(aao_plan* p, const double* u0) {
   close_run(p);
-  HIPCHK(aao::launch_norms_bn(u0, p->B, p->N, p->npart(), kNormBlocks, p->stream));
+  if (p->frc) {
+    aao::FwdArgs fa = fwd_args(p, nullptr, 0);
+    fa.w0 = u0;
+    HIPCHK(aao::launch_wnorms(p->M, fa, p->B, p->npart(), kNormBlocks, p->stream));
+  } else {
+    HIPCHK(aao::launch_norms_bn(u0, p->B, p->N, p->npart(), kNormBlocks, p->stream));
+  }
   std::vector<double> h(2 * kNormBlocks);
-  close_run(p);
   HIPCHK(hipMemcpyAsync(h.data(), p->npart(), h.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  close_run(p);
   HIPCHK(hipStreamSynchronize(p->stream));
   double s2 = 0, mx = 0;
   for (int i = 0; i < kNormBlocks; ++i) {
     s2 += h[2 * i];
     mx = std::max(mx, h[2 * i + 1]);
   }
-  if (!std::isfinite(s2)) return fail(AAO_ENAN, "u0 contains NaN or Inf");
-  p->u0 = u0;
-  p->w2 = p->M * s2;  // ||w||_2^2 = M ||u0||^2
+  if (!std::isfinite(s2)) return fail(AAO_ENAN, p->frc ? "u0 or the source contains NaN or Inf"
+                                                       : "u0 contains NaN or Inf");
+  p->w2 = p->frc ? s2 : p->M * s2;  // without a source ||w||_2^2 = M ||u0||^2
   p->winf = mx;
+  return AAO_OK;
+}
+
+aao_status aao_set_u0(aao_plan_t p, const double* u0) {
+  aao_status s = need_ready(p, false);
+  if (s != AAO_OK) return s;
+  if (!u0) return fail(AAO_EINVAL, "null u0");
+  s = update_wnorms(p, u0);
+  if (s != AAO_OK) return s;
+  p->u0 = u0;
+  return AAO_OK;
+}
+
+aao_status aao_set_forcing(aao_plan_t p, const double* b) {
+  aao_status s = need_ready(p, false);
+  if (s != AAO_OK) return s;
+  const double* keep = p->frc;
+  p->frc = b;
+  if (p->u0) {
+    s = update_wnorms(p, p->u0);
+    if (s != AAO_OK) {
+      p->frc = keep;
+      return s;
+    }
+  }
   return AAO_OK;
 }
 

@@ -78,11 +78,14 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
         } else {
           for (int t = 0; t < a.taps.n; ++t) tap(t);
         }
+        double f[M];  // source at the collocation times (eq. (collocation): dT Q b_l)
+#pragma unroll
+        for (int m = 0; m < M; ++m) f[m] = (!ADJ && a.frc) ? a.frc[base + (size_t)m * N + n] : 0.0;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
           double s = 0.0;
 #pragma unroll
-          for (int k = 0; k < M; ++k) s = fma(a.q[m * M + k], v[k], s);
+          for (int k = 0; k < M; ++k) s = fma(a.q[m * M + k], v[k] + f[k], s);
           rv[m] = fma(a.dt, s, -ul[(size_t)m * N + n]);
         }
         if (!ADJ) {
@@ -185,11 +188,14 @@ __global__ __launch_bounds__(kBlock) void k_residual(FwdArgs a, double* r_out, i
 #pragma unroll
       for (int m = 0; m < M; ++m) v[m] = fma(a.taps.c[t], ul[(size_t)m * N + nb], v[m]);
     }
+    double f[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) f[m] = (!ADJ && a.frc) ? a.frc[base + (size_t)m * N + n] : 0.0;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       double s = 0.0;
 #pragma unroll
-      for (int k = 0; k < M; ++k) s = fma(a.q[m * M + k], v[k], s);
+      for (int k = 0; k < M; ++k) s = fma(a.q[m * M + k], v[k] + f[k], s);
       rv[m] = fma(a.dt, s, -ul[(size_t)m * N + n]);
     }
     if (!ADJ) {
@@ -350,6 +356,44 @@ __global__ __launch_bounds__(kBlock) void k_norms(const double* v, int64_t n, do
   mx = block_max(mx, sh);
   if (threadIdx.x == 0) {
     part[2 * blockIdx.x] = t[0];
+    part[2 * blockIdx.x + 1] = mx;
+  }
+}
+
+// ||w||^2 and max |w| of the all-at-once right-hand side w_{l,m} = [l = 0] u0 +
+// dT sum_k Q_mk b_{l,k} (eq. (collocation)) over a grid-stride share of
+// (b, l, n): part[2 blk], part[2 blk + 1].
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_wnorms(FwdArgs a, int B, double* part) {
+  __shared__ double sh[4];
+  const int L = a.L, N = a.g.N;
+  const size_t total = (size_t)B * L * N;
+  double s2 = 0.0, mx = 0.0;
+  for (size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x; idx < total; idx += (size_t)gridDim.x * kBlock) {
+    const int n = (int)(idx % N);
+    const size_t bl = idx / N;
+    const int l = (int)(bl % L);
+    const int b = (int)(bl / L);
+    const size_t base = ((size_t)b * L + l) * M * (size_t)N;
+    const double u0 = (l == 0) ? a.w0[(size_t)b * N + n] : 0.0;
+    double f[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) f[m] = a.frc ? a.frc[base + (size_t)m * N + n] : 0.0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) s = fma(a.q[m * M + k], f[k], s);
+      const double w = fma(a.dt, s, u0);
+      s2 = fma(w, w, s2);
+      mx = fmax(mx, fabs(w));
+    }
+  }
+  double v[1] = {s2};
+  block_sum<1>(v, sh);
+  mx = block_max(mx, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = v[0];
     part[2 * blockIdx.x + 1] = mx;
   }
 }
@@ -819,6 +863,26 @@ hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t st) {
 hipError_t launch_norms_bn(const double* v, int B, int N, double* part, int nparts, hipStream_t st) {
   hipLaunchKernelGGL(k_norms, dim3(nparts), dim3(kBlock), 0, st, v, (int64_t)B * N, part);
   return hipGetLastError();
+}
+
+template <int M>
+hipError_t wnorms_m(const FwdArgs& a, int B, double* part, int nparts, hipStream_t st) {
+  hipLaunchKernelGGL((k_wnorms<M>), dim3(nparts), dim3(kBlock), 0, st, a, B, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_wnorms(int M, const FwdArgs& a, int B, double* part, int nparts, hipStream_t st) {
+  switch (M) {
+    case 1: return wnorms_m<1>(a, B, part, nparts, st);
+    case 2: return wnorms_m<2>(a, B, part, nparts, st);
+    case 3: return wnorms_m<3>(a, B, part, nparts, st);
+    case 4: return wnorms_m<4>(a, B, part, nparts, st);
+    case 5: return wnorms_m<5>(a, B, part, nparts, st);
+    case 6: return wnorms_m<6>(a, B, part, nparts, st);
+    case 7: return wnorms_m<7>(a, B, part, nparts, st);
+    case 8: return wnorms_m<8>(a, B, part, nparts, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, int nact, hipStream_t st) {

@@ -69,6 +69,7 @@ struct CgArgs {
 struct FwdArgs {
   const double* u;      // u (or lambda) [B][L][M][N], or r when the input is a residual
   const double* w0;     // u0 [B][N] (primal) or g_last [B][N] (adjoint)
+  const double* frc;    // source b at the collocation times [B][L][M][N] or null (primal only)
   void* out;            // x1 [B][Lh][M][N] complex (double2 or float2)
   const double* scale;  // [L] scaling applied before the DFT over l
   const double2* tw;    // [L/2] e^{-2 pi i k / L}
@@ -150,6 +151,7 @@ hipError_t launch_init_u(double* u, const double* u0, int B, int L, int M, int N
 hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t st);
 hipError_t launch_norms_bn(const double* v, int B, int N, double* part, int nparts,
                            hipStream_t st);
+hipError_t launch_wnorms(int M, const FwdArgs& a, int B, double* part, int nparts, hipStream_t st);
 hipError_t launch_cg_init(bool f32, const CgArgs& a, int nact, hipStream_t st);
 hipError_t launch_cg_pass(bool f32, const CgArgs& a, int k, int nact, hipStream_t st);
 hipError_t launch_cg_scalars(const CgArgs& a, int k, int nact, hipStream_t st);

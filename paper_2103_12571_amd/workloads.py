@@ -16,7 +16,7 @@ import numpy as np
 @dataclass(frozen=True)
 class Workload:
     name: str
-    kind: str            # heat1d | heat2d | adv1d_c4 | advdiff2d
+    kind: str            # heat1d | heat2d | adv1d_c4 | advdiff2d | heat2d_central | adv2d_upwind
     nx: int
     ny: int
     L: int
@@ -25,7 +25,7 @@ class Workload:
     nu: float = 0.0
     vel: tuple = (0.0, 0.0)
     batch: int = 1
-    init: str = "modes"  # sine | modes | gauss
+    init: str = "modes"  # sine | modes | gauss | heat_exact | adv_exact
     alpha: float = 0.0   # fixed alpha (0 -> adaptive rule of Alg. 2)
     stop: str = "laststep"   # laststep | residual
     tol: float = 1e-12
@@ -34,6 +34,9 @@ class Workload:
     precision: str = "fp64"  # fp64 | mixed
     seed: int = 2103
     target_seed: int = 12103
+    order: int = 2           # order of the differences (heat2d_central, adv2d_upwind)
+    t0: float = 0.0          # initial time
+    source: str = ""         # "" (b = 0) | heat (the source of eq. (heat))
 
     @property
     def N(self):
@@ -62,6 +65,16 @@ WORKLOADS = {
     "heat2d_1024_mixed": Workload("heat2d_1024_mixed", "heat2d", 1024, 1024, 32, 3, 1e-3, nu=1e-2,
                                   init="modes", tol=1e-8, inner="cocg", precision="mixed",
                                   inner_tol=1e-6),
+    # The two problems of Sec. 5 with Table 1's middle column (tolerance 1e-9):
+    # eq. (heat) on [pi, pi + 0.1], 400^2 points, 4th-order central, M = 2,
+    # L = 32; eq. (advection) on [0, 1e-2], 350^2 points, 4th-order upwind,
+    # M = 2, L = 16.  Inner tolerances are tighter than the sequential ones of
+    # the table (the iteration's error floor scales with L tau / alpha).
+    "heat2d_table1": Workload("heat2d_table1", "heat2d_central", 400, 400, 32, 2, 0.1 / 32, nu=1.0,
+                              init="heat_exact", t0=np.pi, source="heat", order=4, tol=1e-11,
+                              inner="cocg", inner_tol=1e-12),
+    "adv2d_table1": Workload("adv2d_table1", "adv2d_upwind", 350, 350, 16, 2, 1e-2 / 16, vel=(1.0, 1.0),
+                             init="adv_exact", order=4, tol=1e-11, inner="bicgstab", inner_tol=1e-13),
     # 2D advection-diffusion nu=5e-3, v=(1, 0.5) on 512^2, L=64, B=8; adjoint.
     "advdiff2d_512_adj": Workload("advdiff2d_512_adj", "advdiff2d", 512, 512, 64, 3, 1e-3, nu=5e-3,
                                   vel=(1.0, 0.5), batch=8, init="modes", tol=1e-10,
@@ -110,7 +123,39 @@ def initial_condition(w, b=0):
         return np.exp(-(x - 0.5) ** 2 / (2 * 0.05 ** 2)) + 1e-3 * rng.standard_normal(w.nx)
     if w.init == "modes":
         return fourier_modes(w.nx, w.ny, w.seed + b)
+    if w.init in ("heat_exact", "adv_exact"):
+        return exact_solution(w, w.t0)
     raise ValueError(w.init)
+
+
+def _phi(w, shift=0.0):
+    x, y = grid(w)
+    X, Y = np.meshgrid(x, y)
+    return (np.sin(2.0 * np.pi * (X - shift)) * np.sin(2.0 * np.pi * (Y - shift))).reshape(-1)
+
+
+def exact_solution(w, t):
+    """u(t) of the Sec. 5 problems on the grid: eq. (advection) gives
+    sin(2 pi (x - t)) sin(2 pi (y - t)); the source printed in eq. (heat) is
+    solved by cos(t) sin(2 pi x) sin(2 pi y)."""
+    if w.init == "adv_exact":
+        return _phi(w, t)
+    if w.init == "heat_exact":
+        return np.cos(t) * _phi(w)
+    raise ValueError("no exact solution for %r" % w.init)
+
+
+def source_values(w, times):
+    """The source b(t, x) of the problem at the given absolute times
+    (array [L, M]), as [B, L, M, N]; zeros when the problem has none.
+    eq. (heat): b = sin(2 pi x) sin(2 pi y) (8 pi^2 cos t - sin t)."""
+    times = np.asarray(times, dtype=np.float64)
+    out = np.zeros((w.batch,) + times.shape + (w.N,))
+    if w.source == "heat":
+        out[:] = (8.0 * np.pi ** 2 * np.cos(times) - np.sin(times))[None, :, :, None] * _phi(w)[None, None, None, :]
+    elif w.source:
+        raise ValueError(w.source)
+    return out
 
 
 def initial_batch(w):

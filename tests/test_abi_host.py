@@ -181,3 +181,17 @@ def test_set_stencil_coef_checks():
     s, h = _setup(kind="heat1d", nx=16, nu=0.1, inner=bd.AAO_INNER_BICGSTAB)
     assert lib.aao_set_stencil_coef(h, skew.ctypes.data_as(C.POINTER(C.c_double)), None) == bd.AAO_OK
     lib.aao_destroy(h)
+
+
+@pytest.mark.parametrize("kind,order", [("heat2d_central", k) for k in (2, 4, 6)]
+                         + [("adv2d_upwind", k) for k in range(1, 6)])
+def test_test_problem_stencils_match_oracle(kind, order):
+    """The product's stencil taps of the Sec. 5 problems equal the oracle's
+    operators (weights derived independently from the moment conditions)."""
+    nx, ny = 12, 9
+    dx, dy, c, _ = taps_for(kind, nx, ny, nu=0.7, vel=(1.0, 1.0), order=order)
+    op = oracle.stencil_for(kind, nx, ny, nu=0.7, c=(1.0, 1.0), order=order)
+    mine = {(int(a), int(b)): v for a, b, v in zip(dx, dy, c)}
+    assert set(mine) == set(op.weights)
+    for k, v in op.weights.items():
+        assert abs(mine[k] - v) <= 1e-13 * max(1.0, abs(v)), (k, mine[k], v)

@@ -143,3 +143,30 @@ def test_advection_problem_upwind_order(order):
         errs.append(np.max(np.abs(U[-1, -1] - exact)))
     rate = np.log2(errs[0] / errs[1])
     assert rate > order - 0.4, (rate, errs)
+
+
+def _adv_run(n, order, M, L, T):
+    x = np.arange(n) / n
+    X, Y = np.meshgrid(x, x)
+    u0 = (np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y)).reshape(-1)
+    exact = (np.sin(2 * np.pi * (X - T)) * np.sin(2 * np.pi * (Y - T))).reshape(-1)
+    op = oracle.stencil_for("adv2d_upwind", n, n, c=(1.0, 1.0), order=order)
+    Q = oracle.collocation_matrix(oracle.radau_right_nodes(M))
+    U = oracle.sequential_solve(op, Q, T / L, u0, L, backend="spectral")
+    return np.max(np.abs(U[-1, -1] - exact))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("eq,tol,N,order,M,L", [
+    ("heat", 1e-5, 450, 2, 1, 32), ("heat", 1e-9, 400, 4, 2, 32), ("heat", 1e-12, 300, 6, 3, 16),
+    ("adv", 1e-5, 350, 2, 2, 8), ("adv", 1e-9, 350, 4, 2, 16), ("adv", 1e-12, 600, 5, 3, 32)])
+def test_table1_parameter_sets_reach_their_tolerance(eq, tol, N, order, M, L):
+    """Table 1: with N points per dimension, the sequential collocation
+    solution at T (heat T = 0.1 from t = pi, advection T = 1e-2) is within the
+    stated tolerance of the exact solution."""
+    if eq == "heat":
+        uT, phi = _heat_run(N, order, L, 0.1, M)
+        err = np.max(np.abs(uT - np.cos(np.pi + 0.1) * phi))
+    else:
+        err = _adv_run(N, order, M, L, 1e-2)
+    assert err < tol, err
