@@ -201,6 +201,20 @@ aao_status aao_sweep(aao_plan_t plan, double* u_dev, double alpha, double* res_r
 aao_status aao_solve(aao_plan_t plan, double* u_dev, const double* alphas, int n_alphas,
                      double m0, double tol, int stop_rule, int max_iter, aao_solve_info* info);
 
+/* Moving window (Sec. 5.2): n_windows consecutive blocks of L steps, each
+ * solved as by aao_solve (same alphas / m0 / tol / stop rule / max_iter),
+ * window k + 1 starting from the last node of window k's last step (copied
+ * on the device).  Window 0 starts from the u0 given to aao_set_u0.
+ * frc_all (nullable, device): the source of every window, [W][B][L][M][N]
+ * at each window's collocation times; NULL keeps the source of
+ * aao_set_forcing (if any) for every window.  u_dev ends as the last
+ * window's solution.  infos: n_windows entries (host).  Stops at the first
+ * window that fails (its status is returned); the plan's u0 and source are
+ * restored afterwards. */
+aao_status aao_solve_windows(aao_plan_t plan, double* u_dev, int n_windows, const double* frc_all,
+                             const double* alphas, int n_alphas, double m0, double tol, int stop_rule,
+                             int max_iter, aao_solve_info* infos);
+
 /* Adjoint: solve C^T lambda = g, g = e_{L,M} (x) g_last, by the same
  * alpha-circulant machinery transposed (E_alpha^T = V^{-T} D_alpha V^T, Lemma
  * 1 transposed): per sweep lambda <- lambda + C_alpha^{-T}(g - C^T lambda).

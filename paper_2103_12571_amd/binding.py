@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "AAO_OK", -1: "AAO_EINVAL", -2: "AAO_EHIP", -3: "AAO_ENODIAG"
                 -5: "AAO_ESTAGNATE", -6: "AAO_EWORKSPACE", -7: "AAO_ENAN", -8: "AAO_ESTATE"}
 
 EXPORTS = ["aao_setup", "aao_set_stream", "aao_workspace_size", "aao_set_workspace", "aao_set_u0",
-           "aao_set_stencil_coef", "aao_set_forcing",
+           "aao_set_stencil_coef", "aao_set_forcing", "aao_solve_windows",
            "aao_residual", "aao_precond", "aao_sweep", "aao_solve", "aao_adjoint_solve", "aao_grad",
            "aao_shifted_solve", "aao_set_timing", "aao_get_stats", "aao_reset_stats", "aao_kernel_name",
            "aao_tables", "aao_collocation", "aao_last_error", "aao_destroy"]
@@ -88,6 +88,8 @@ def lib():
         "aao_set_u0": [P, P],
         "aao_set_stencil_coef": [P, D, D],
         "aao_set_forcing": [P, P],
+        "aao_solve_windows": [P, P, C.c_int, P, D, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
+                              C.POINTER(aao_solve_info)],
         "aao_residual": [P, P, P, D],
         "aao_precond": [P, P, P, C.c_double],
         "aao_sweep": [P, P, C.c_double, D, D],
@@ -283,6 +285,30 @@ class Plan:
                 raise AAOError(s, "%s; history %s" % (lib().aao_last_error().decode(), info.as_dict()))
             check(s)
         return u, info.as_dict()
+
+    def solve_windows(self, n_windows, sources=None, u=None, alphas=None, m0=0.0, tol=1e-12, stop="laststep",
+                      max_iter=50):
+        """Moving window: n_windows blocks of L steps from the plan's u0;
+        sources [W, B, L, M, N] or None.  Returns (u of the last window, infos)."""
+        if u is None:
+            u = self.torch.empty(self.shape, dtype=self.torch.float64, device=self.device)
+        frc = None
+        if sources is not None:
+            frc = self.torch.as_tensor(sources).to(device=self.device, dtype=self.torch.float64).contiguous()
+            if tuple(frc.shape) != (n_windows,) + tuple(self.shape):
+                raise ValueError("sources must be [W, B, L, M, N]")
+        infos = (aao_solve_info * n_windows)()
+        al = None if alphas is None else np.ascontiguousarray(alphas, dtype=np.float64)
+        self._sync_stream()
+        s = lib().aao_solve_windows(self._h, _ptr(u), int(n_windows), _ptr(frc) if frc is not None else None,
+                                    _dptr(al) if al is not None else None, 0 if al is None else len(al),
+                                    float(m0), float(tol),
+                                    {"laststep": AAO_STOP_LASTSTEP, "residual": AAO_STOP_RESIDUAL}[stop],
+                                    int(max_iter), infos)
+        out = [infos[k].as_dict() for k in range(n_windows)]
+        if s != AAO_OK:
+            raise AAOError(s, "%s; histories %s" % (lib().aao_last_error().decode(), out))
+        return u, out
 
     def adjoint_solve(self, g_last, alphas=None, m0=0.0, tol=1e-12, max_iter=50):
         g = self._f64(g_last, (self.B, self.N))

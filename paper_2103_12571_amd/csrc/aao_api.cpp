@@ -114,7 +114,7 @@ struct aao_plan {
   char* ws = nullptr;
   size_t ws_bytes = 0, ws_need = 0;
   size_t off_vec = 0, off_part = 0, off_st = 0, off_fb = 0, off_norms = 0, off_cnt = 0,
-         off_work = 0, off_gpart = 0, off_npart = 0, off_list = 0;
+         off_work = 0, off_gpart = 0, off_npart = 0, off_list = 0, off_win = 0;
   int fb_slots = 0, grad_blocks = 0;
   // state
   const double* u0 = nullptr;
@@ -140,6 +140,7 @@ struct aao_plan {
   unsigned long long* work() const { return reinterpret_cast<unsigned long long*>(ws + off_work); }
   double* gpart() const { return reinterpret_cast<double*>(ws + off_gpart); }
   double* npart() const { return reinterpret_cast<double*>(ws + off_npart); }
+  double* win() const { return reinterpret_cast<double*>(ws + off_win); }  // [B][N] window initial value
   int* dlist(int i = 2) const { return reinterpret_cast<int*>(ws + off_list) + (size_t)i * S; }
   double2* d_tw() const { return reinterpret_cast<double2*>(dtab + off_tw); }
   double* d_sf() const { return reinterpret_cast<double*>(dtab + off_sf + (size_t)cur_slot * atab_stride); }
@@ -905,6 +906,8 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   off = align256(off + (size_t)p->B * p->grad_blocks * sizeof(double));
   p->off_npart = off;
   off = align256(off + 2 * kNormBlocks * sizeof(double));
+  p->off_win = off;
+  off = align256(off + (size_t)p->B * p->N * sizeof(double));
   p->ws_need = off;
 
   // library-owned tables
@@ -1178,6 +1181,41 @@ aao_status aao_solve(aao_plan_t p, double* u, const double* alphas, int n_alphas
   if (!u) return fail(AAO_EINVAL, "null u");
   HIPCHK(timed(p, aao::KC_INIT, [&] { return aao::launch_init_u(u, p->u0, p->B, p->L, p->M, p->N, p->stream); }));
   return run_solve(p, u, alphas, n_alphas, m0, tol, stop_rule, max_iter, info, 0, 0.0);
+}
+
+aao_status aao_solve_windows(aao_plan_t p, double* u, int n_windows, const double* frc_all, const double* alphas,
+                             int n_alphas, double m0, double tol, int stop_rule, int max_iter,
+                             aao_solve_info* infos) {
+  aao_status s = need_ready(p, true);
+  if (s != AAO_OK) return s;
+  if (!u || !infos) return fail(AAO_EINVAL, "null argument");
+  if (n_windows < 1) return fail(AAO_EINVAL, "n_windows must be >= 1");
+  const double* user_u0 = p->u0;
+  const double* user_frc = p->frc;
+  const size_t dofs = (size_t)p->B * p->L * p->M * p->N;
+  aao_status r = AAO_OK;
+  for (int k = 0; k < n_windows; ++k) {
+    if (frc_all) p->frc = frc_all + (size_t)k * dofs;
+    if (k > 0 || frc_all) {  // w changes with the window's initial value and source
+      r = update_wnorms(p, p->u0);
+      if (r != AAO_OK) break;
+    }
+    close_run(p);
+    HIPCHK(timed(p, aao::KC_INIT, [&] { return aao::launch_init_u(u, p->u0, p->B, p->L, p->M, p->N, p->stream); }));
+    r = run_solve(p, u, alphas, n_alphas, m0, tol, stop_rule, max_iter, infos + k, 0, 0.0);
+    if (r != AAO_OK) break;
+    if (k + 1 < n_windows) {
+      // the next window starts from the last node of this one's last step;
+      // the buffer is free again: this window's own u0 was last read above
+      close_run(p);
+      HIPCHK(aao::launch_last_node(u, p->win(), p->B, p->L, p->M, p->N, p->stream));
+      p->u0 = p->win();
+    }
+  }
+  p->u0 = user_u0;
+  p->frc = user_frc;
+  aao_status rs = update_wnorms(p, p->u0);
+  return r != AAO_OK ? r : rs;
 }
 
 aao_status aao_adjoint_solve(aao_plan_t p, const double* g_last, double* lam, const double* alphas,

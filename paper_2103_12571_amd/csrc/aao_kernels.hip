@@ -337,6 +337,16 @@ __global__ void k_init_u(double* u, const double* u0, int B, int L, int M, int N
   }
 }
 
+// out[b][n] = u[b][L-1][M-1][n]: the last node of the last step (the next
+// window's initial value).
+__global__ void k_last_node(const double* u, double* out, int B, int L, int M, int N) {
+  const size_t total = (size_t)B * N;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t b = i / N, n = i % N;
+    out[i] = u[((b * L + (L - 1)) * M + (M - 1)) * (size_t)N + n];
+  }
+}
+
 __global__ void k_fill(double* p, double v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -846,6 +856,11 @@ int residual_blocks(int B, int L, int N) { return grid_for((int64_t)B * L * N, k
 hipError_t launch_finalize(const double* ps, int ns, const double* pm, int nm, double* out,
                            hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, ps, ns, pm, nm, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_last_node(const double* u, double* out, int B, int L, int M, int N, hipStream_t st) {
+  hipLaunchKernelGGL(k_last_node, dim3(grid_for((int64_t)B * N)), dim3(kBlock), 0, st, u, out, B, L, M, N);
   return hipGetLastError();
 }
 

@@ -148,6 +148,7 @@ hipError_t launch_residual(int M, bool adj, const FwdArgs& a, double* r_out, int
 hipError_t launch_finalize(const double* part_sum, int n_sum, const double* part_max, int n_max,
                            double* out, hipStream_t st);
 hipError_t launch_init_u(double* u, const double* u0, int B, int L, int M, int N, hipStream_t st);
+hipError_t launch_last_node(const double* u, double* out, int B, int L, int M, int N, hipStream_t st);
 hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t st);
 hipError_t launch_norms_bn(const double* v, int B, int N, double* part, int nparts,
                            hipStream_t st);

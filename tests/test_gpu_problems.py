@@ -112,3 +112,41 @@ def test_table1_middle_column_reaches_tolerance(w, tol):
         "exact err %.2e" % err, "oracle err %.2e" % e)
     assert err < tol
     assert e < 1e-10
+
+
+def test_moving_window_equals_sequential():
+    """Four windows of L = 4 steps reproduce steps 13-16 of the sequential
+    collocation solution over 16 steps (Sec. 5.2's moving window)."""
+    need_gpu()
+    w = wl.WORKLOADS["heat2d_256"].with_(nx=24, ny=16, L=4, tol=1e-12, inner_tol=1e-13)
+    p = plan_for(w)
+    u0 = wl.initial_batch(w)
+    p.set_u0(dev(u0))
+    u, infos = p.solve_windows(4, tol=w.tol, max_iter=40)
+    say("windows", [i["iterations"] for i in infos])
+    op, Q, _ = _oracle(w, u0, None)
+    ref = oracle.sequential_solve(op, Q, w.dt, u0[0], 4 * w.L, backend="spectral")
+    assert rel_l2(host(u)[0], ref[-w.L:]) < 1e-10
+    # the plan's own u0 is restored: a plain solve starts from it again
+    u1, _ = p.solve(tol=w.tol, max_iter=40)
+    assert rel_l2(host(u1)[0], ref[:w.L]) < 1e-10
+
+
+def test_moving_window_table2_heat():
+    """Table 2, heat, tolerance 1e-9: 400^2 points, 4th order, M = 2,
+    T_64 = 0.16 over 64 steps, solved as 4 windows of L = 16 with the source
+    of each window; the result at T is within 1e-9 of the exact solution."""
+    need_gpu()
+    W, L = 4, 16
+    w = HEAT.with_(L=L, dt=0.16 / 64, inner_tol=1e-12, tol=1e-11)
+    p = plan_for(w)
+    u0 = wl.initial_batch(w)
+    p.set_u0(dev(u0))
+    tau = np.asarray(p.collocation()[0])
+    src = np.stack([wl.source_values(w, w.t0 + (k * L + np.arange(L)[:, None] + tau[None, :]) * w.dt)
+                    for k in range(W)])
+    u, infos = p.solve_windows(W, sources=dev(src), tol=w.tol, max_iter=40)
+    T = w.t0 + W * L * w.dt
+    err = np.max(np.abs(host(u)[0, -1, -1] - wl.exact_solution(w, T)))
+    say("table 2 heat windows", [i["iterations"] for i in infos], "exact err %.2e" % err)
+    assert err < 1e-9
