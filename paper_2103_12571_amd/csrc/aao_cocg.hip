@@ -191,6 +191,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   // the state is read with workgroup-uniform addresses (scalar loads)
   const SysState* st0 = a.st + s;
   const int act0 = st0->active;
+  // A system that stopped in an earlier pass can still be on the lagged
+  // list; it leaves before its vectors are requested (nothing below writes
+  // for it).  The flag is workgroup-uniform.
+  if (!act0) return;
   const double bb0 = a.fused ? st0->bb : 0.0;
   const double2 s0 = a.fused ? st0->gamma2[(k + 1) & 1] : st0->alpha;
   const double2 s1 = a.fused ? st0->alpha2[(k + 1) & 1] : st0->beta;
