@@ -50,6 +50,11 @@ int ilog2(int64_t v) {
 #ifndef AAO_CG_TY2D
 #define AAO_CG_TY2D 16
 #endif
+// small COCG tiles once few systems remain: used when (active systems) x
+// (large-tile count) is at most this many workgroups (0: never)
+#ifndef AAO_CG_SMALL_WG
+#define AAO_CG_SMALL_WG 256
+#endif
 #ifndef AAO_XCD_BANDS
 #define AAO_XCD_BANDS 1
 #endif
@@ -90,10 +95,10 @@ struct aao_plan {
   // inner solves
   int S = 0, wps = 1, chunk = 256, nvec = 0;
   int cgTX = 1, cgTY = 1, cg_ntx = 1, cg_nty = 1, cg_ntiles = 1, Rx = 0, Ry = 0;
+  int cgTXs = 0, cgTYs = 0, cg_ntxs = 0, cg_ntiles_s = 0;  // small tiling (cg_ntiles_s = 0: none)
   int fft_rows = 1, fft_cols = 1;
   int* hlist = nullptr;      // pinned: (count, tag) of the active-system snapshots, per slot
   int snap_tag = 0;          // tag of the latest snapshot
-  hipEvent_t chk_ev[2] = {nullptr, nullptr};
   bool f32 = false;
   size_t csize = 16;
   // library-owned device tables and pinned staging
@@ -367,6 +372,21 @@ aao::KrylovArgs krylov_args(aao_plan* p, int adj, int nsys) {
   return a;
 }
 
+// Tile fields of the COCG arguments: the large tiling, or the small one.
+void cg_tiling(aao::CgArgs& a, const aao_plan* p, bool small) {
+  a.TX = small ? p->cgTXs : p->cgTX;
+  a.TY = small ? p->cgTYs : p->cgTY;
+  a.ntx = small ? p->cg_ntxs : p->cg_ntx;
+  a.ntiles = small ? p->cg_ntiles_s : p->cg_ntiles;
+  a.nty = a.ntiles / a.ntx;
+  auto magic = [](int d) { return ((1ull << 40) + (unsigned long long)d - 1) / (unsigned long long)d; };
+  a.m_ntx = magic(a.ntx);
+  a.m_tx = magic(a.TX);
+  a.m_pw = magic(a.TX + 4 * a.Rx);
+  a.m_hw = a.Rx > 0 ? magic(4 * a.Rx) : 0;
+  a.xcd_band = (AAO_XCD_BANDS && a.ntiles % 8 == 0 && a.ntiles >= 16) ? a.ntiles / 8 : 0;
+}
+
 aao::CgArgs cg_args(aao_plan* p, int adj, int nsys) {
   aao::CgArgs a{};
   a.X = p->vec(0);
@@ -382,41 +402,28 @@ aao::CgArgs cg_args(aao_plan* p, int adj, int nsys) {
   a.g = {p->nx, p->ny, p->N};
   a.taps = adj ? p->tapsT : p->taps;
   a.num_sys = nsys;
-  a.TX = p->cgTX;
-  a.TY = p->cgTY;
-  a.ntx = p->cg_ntx;
-  a.nty = p->cg_nty;
-  a.ntiles = p->cg_ntiles;
   a.Rx = p->Rx;
   a.Ry = p->Ry;
-  auto magic = [](int d) { return ((1ull << 40) + (unsigned long long)d - 1) / (unsigned long long)d; };
-  a.m_ntx = magic(a.ntx);
-  a.m_tx = magic(a.TX);
-  a.m_pw = magic(a.TX + 4 * a.Rx);
-  a.m_hw = a.Rx > 0 ? magic(4 * a.Rx) : 0;
-  a.xcd_band = (AAO_XCD_BANDS && a.ntiles % 8 == 0 && a.ntiles >= 16) ? a.ntiles / 8 : 0;
+  cg_tiling(a, p, false);
   a.fused = a.ntiles <= 256 ? 1 : 0;
+  a.ntiles_prev = a.ntiles;
+  a.part_stride = (size_t)5 * nsys * std::max(p->cg_ntiles, p->cg_ntiles_s);
   a.tol2 = p->inner_tol * p->inner_tol;
   a.maxit = p->inner_maxit;
   return a;
 }
 
-// Lagged convergence checks: every few iterations the system states are
-// copied to pinned memory behind an event, and the copy made one interval
-// earlier is inspected; the launch queue never drains on a host round trip.
-// Iterations launched after a system converged exit at once (its state says
-// inactive).  Returns the final states in p->hread + 128.
 // Lagged convergence checks: every few iterations a one-workgroup kernel
 // lists the still-active systems into one of two device buffers and writes
-// their count to pinned host memory behind an event; at the next check the
-// host waits for that event (one interval late, so the launch queue never
-// drains on a host round trip), switches the launches to that list and sizes
-// their grids by its count.  Iterations launched after a system converged
-// exit at once (its state says inactive).
+// their count, then a tag, to pinned host memory (a system-scope fence between
+// the two).  At the next check the host waits for that tag (one interval
+// late, so the launch queue never drains on a host round trip), switches the
+// launches to that list and sizes their grids by its count.  No event is
+// recorded: a marker in the queue would hold back the next pass.  Passes
+// launched after a system converged exit at once (its state says inactive).
 struct LagCheck {
   aao_plan* p;
   int nsys;
-  hipEvent_t ev[2] = {nullptr, nullptr};
   int tag[2] = {0, 0};
   int pending = -1, cur = 0;
 };
@@ -427,9 +434,8 @@ aao_status lag_check(LagCheck& c, int& nact, const int*& list, int& n_out, bool 
   aao_plan* p = c.p;
   n_out = -1;
   if (c.pending >= 0) {
-    HIPCHK(hipEventSynchronize(c.ev[c.pending]));
-    // the event carries no system-scope fence: the kernel's own fence orders
-    // count before tag, so wait (bounded) for this snapshot's tag
+    // the kernel's own fence orders count before tag: wait (bounded) for
+    // this snapshot's tag
     volatile int* ct = p->hlist + 2 * c.pending;
     const auto t0 = std::chrono::steady_clock::now();
     while (ct[1] != c.tag[c.pending]) {
@@ -449,7 +455,6 @@ aao_status lag_check(LagCheck& c, int& nact, const int*& list, int& n_out, bool 
   close_run(p);
   HIPCHK(aao::launch_compact_active(p->st(), c.nsys, p->dlist(c.cur), p->hlist + 2 * c.cur, c.tag[c.cur],
                                     p->stream));
-  HIPCHK(hipEventRecord(c.ev[c.cur], p->stream));
   c.pending = c.cur;
   c.cur ^= 1;
   return AAO_OK;
@@ -458,11 +463,6 @@ aao_status lag_check(LagCheck& c, int& nact, const int*& list, int& n_out, bool 
 aao_status lag_begin(aao_plan* p, LagCheck& c, int nsys) {
   c.p = p;
   c.nsys = nsys;
-  for (int i = 0; i < 2; ++i) {
-    if (!p->chk_ev[i])
-      HIPCHK(hipEventCreateWithFlags(&p->chk_ev[i], hipEventDisableTiming | hipEventDisableSystemFence));
-    c.ev[i] = p->chk_ev[i];
-  }
   return AAO_OK;
 }
 
@@ -481,11 +481,13 @@ aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
   aao_status ls = lag_begin(p, c, nsys);
   if (ls != AAO_OK) return ls;
   int next_check = 4;
+  bool small = false;
   // fused: pass k advances the scalars from pass k-1's sums (pass inner_maxit
   // only records the iteration cap); else a scalar kernel follows each pass
   const int last = a.fused ? p->inner_maxit : p->inner_maxit - 1;
   for (int k = 0; k <= last; ++k) {
     HIPCHK(timed(p, aao::KC_COCG_A, [&] { return aao::launch_cg_pass(p->f32, a, k, nact, p->stream); }));
+    a.ntiles_prev = a.ntiles;
     if (!a.fused)
       HIPCHK(timed(p, aao::KC_MISC, [&] { return aao::launch_cg_scalars(a, k, nact, p->stream); }));
     if (k + 1 == next_check) {
@@ -494,6 +496,12 @@ aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
       aao_status s = lag_check(c, nact, a.sys_list, n, false);
       if (s != AAO_OK) return s;
       if (n == 0) break;
+      // few systems left: the passes are bound by latency, and small tiles
+      // spread each system over more CUs
+      if (!small && a.fused && p->cg_ntiles_s > 0 && (long)nact * p->cg_ntiles <= AAO_CG_SMALL_WG) {
+        cg_tiling(a, p, true);
+        small = true;
+      }
     }
   }
   if (c.pending >= 0) {  // drain the last outstanding snapshot
@@ -862,20 +870,35 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
     p->cgTX = std::min(p->nx, AAO_CG_TX2D);
     p->cgTY = std::min(p->ny, AAO_CG_TY2D);
   }
-  {  // at most 4 tile points per thread, and the two-hop region within 8 per thread (LDS <= 32 KB)
-    auto pts = [&](int tx, int ty) { return (tx + 4 * p->Rx) * (ty + 4 * p->Ry); };
-    while ((pts(p->cgTX, p->cgTY) > 8 * aao::kBlock || p->cgTX * p->cgTY > 4 * aao::kBlock) && p->cgTY > 1)
-      p->cgTY = (p->cgTY + 1) / 2;
-    while ((pts(p->cgTX, p->cgTY) > 8 * aao::kBlock || p->cgTX * p->cgTY > 4 * aao::kBlock) && p->cgTX > 8)
-      p->cgTX = (p->cgTX + 1) / 2;
-    if (pts(p->cgTX, p->cgTY) > 8 * aao::kBlock || p->cgTX * p->cgTY > 4 * aao::kBlock) {
-      delete p;
-      return fail(AAO_EINVAL, "stencil reach too large for the COCG tile");
-    }
+  // at most `per` tile points per thread, and the two-hop region within 8 per
+  // thread (LDS <= 32 KB); halves TY, then TX, until both hold
+  auto fit_tile = [&](int& tx, int& ty, int per) {
+    auto pts = [&](int x, int y) { return (x + 4 * p->Rx) * (y + 4 * p->Ry); };
+    auto bad = [&] { return pts(tx, ty) > 8 * aao::kBlock || tx * ty > per * aao::kBlock; };
+    while (bad() && ty > 1) ty = (ty + 1) / 2;
+    while (bad() && tx > 8) tx = (tx + 1) / 2;
+    return !bad();
+  };
+  if (!fit_tile(p->cgTX, p->cgTY, 4)) {
+    delete p;
+    return fail(AAO_EINVAL, "stencil reach too large for the COCG tile");
   }
   p->cg_ntx = (p->nx + p->cgTX - 1) / p->cgTX;
   p->cg_nty = (p->ny + p->cgTY - 1) / p->cgTY;
   p->cg_ntiles = p->cg_ntx * p->cg_nty;
+  {  // small tiling (one point per thread) for the passes where few systems remain
+    int tx = (p->ny == 1) ? std::min(p->nx, 256) : std::min(p->nx, 32);
+    int ty = (p->ny == 1) ? 1 : std::min(p->ny, 8);
+    if (fit_tile(tx, ty, 1)) {
+      const int ntx = (p->nx + tx - 1) / tx, nts = ntx * ((p->ny + ty - 1) / ty);
+      if (nts > p->cg_ntiles && nts <= aao::kBlock && p->cg_ntiles <= aao::kBlock) {
+        p->cgTXs = tx;
+        p->cgTYs = ty;
+        p->cg_ntxs = ntx;
+        p->cg_ntiles_s = nts;
+      }
+    }
+  }
   if (p->inner == AAO_INNER_COCG && p->cg_ntiles >= (1 << 16)) {  // tile indices use 16-bit exact division
     delete p;
     return fail(AAO_EINVAL, "grid too large for the COCG tiling (at most 65535 tiles per system)");
@@ -888,7 +911,7 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   p->off_vec = off;
   off = align256(off + (size_t)p->nvec * p->S * p->N * p->csize);
   p->off_part = off;
-  off = align256(off + std::max((size_t)aao::QP_COUNT * p->S * p->wps, (size_t)2 * 5 * p->S * p->cg_ntiles) *
+  off = align256(off + std::max((size_t)aao::QP_COUNT * p->S * p->wps, (size_t)2 * 5 * p->S * std::max(p->cg_ntiles, p->cg_ntiles_s)) *
                            sizeof(double));
   p->off_list = off;  // three lists of active systems (two alternating snapshots, the initial one)
   off = align256(off + (size_t)3 * p->S * sizeof(int));
@@ -1381,8 +1404,6 @@ void aao_destroy(aao_plan_t p) {
   if (p->hread) (void)hipHostFree(p->hread);
   if (p->hlist) (void)hipHostFree(p->hlist);
   for (auto e : p->slot_ev)
-    if (e) (void)hipEventDestroy(e);
-  for (auto e : p->chk_ev)
     if (e) (void)hipEventDestroy(e);
   delete p;
 }

@@ -17,7 +17,9 @@
 // Scalars live in SysState.  When a system has at most 256 tiles every pass
 // reduces the previous pass's tile sums itself (fused); otherwise a small
 // per-system kernel does it between passes.  Sums run in a fixed order, so
-// results are bitwise reproducible.
+// results are bitwise reproducible.  A fused solve may change its tiling
+// between passes (small tiles once few systems remain): a pass reduces the
+// sums of the previous pass's tiling.
 #include "aao_device.hpp"
 #include "aao_kernels.hpp"
 
@@ -79,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
   }
   block_sum_wave0<kQ>(v, sh);
   if (threadIdx.x == 0) {
-    double* pb = a.part + (a.fused ? (size_t)kQ * a.num_sys * a.ntiles : 0);
+    double* pb = a.part + (a.fused ? a.part_stride : 0);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) pb[((size_t)q * a.num_sys + s) * a.ntiles + tile] = v[q];
   }
@@ -148,13 +150,15 @@ __device__ __forceinline__ double2 uniform(double2 v) {
 }
 
 // One COCG iteration for one tile of one system.  Thread t owns tile points
-// t + 256 j (j < kInside) and points t + 256 j of the two-hop ring around the
+// t + 256 j (j < NI) and points t + 256 j of the two-hop ring around the
 // tile (j < NH); it keeps r_k and then r_{k+1} of its points in registers across
-// the stages.  NT > 0: the stencil has NT taps (unrolled).
-template <typename T, int NH, int NT>
+// the stages.  NT > 0: the stencil has NT taps (unrolled).  NI = 1 (tiles of
+// at most 256 points, used when few systems remain and the pass is bound by
+// latency, not bandwidth) also requests x_k together with r_k and p_{k-1}.
+template <typename T, int NI, int NH, int NT>
 __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   using V = typename cvec<T>::type;
-  constexpr int NI = kInside;
+  constexpr bool kEarlyX = NI == 1;
   extern __shared__ char smem[];
   __shared__ double sh[4 * kQ];
   __shared__ int act;
@@ -183,10 +187,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   //    pass's tile sums in fused mode, the system state), so that it arrives
   //    ahead of the vectors.
   double pv[kQ] = {0, 0, 0, 0, 0};
-  if (a.fused && t < a.ntiles) {
-    const double* pp0 = a.part + (size_t)((k + 1) & 1) * kQ * a.num_sys * a.ntiles + (size_t)s * a.ntiles + t;
+  if (a.fused && t < a.ntiles_prev) {
+    const double* pp0 = a.part + ((k + 1) & 1) * a.part_stride + (size_t)s * a.ntiles_prev + t;
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) pv[q] = pp0[(size_t)q * a.num_sys * a.ntiles];
+    for (int q = 0; q < kQ; ++q) pv[q] = pp0[(size_t)q * a.num_sys * a.ntiles_prev];
   }
   // the state is read with workgroup-uniform addresses (scalar loads)
   const SysState* st0 = a.st + s;
@@ -242,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
     l = valid ? py * PW + px : -1;
     q = (valid && px >= Rx && px < PW - Rx && py >= Ry && py < PH - Ry) ? (py - Ry) * QW + (px - Rx) : -1;
   };
-  V ri[NI], pi[NI], rh[NH], ph[NH];
+  V ri[NI], pi[NI], rh[NH], ph[NH], xi[NI];
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
     int g, l, q;
@@ -250,6 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
     tile_slot(t, j, g, l, q, own);
     ri[j] = Rin[g];
     pi[j] = (k > 0) ? Pold[g] : vzero<V>();
+    if (kEarlyX) xi[j] = (k > 0 && own) ? X[g] : vzero<V>();
   }
 #pragma unroll
   for (int j = 0; j < NH; ++j) {
@@ -325,9 +330,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
 #pragma unroll
   for (int j = 0; j < NH; ++j)
     if (lh[j] >= 0) Pt.st(lh[j], (k > 0) ? vadd(rh[j], vmul(be, ph[j])) : rh[j]);
-  V xi[NI];
+  if (!kEarlyX) {
 #pragma unroll
-  for (int j = 0; j < NI; ++j) xi[j] = (k > 0 && gi[j] >= 0) ? X[gi[j]] : vzero<V>();
+    for (int j = 0; j < NI; ++j) xi[j] = (k > 0 && gi[j] >= 0) ? X[gi[j]] : vzero<V>();
+  }
   __syncthreads();
 
   // 5. r_{k+1} = r_k - alpha_k (p_k - c A p_k) on the one-hop region; tile
@@ -383,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   }
   block_sum_wave0<kQ>(v, sh);
   if (t == 0) {
-    double* pb = a.part + (a.fused ? (size_t)(k & 1) * kQ * a.num_sys * a.ntiles : 0);
+    double* pb = a.part + (a.fused ? (k & 1) * a.part_stride : 0);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) pb[((size_t)q * a.num_sys + s) * a.ntiles + tile] = v[q];
   }
@@ -462,14 +468,21 @@ hipError_t launch_cg_init(bool f32, const CgArgs& a, int nact, hipStream_t st) {
 
 hipError_t launch_cg_pass(bool f32, const CgArgs& a, int k, int nact, hipStream_t st) {
   if (a.TX * a.TY > kInside * kBlock) return hipErrorInvalidValue;
+  if (a.fused && (a.ntiles > kBlock || a.ntiles_prev < 1 || a.ntiles_prev > kBlock)) return hipErrorInvalidValue;
   dim3 grid(a.ntiles, nact);
   const size_t lds = cg_lds_bytes(f32, a);
   const int nh = cg_ring_slots(a);
   const int nt = (a.taps.n == 3 || a.taps.n == 5) ? a.taps.n : 0;
-#define AAO_CGP2(NH, NT)                                                                          \
-  do {                                                                                            \
-    if (f32) hipLaunchKernelGGL((k_cg_pass<float, NH, NT>), grid, dim3(kBlock), lds, st, a, k);   \
-    else hipLaunchKernelGGL((k_cg_pass<double, NH, NT>), grid, dim3(kBlock), lds, st, a, k);      \
+  const bool one = a.TX * a.TY <= kBlock;
+#define AAO_CGP3(NI, NH, NT)                                                                          \
+  do {                                                                                                \
+    if (f32) hipLaunchKernelGGL((k_cg_pass<float, NI, NH, NT>), grid, dim3(kBlock), lds, st, a, k);   \
+    else hipLaunchKernelGGL((k_cg_pass<double, NI, NH, NT>), grid, dim3(kBlock), lds, st, a, k);      \
+  } while (0)
+#define AAO_CGP2(NH, NT)         \
+  do {                           \
+    if (one) AAO_CGP3(1, NH, NT); \
+    else AAO_CGP3(kInside, NH, NT); \
   } while (0)
 #define AAO_CGP(NH)                  \
   do {                               \
@@ -482,6 +495,7 @@ hipError_t launch_cg_pass(bool f32, const CgArgs& a, int k, int nact, hipStream_
   else if (nh <= 4) AAO_CGP(4);
   else if (nh <= 8) AAO_CGP(8);
   else return hipErrorInvalidValue;
+#undef AAO_CGP3
 #undef AAO_CGP2
 #undef AAO_CGP
   return hipGetLastError();

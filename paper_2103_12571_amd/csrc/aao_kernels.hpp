@@ -61,6 +61,11 @@ struct CgArgs {
   unsigned long long m_ntx, m_tx, m_pw, m_hw;
   int xcd_band;  // ntiles / 8 when tiles are banded per XCD, else 0
   int fused;     // 1: each pass advances the scalars itself (partials double-buffered)
+  // fused: tile count of the pass that wrote the partials this pass reduces
+  // (the tiling may change between passes) and the offset between the two
+  // partial buffers (5 num_sys times the larger tile count)
+  int ntiles_prev;
+  size_t part_stride;
   double tol2;
   int maxit;
 };
