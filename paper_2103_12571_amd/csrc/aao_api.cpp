@@ -586,9 +586,10 @@ aao_status read_back(aao_plan* p, int nsys, bool want_norms, SweepOut& o) {
   double* hn = reinterpret_cast<double*>(p->hread + 64);
   aao::SysState* hs = reinterpret_cast<aao::SysState*>(p->hread + 128);
   if (want_norms) HIPCHK(hipMemcpyAsync(hn, p->norms(), 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  if (nsys > 0)
+  if (nsys > 0) {
     close_run(p);
     HIPCHK(hipMemcpyAsync(hs, p->st(), (size_t)nsys * sizeof(aao::SysState), hipMemcpyDeviceToHost, p->stream));
+  }
   close_run(p);
   HIPCHK(hipStreamSynchronize(p->stream));
   collect_timing(p);

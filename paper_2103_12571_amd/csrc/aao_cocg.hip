@@ -149,6 +149,85 @@ __device__ __forceinline__ double2 uniform(double2 v) {
   return mk(u(v.x), u(v.y));
 }
 
+// Where a workgroup's tile sits: the tile origin, the widths of the two-hop
+// (PW x PH) and one-hop (QW wide) regions around it, the slot counts.
+struct TileGeo {
+  int TX, TY, Rx, Ry, PW, PH, QW, nx, ny, x0, y0, nin, nring;
+};
+
+// XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs (each
+// with its own L2), so slot b goes to XCD b % 8; give each XCD a contiguous
+// band of tiles so that tile halos are read from its own L2.
+__device__ __forceinline__ int tile_of_block(const CgArgs& a) {
+  const int b = blockIdx.x;
+  return (a.xcd_band > 0) ? (b & 7) * a.xcd_band + (b >> 3) : b;
+}
+
+__device__ __forceinline__ TileGeo tile_geo(const CgArgs& a, int tile) {
+  TileGeo G;
+  G.TX = a.TX;
+  G.TY = a.TY;
+  G.Rx = a.Rx;
+  G.Ry = a.Ry;
+  G.PW = G.TX + 4 * G.Rx;
+  G.PH = G.TY + 4 * G.Ry;
+  G.QW = G.TX + 2 * G.Rx;
+  G.nx = a.g.nx;
+  G.ny = a.g.ny;
+  const int ty = fdiv(tile, a.m_ntx), tx = tile - ty * a.ntx;
+  G.x0 = tx * G.TX;
+  G.y0 = ty * G.TY;
+  G.nin = G.TX * G.TY;
+  G.nring = G.PW * G.PH - G.nin;
+  return G;
+}
+
+// Tile slot j of thread tt: global index g, LDS index l in the two-hop layout
+// (-1: no point), index q in the one-hop layout, own: stored by this tile.
+// Tile points of a ragged last tile that fall outside the grid hold their
+// periodic images (used as neighbours, never stored).
+__device__ __forceinline__ void tile_slot(const CgArgs& a, const TileGeo& G, int tt, int j, int& g, int& l, int& q,
+                                          bool& own) {
+  const int i = tt + j * kBlock;
+  const bool valid = i < G.nin;
+  const int ii = valid ? i : 0;
+  const int iy = fdiv(ii, a.m_tx), ix = ii - iy * G.TX;
+  int ux = G.x0 + ix, uy = G.y0 + iy;
+  own = valid && ux < G.nx && uy < G.ny;
+  ux -= (ux >= G.nx) ? G.nx : 0;  // TX <= nx, TY <= ny
+  uy -= (uy >= G.ny) ? G.ny : 0;
+  g = uy * G.nx + ux;
+  l = valid ? (iy + 2 * G.Ry) * G.PW + ix + 2 * G.Rx : -1;
+  q = (iy + G.Ry) * G.QW + ix + G.Rx;
+}
+
+// Ring slot j of thread tt: 2Ry full rows above, 2Ry full rows below, then the
+// rows of the tile with 2Rx points on each side; q = -1 outside the one-hop
+// ring.
+__device__ __forceinline__ void ring_slot(const CgArgs& a, const TileGeo& G, int tt, int j, int& g, int& l, int& q) {
+  const int h = tt + j * kBlock;
+  const bool valid = h < G.nring;
+  const int hh = valid ? h : 0;
+  const int band = 2 * G.Ry * G.PW;
+  int px, py;
+  if (hh < band) {
+    py = fdiv(hh, a.m_pw);
+    px = hh - py * G.PW;
+  } else if (hh < 2 * band) {
+    const int h2 = hh - band, r2 = fdiv(h2, a.m_pw);
+    py = G.PH - 2 * G.Ry + r2;
+    px = h2 - r2 * G.PW;
+  } else {
+    const int h3 = hh - 2 * band, r3 = fdiv(h3, a.m_hw), c3 = h3 - r3 * 4 * G.Rx;
+    py = 2 * G.Ry + r3;
+    px = (c3 < 2 * G.Rx) ? c3 : G.TX + c3;
+  }
+  g = pmod(G.y0 - 2 * G.Ry + py, G.ny) * G.nx + pmod(G.x0 - 2 * G.Rx + px, G.nx);
+  l = valid ? py * G.PW + px : -1;
+  q = (valid && px >= G.Rx && px < G.PW - G.Rx && py >= G.Ry && py < G.PH - G.Ry) ? (py - G.Ry) * G.QW + (px - G.Rx)
+                                                                                     : -1;
+}
+
 // One COCG iteration for one tile of one system.  Thread t owns tile points
 // t + 256 j (j < NI) and points t + 256 j of the two-hop ring around the
 // tile (j < NH); it keeps r_k and then r_{k+1} of its points in registers across
@@ -165,23 +244,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   __shared__ double2 sc[2];
   const int t = threadIdx.x;
   const int s = a.sys_list[blockIdx.y];
-  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs
-  // (each with its own L2), so slot b goes to XCD b % 8; give each XCD a
-  // contiguous band of tiles so that tile halos are read from its own L2.
-  int tile = blockIdx.x;
-  if (a.xcd_band > 0) tile = (tile & 7) * a.xcd_band + (tile >> 3);
-  const int Rx = a.Rx, Ry = a.Ry, TX = a.TX, TY = a.TY;
-  const int PW = TX + 4 * Rx, PH = TY + 4 * Ry, QW = TX + 2 * Rx;
-  const int nx = a.g.nx, ny = a.g.ny;
-  const int ty = fdiv(tile, a.m_ntx), tx = tile - ty * a.ntx;
-  const int x0 = tx * TX, y0 = ty * TY;
+  const int tile = tile_of_block(a);
+  const TileGeo G = tile_geo(a, tile);
+  const int PW = G.PW;
   const size_t off = (size_t)s * a.g.N;
   const V* Rin = reinterpret_cast<const V*>(a.R[k & 1]) + off;
   V* Rout = reinterpret_cast<V*>(a.R[(k + 1) & 1]) + off;
   const V* Pold = reinterpret_cast<const V*>(a.P[(k + 1) & 1]) + off;
   V* Pnew = reinterpret_cast<V*>(a.P[k & 1]) + off;
   V* X = reinterpret_cast<V*>(a.X) + off;
-  const LdsCplx<V> Pt(smem, PW * PH);  // p_k on the two-hop region, then r_{k+1} on the one-hop region
+  const LdsCplx<V> Pt(smem, G.PW * G.PH);  // p_k on the two-hop region, then r_{k+1} on the one-hop region
 
   // 1. What decides this pass's scalars is requested first (the previous
   //    pass's tile sums in fused mode, the system state), so that it arrives
@@ -206,52 +278,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   // 2. r_k and p_{k-1} at the tile points and on the two-hop ring.  Tile
   //    points of a ragged last tile that fall outside the grid hold their
   //    periodic images (used as neighbours, never stored).
-  const int nin = TX * TY, nring = PW * PH - nin;
-  // tile slot j of thread tt: global index g, LDS index l in the two-hop
-  // layout (-1: no point), index q in the one-hop layout, own: stored here
-  auto tile_slot = [&](int tt, int j, int& g, int& l, int& q, bool& own) {
-    const int i = tt + j * kBlock;
-    const bool valid = i < nin;
-    const int ii = valid ? i : 0;
-    const int iy = fdiv(ii, a.m_tx), ix = ii - iy * TX;
-    int ux = x0 + ix, uy = y0 + iy;
-    own = valid && ux < nx && uy < ny;
-    ux -= (ux >= nx) ? nx : 0;  // TX <= nx, TY <= ny
-    uy -= (uy >= ny) ? ny : 0;
-    g = uy * nx + ux;
-    l = valid ? (iy + 2 * Ry) * PW + ix + 2 * Rx : -1;
-    q = (iy + Ry) * QW + ix + Rx;
-  };
-  // ring slot j: 2Ry full rows above, 2Ry full rows below, then the rows of
-  // the tile with 2Rx points on each side; q = -1 outside the one-hop ring
-  auto ring_slot = [&](int tt, int j, int& g, int& l, int& q) {
-    const int h = tt + j * kBlock;
-    const bool valid = h < nring;
-    const int hh = valid ? h : 0;
-    const int band = 2 * Ry * PW;
-    int px, py;
-    if (hh < band) {
-      py = fdiv(hh, a.m_pw);
-      px = hh - py * PW;
-    } else if (hh < 2 * band) {
-      const int h2 = hh - band, r2 = fdiv(h2, a.m_pw);
-      py = PH - 2 * Ry + r2;
-      px = h2 - r2 * PW;
-    } else {
-      const int h3 = hh - 2 * band, r3 = fdiv(h3, a.m_hw), c3 = h3 - r3 * 4 * Rx;
-      py = 2 * Ry + r3;
-      px = (c3 < 2 * Rx) ? c3 : TX + c3;
-    }
-    g = pmod(y0 - 2 * Ry + py, ny) * nx + pmod(x0 - 2 * Rx + px, nx);
-    l = valid ? py * PW + px : -1;
-    q = (valid && px >= Rx && px < PW - Rx && py >= Ry && py < PH - Ry) ? (py - Ry) * QW + (px - Rx) : -1;
-  };
   V ri[NI], pi[NI], rh[NH], ph[NH], xi[NI];
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
     int g, l, q;
     bool own;
-    tile_slot(t, j, g, l, q, own);
+    tile_slot(a, G, t, j, g, l, q, own);
     ri[j] = Rin[g];
     pi[j] = (k > 0) ? Pold[g] : vzero<V>();
     if (kEarlyX) xi[j] = (k > 0 && own) ? X[g] : vzero<V>();
@@ -259,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
 #pragma unroll
   for (int j = 0; j < NH; ++j) {
     int g, l, q;
-    ring_slot(t, j, g, l, q);
+    ring_slot(a, G, t, j, g, l, q);
     rh[j] = Rin[g];
     ph[j] = (k > 0) ? Pold[g] : vzero<V>();
   }
@@ -314,13 +346,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   for (int j = 0; j < NI; ++j) {
     int g;
     bool own;
-    tile_slot(t2, j, g, li[j], qi[j], own);
+    tile_slot(a, G, t2, j, g, li[j], qi[j], own);
     gi[j] = own ? g : -1;
   }
 #pragma unroll
   for (int j = 0; j < NH; ++j) {
     int g;
-    ring_slot(t2, j, g, lh[j], qh[j]);
+    ring_slot(a, G, t2, j, g, lh[j], qh[j]);
   }
 
   // 4. p_k = r_k + beta_k p_{k-1} on the two-hop region
@@ -377,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
     if (gi[j] >= 0) {
-      const V acc = tile_stencil<NT, T>(a, Rt, qi[j], QW);
+      const V acc = tile_stencil<NT, T>(a, Rt, qi[j], G.QW);
       const V r = ri[j];
       const V w = vsub(r, vmul(sft, acc));
       v[0] += (double)r.x * r.x - (double)r.y * r.y;
