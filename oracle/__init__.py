@@ -22,6 +22,8 @@ What it computes (Caklovic, Speck, Frank, arXiv 2103.12571):
   (eq. (prec)) by a sparse direct solve, and the alpha schedule of Alg. 2.
 * The adjoint system C^T lambda = g by a backward sequential sweep and the
   gradients of 1/2 ||u_{L,M} - u_target||^2 with respect to u0 and nu.
+* Flexible GMRES on C u = w with C_alpha as right preconditioner (the Krylov
+  alternative to Richardson that the paper points to).
 
 Parity status of each function is stated in its docstring; every function is
 pinned by a ``-m "not gpu"`` test against closed forms or values printed in
@@ -35,8 +37,10 @@ from .allatonce import (assemble_C, assemble_C_alpha, assemble_w, residual,
                         precond_solve, brute_force_solve)
 from .adjoint import adjoint_solve, gradients
 from .alpha import alpha_schedule
+from .gmres import fgmres, gmres_solve
 
 __all__ = [
+    "fgmres", "gmres_solve",
     "radau_right_nodes", "collocation_matrix", "node_polynomial",
     "PeriodicStencil", "stencil_for", "fd_weights", "central_d2", "upwind_d1", "sequential_solve",
     "assemble_C", "assemble_C_alpha", "assemble_w", "residual",
