@@ -124,7 +124,7 @@ typedef struct {
 /* Per kernel class: launches, elements processed, event-timed milliseconds and
  * algorithmic bytes moved.  Timing is collected only while enabled by
  * aao_set_timing(plan, 1).  Classes: see aao_kernel_name(). */
-#define AAO_NUM_KERNELS 12
+#define AAO_NUM_KERNELS 13
 typedef struct {
   int64_t launches[AAO_NUM_KERNELS];
   double elements[AAO_NUM_KERNELS];
@@ -214,6 +214,36 @@ aao_status aao_solve(aao_plan_t plan, double* u_dev, const double* alphas, int n
 aao_status aao_solve_windows(aao_plan_t plan, double* u_dev, int n_windows, const double* frc_all,
                              const double* alphas, int n_alphas, double m0, double tol, int stop_rule,
                              int max_iter, aao_solve_info* infos);
+
+/* Outer Krylov solver in place of the Richardson sweep (the paper points to
+ * Krylov acceleration of the alpha-circulant preconditioner, introduction and
+ * Sec. 6): flexible GMRES(restart) on C u = w (eq. (globalsys)) with C_alpha
+ * (eq. (prec)) as right preconditioner, one Krylov space per instance b.
+ * Step k applies C_alpha^{-1} with alphas[min(k, n_alphas-1)]; alphas = NULL
+ * uses the fixed alpha = clamp(sqrt(L (3 eps + tau)), 1e-8, 1/2), eps = 2^-53
+ * (FP64) or 2^-24 (MIXED): the relative round-off model of mixed precision
+ * also fits here, since each preconditioner application is relative to the
+ * current Krylov vector.  Gram-Schmidt is classical with one
+ * re-orthogonalisation; the small least-squares problems are solved by Givens
+ * rotations on the host.  u_dev [B][L][M][N] is overwritten: it starts from
+ * u0 at every node.  Stops when max over b of ||w_b - C u_b||_2 / ||w_b||_2
+ * <= tol (the true residual, checked at every restart and at the end) or after
+ * max_steps preconditioner applications (ENOCONV).
+ * work_dev: device scratch of at least aao_gmres_workspace_size bytes, 256-byte
+ * aligned, owned by the caller; restart in 1..31. */
+typedef struct {
+  int steps;                         /* preconditioner applications */
+  int cycles;                        /* restart cycles started */
+  int converged;                     /* 1 if tol was met */
+  double res_rel;                    /* final true max_b ||w_b - C u_b|| / ||w_b|| */
+  double alpha[AAO_MAX_HIST];        /* alpha of step k */
+  double res_est[AAO_MAX_HIST];      /* least-squares estimate of the relative residual after step k */
+  double inner_mean[AAO_MAX_HIST];   /* mean inner iterations per shifted system, step k */
+  int inner_max[AAO_MAX_HIST];       /* max inner iterations over systems, step k */
+} aao_gmres_info;
+aao_status aao_gmres_workspace_size(aao_plan_t plan, int restart, size_t* bytes);
+aao_status aao_solve_gmres(aao_plan_t plan, double* u_dev, int restart, const double* alphas, int n_alphas,
+                           double tol, int max_steps, void* work_dev, size_t work_bytes, aao_gmres_info* info);
 
 /* Adjoint: solve C^T lambda = g, g = e_{L,M} (x) g_last, by the same
  * alpha-circulant machinery transposed (E_alpha^T = V^{-T} D_alpha V^T, Lemma

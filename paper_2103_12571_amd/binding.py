@@ -18,13 +18,14 @@ AAO_FP64, AAO_MIXED = 0, 1
 AAO_INNER_COCG, AAO_INNER_BICGSTAB, AAO_INNER_FFT = 0, 1, 2
 AAO_STOP_LASTSTEP, AAO_STOP_RESIDUAL = 0, 1
 AAO_MAX_HIST = 64
-AAO_NUM_KERNELS = 12
+AAO_NUM_KERNELS = 13
 
 STATUS_NAMES = {0: "AAO_OK", -1: "AAO_EINVAL", -2: "AAO_EHIP", -3: "AAO_ENODIAG", -4: "AAO_ENOCONV",
                 -5: "AAO_ESTAGNATE", -6: "AAO_EWORKSPACE", -7: "AAO_ENAN", -8: "AAO_ESTATE"}
 
 EXPORTS = ["aao_setup", "aao_set_stream", "aao_workspace_size", "aao_set_workspace", "aao_set_u0",
-           "aao_set_stencil_coef", "aao_set_forcing", "aao_solve_windows",
+           "aao_set_stencil_coef", "aao_set_forcing", "aao_solve_windows", "aao_gmres_workspace_size",
+           "aao_solve_gmres",
            "aao_residual", "aao_precond", "aao_sweep", "aao_solve", "aao_adjoint_solve", "aao_grad",
            "aao_shifted_solve", "aao_set_timing", "aao_get_stats", "aao_reset_stats", "aao_kernel_name",
            "aao_tables", "aao_collocation", "aao_last_error", "aao_destroy"]
@@ -62,6 +63,18 @@ class aao_solve_info(C.Structure):
                 "inner_mean": list(self.inner_mean[:k]), "inner_max": list(self.inner_max[:k])}
 
 
+class aao_gmres_info(C.Structure):
+    _fields_ = [("steps", C.c_int), ("cycles", C.c_int), ("converged", C.c_int), ("res_rel", C.c_double),
+                ("alpha", C.c_double * AAO_MAX_HIST), ("res_est", C.c_double * AAO_MAX_HIST),
+                ("inner_mean", C.c_double * AAO_MAX_HIST), ("inner_max", C.c_int * AAO_MAX_HIST)]
+
+    def as_dict(self):
+        k = min(self.steps, AAO_MAX_HIST)
+        return {"steps": self.steps, "cycles": self.cycles, "converged": bool(self.converged),
+                "res_rel": self.res_rel, "alpha": list(self.alpha[:k]), "res_est": list(self.res_est[:k]),
+                "inner_mean": list(self.inner_mean[:k]), "inner_max": list(self.inner_max[:k])}
+
+
 class aao_kernel_stats(C.Structure):
     _fields_ = [("launches", C.c_int64 * AAO_NUM_KERNELS), ("elements", C.c_double * AAO_NUM_KERNELS),
                 ("bytes", C.c_double * AAO_NUM_KERNELS), ("ms", C.c_double * AAO_NUM_KERNELS)]
@@ -90,6 +103,9 @@ def lib():
         "aao_set_forcing": [P, P],
         "aao_solve_windows": [P, P, C.c_int, P, D, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
                               C.POINTER(aao_solve_info)],
+        "aao_gmres_workspace_size": [P, C.c_int, C.POINTER(C.c_size_t)],
+        "aao_solve_gmres": [P, P, C.c_int, D, C.c_int, C.c_double, C.c_int, P, C.c_size_t,
+                            C.POINTER(aao_gmres_info)],
         "aao_residual": [P, P, P, D],
         "aao_precond": [P, P, P, C.c_double],
         "aao_sweep": [P, P, C.c_double, D, D],
@@ -173,6 +189,7 @@ class Plan:
             check(lib().aao_set_workspace(self._h, C.c_void_p(base + off), size.value))
         self._u0 = None
         self._frc = None
+        self._gmres_ws = {}
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -309,6 +326,29 @@ class Plan:
         if s != AAO_OK:
             raise AAOError(s, "%s; histories %s" % (lib().aao_last_error().decode(), out))
         return u, out
+
+    def solve_gmres(self, u=None, restart=20, alphas=None, tol=1e-12, max_steps=200, raise_on_noconv=True):
+        """Flexible GMRES(restart) on C u = w with C_alpha as right preconditioner
+        (aao_solve_gmres); the scratch is a torch allocation kept per restart.
+        Returns (u, info)."""
+        if u is None:
+            u = self.torch.empty(self.shape, dtype=self.torch.float64, device=self.device)
+        need = C.c_size_t()
+        check(lib().aao_gmres_workspace_size(self._h, int(restart), C.byref(need)))
+        ws = self._gmres_ws.get(int(restart))
+        if ws is None or ws.numel() < need.value + 256:
+            ws = self.torch.empty(need.value + 256, dtype=self.torch.uint8, device=self.device)
+            self._gmres_ws = {int(restart): ws}
+        base = ws.data_ptr() + (-ws.data_ptr()) % 256
+        info = aao_gmres_info()
+        al = None if alphas is None else np.ascontiguousarray(alphas, dtype=np.float64)
+        self._sync_stream()
+        s = lib().aao_solve_gmres(self._h, _ptr(u), int(restart), _dptr(al) if al is not None else None,
+                                  0 if al is None else len(al), float(tol), int(max_steps), C.c_void_p(base),
+                                  need.value, C.byref(info))
+        if s != AAO_OK and (raise_on_noconv or s != AAO_ENOCONV):
+            raise AAOError(s, "%s; history %s" % (lib().aao_last_error().decode(), info.as_dict()))
+        return u, info.as_dict()
 
     def adjoint_solve(self, g_last, alphas=None, m0=0.0, tol=1e-12, max_iter=50):
         g = self._f64(g_last, (self.B, self.N))

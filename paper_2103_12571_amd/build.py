@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libaao.so")
-SOURCES = ["csrc/aao_kernels.hip", "csrc/aao_cocg.hip", "csrc/aao_fftsolve.hip", "csrc/aao_api.cpp",
+SOURCES = ["csrc/aao_kernels.hip", "csrc/aao_cocg.hip", "csrc/aao_fftsolve.hip", "csrc/aao_gmres.hip", "csrc/aao_api.cpp",
            "csrc/aao_host.cpp"]
 
 

@@ -135,6 +135,9 @@ struct aao_plan {
   // elements processed per kernel class (first iteration / later iterations),
   // from the per-system iteration counts read back after each inner solve
   double work_first[AAO_NUM_KERNELS] = {}, work_later[AAO_NUM_KERNELS] = {};
+  double bytes_direct[AAO_NUM_KERNELS] = {};  // algorithmic bytes counted at launch (outer GMRES)
+  double* hgm = nullptr;                      // pinned: GMRES partial sums down, coefficients up
+  size_t hgm_bytes = 0;
 
   void* vec(int i) const { return ws + off_vec + (size_t)i * S * N * csize; }
   double* part() const { return reinterpret_cast<double*>(ws + off_part); }
@@ -745,7 +748,7 @@ const char* aao_kernel_name(int c) {
   static const char* names[AAO_NUM_KERNELS] = {
       "fwd_residual_dft_l", "bwd_idft_l_update", "cocg_pass", "cocg_init",
       "bicgstab_p_matvec", "bicgstab_s_matvec", "bicgstab_update", "fft_inner",
-      "residual", "misc", "init", "grad"};
+      "residual", "misc", "init", "grad", "gmres_orth"};
   return (c >= 0 && c < AAO_NUM_KERNELS) ? names[c] : "";
 }
 
@@ -1207,6 +1210,288 @@ aao_status aao_solve(aao_plan_t p, double* u, const double* alphas, int n_alphas
   return run_solve(p, u, alphas, n_alphas, m0, tol, stop_rule, max_iter, info, 0, 0.0);
 }
 
+// ------------------------------------------------------------ outer GMRES
+namespace {
+
+// Scratch of aao_solve_gmres inside the caller's buffer: restart + 1 Arnoldi
+// vectors V, restart preconditioned vectors Z (each [B][L][M][N] FP64,
+// 256-byte aligned), a zero initial value [B][N] (to apply C alone), block
+// partial sums, then coefficients [B][kGmresMax] followed by scales [B] (one
+// upload).
+struct GmresWs {
+  double *V = nullptr, *Z = nullptr, *zero_u0 = nullptr, *part = nullptr, *coef = nullptr, *scl = nullptr;
+  size_t stride = 0;  // doubles between basis vectors
+  int nblk = 1;
+  size_t bytes = 0;
+};
+
+GmresWs gmres_layout(const aao_plan* p, int restart, char* base) {
+  GmresWs w;
+  const int64_t D = (int64_t)p->L * p->M * p->N;
+  w.stride = ((size_t)p->B * D + 31) / 32 * 32;
+  w.nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (D + 2047) / 2048));
+  size_t off = 0;
+  auto take = [&](size_t n_doubles) {
+    double* q = reinterpret_cast<double*>(base + off);
+    off = align256(off + n_doubles * sizeof(double));
+    return q;
+  };
+  w.V = take((size_t)(restart + 1) * w.stride);
+  w.Z = take((size_t)restart * w.stride);
+  w.zero_u0 = take((size_t)p->B * p->N);
+  w.part = take((size_t)p->B * w.nblk * aao::kGmresMax);
+  w.coef = take((size_t)p->B * (aao::kGmresMax + 1));
+  w.scl = w.coef + (size_t)p->B * aao::kGmresMax;
+  w.bytes = off;
+  return w;
+}
+
+// Pinned staging: [B][nblk][kGmresMax] partial sums, then coefficients and scales.
+aao_status gmres_pinned(aao_plan* p, const GmresWs& w) {
+  const size_t need = ((size_t)p->B * w.nblk * aao::kGmresMax + (size_t)p->B * (aao::kGmresMax + 1)) * sizeof(double);
+  if (p->hgm_bytes >= need) return AAO_OK;
+  if (p->hgm) HIPCHK(hipHostFree(p->hgm));
+  p->hgm = nullptr;
+  p->hgm_bytes = 0;
+  HIPCHK(hipHostMalloc(&p->hgm, need, hipHostMallocDefault));
+  p->hgm_bytes = need;
+  return AAO_OK;
+}
+
+// Dot products <V_i[b], t[b]> (i < nvec) into out[b][i], summed on the host in
+// a fixed order; synchronises the stream.
+aao_status gmres_dots(aao_plan* p, const GmresWs& w, const double* V, int nvec, const double* t, double* out) {
+  const int64_t D = (int64_t)p->L * p->M * p->N;
+  const int K = aao::gmres_bucket(nvec);
+  p->bytes_direct[aao::KC_GMRES] += (double)(nvec + 1) * p->B * D * sizeof(double);
+  HIPCHK(timed(p, aao::KC_GMRES,
+               [&] { return aao::launch_mdot(V, w.stride, nvec, t, D, p->B, w.part, w.nblk, p->stream); }));
+  close_run(p);
+  HIPCHK(hipMemcpyAsync(p->hgm, w.part, (size_t)p->B * w.nblk * K * sizeof(double), hipMemcpyDeviceToHost,
+                        p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  for (int b = 0; b < p->B; ++b)
+    for (int i = 0; i < nvec; ++i) {
+      double acc = 0.0;
+      for (int k = 0; k < w.nblk; ++k) acc += p->hgm[((size_t)b * w.nblk + k) * K + i];
+      out[b * aao::kGmresMax + i] = acc;
+    }
+  return AAO_OK;
+}
+
+// out = s[b] in + sum_{i < nvec} c[b][i] V_i (c: [B][kGmresMax] host); with
+// norm2 != null also ||out[b]||^2 (synchronises the stream).
+aao_status gmres_axpy(aao_plan* p, const GmresWs& w, double* out, const double* in, const double* s,
+                      const double* V, int nvec, const double* c, double* norm2) {
+  const int64_t D = (int64_t)p->L * p->M * p->N;
+  double* hc = p->hgm + (size_t)p->B * w.nblk * aao::kGmresMax;
+  // the staging area is free: every earlier use of it ended in a stream synchronisation
+  for (int b = 0; b < p->B; ++b) {
+    for (int i = 0; i < aao::kGmresMax; ++i) hc[b * aao::kGmresMax + i] = (c && i < nvec) ? c[b * aao::kGmresMax + i] : 0.0;
+    hc[(size_t)p->B * aao::kGmresMax + b] = s[b];
+  }
+  close_run(p);
+  HIPCHK(hipMemcpyAsync(w.coef, hc, (size_t)p->B * (aao::kGmresMax + 1) * sizeof(double), hipMemcpyHostToDevice,
+                        p->stream));
+  p->bytes_direct[aao::KC_GMRES] += (double)(nvec + 2) * p->B * D * sizeof(double);
+  HIPCHK(timed(p, aao::KC_GMRES, [&] {
+    return aao::launch_maxpy(out, in, w.scl, V, w.stride, nvec, w.coef, D, p->B, norm2 ? w.part : nullptr, w.nblk,
+                             p->stream);
+  }));
+  close_run(p);
+  if (norm2) {
+    HIPCHK(hipMemcpyAsync(p->hgm, w.part, (size_t)p->B * w.nblk * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  }
+  // the next staging write must not overtake the upload
+  HIPCHK(hipStreamSynchronize(p->stream));
+  if (norm2)
+    for (int b = 0; b < p->B; ++b) {
+      double acc = 0.0;
+      for (int k = 0; k < w.nblk; ++k) acc += p->hgm[(size_t)b * w.nblk + k];
+      norm2[b] = acc;
+    }
+  return AAO_OK;
+}
+
+// r = w - C v with the plan's w (zero_w: w = 0 and no source, so r = -C v).
+aao_status gmres_residual(aao_plan* p, const GmresWs& w, const double* v, double* r, bool zero_w) {
+  aao::FwdArgs fa = fwd_args(p, v, 0);
+  if (zero_w) {
+    fa.w0 = w.zero_u0;
+    fa.frc = nullptr;
+  }
+  HIPCHK(timed(p, aao::KC_RESIDUAL, [&] { return aao::launch_residual(p->M, false, fa, r, p->B, p->stream); }));
+  return AAO_OK;
+}
+
+// z = C_alpha^{-1} v (rows a2 - a4); inner statistics into o.
+aao_status gmres_precond(aao_plan* p, const double* v, double* z, double alpha, SweepOut& o) {
+  aao_status s = upload_tables(p, alpha, 0);
+  if (s != AAO_OK) return s;
+  aao::FwdArgs fa = fwd_args(p, v, 0);
+  HIPCHK(timed(p, aao::KC_FWD, [&] { return aao::launch_fwd(p->M, false, true, p->f32, fa, p->B, p->stream); }));
+  s = inner_solve(p, 0, p->S);
+  if (s != AAO_OK) return s;
+  aao::BwdArgs ba = bwd_args(p, z);
+  HIPCHK(timed(p, aao::KC_BWD, [&] { return aao::launch_bwd(p->M, false, true, p->f32, ba, p->B, p->stream); }));
+  return read_back(p, p->S, false, o);
+}
+
+}  // namespace
+
+aao_status aao_gmres_workspace_size(aao_plan_t p, int restart, size_t* bytes) {
+  if (!p || !bytes) return fail(AAO_EINVAL, "null argument");
+  if (restart < 1 || restart >= aao::kGmresMax) return fail(AAO_EINVAL, "restart must lie in 1..31");
+  *bytes = gmres_layout(p, restart, nullptr).bytes;
+  return AAO_OK;
+}
+
+aao_status aao_solve_gmres(aao_plan_t p, double* u, int restart, const double* alphas, int n_alphas, double tol,
+                           int max_steps, void* work, size_t work_bytes, aao_gmres_info* info) {
+  aao_status s = need_ready(p, true);
+  if (s != AAO_OK) return s;
+  if (!u || !work) return fail(AAO_EINVAL, "null array");
+  if (restart < 1 || restart >= aao::kGmresMax) return fail(AAO_EINVAL, "restart must lie in 1..31");
+  if (!(tol >= 0.0) || max_steps < 1) return fail(AAO_EINVAL, "tol must be >= 0 and max_steps >= 1");
+  if ((reinterpret_cast<uintptr_t>(work) & 255) != 0) return fail(AAO_EINVAL, "GMRES workspace must be 256-byte aligned");
+  if (alphas) {
+    if (n_alphas < 1) return fail(AAO_EINVAL, "n_alphas must be >= 1");
+    for (int i = 0; i < n_alphas; ++i)
+      if (!(alphas[i] > 0.0 && alphas[i] < 1.0)) return fail(AAO_EINVAL, "alpha must lie in (0, 1)");
+  }
+  const GmresWs w = gmres_layout(p, restart, reinterpret_cast<char*>(work));
+  if (work_bytes < w.bytes)
+    return fail(AAO_EWORKSPACE, "GMRES workspace of " + std::to_string(work_bytes) + " bytes < required " +
+                                    std::to_string(w.bytes));
+  s = gmres_pinned(p, w);
+  if (s != AAO_OK) return s;
+  aao_gmres_info loc{};
+  aao_gmres_info& o = info ? *info : loc;
+  std::memset(&o, 0, sizeof(o));
+  const int B = p->B, m = restart, KM = aao::kGmresMax;
+  const int64_t D = (int64_t)p->L * p->M * p->N;
+  const double eps = p->f32 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
+  const double a_def = std::min(0.5, std::max(1e-8, std::sqrt(p->L * (3.0 * eps + p->inner_tol))));
+  auto Vi = [&](int i) { return w.V + (size_t)i * w.stride; };
+  auto Zi = [&](int i) { return w.Z + (size_t)i * w.stride; };
+
+  close_run(p);
+  HIPCHK(aao::launch_fill(w.zero_u0, 0.0, (int64_t)B * p->N, p->stream));
+  // ||w_b||: the residual of a zero vector is w
+  HIPCHK(aao::launch_fill(Zi(0), 0.0, (int64_t)B * D, p->stream));
+  s = gmres_residual(p, w, Zi(0), Vi(0), false);
+  if (s != AAO_OK) return s;
+  std::vector<double> wn(B), dot((size_t)B * KM), h1((size_t)B * KM), h2((size_t)B * KM), nrm(B), scl(B);
+  s = gmres_dots(p, w, Vi(0), 1, Vi(0), dot.data());
+  if (s != AAO_OK) return s;
+  for (int b = 0; b < B; ++b) wn[b] = std::sqrt(dot[(size_t)b * KM]);
+  close_run(p);
+  HIPCHK(aao::launch_init_u(u, p->u0, B, p->L, p->M, p->N, p->stream));
+
+  // H[b][i][j] (i <= j + 1), Givens (c, s) per column, g the rotated right-hand side
+  std::vector<double> H((size_t)B * (m + 1) * m), cs((size_t)B * m), sn((size_t)B * m), g((size_t)B * (m + 1)),
+      y((size_t)B * KM);
+  auto h = [&](int b, int i, int j) -> double& { return H[((size_t)b * (m + 1) + i) * m + j]; };
+  auto rel = [&](int b, double r) { return wn[b] > 0.0 ? r / wn[b] : r; };
+  bool conv = false;
+  while (true) {
+    // true residual r0 = w - C u
+    s = gmres_residual(p, w, u, Vi(0), false);
+    if (s != AAO_OK) return s;
+    s = gmres_dots(p, w, Vi(0), 1, Vi(0), dot.data());
+    if (s != AAO_OK) return s;
+    double worst = 0.0;
+    for (int b = 0; b < B; ++b) {
+      nrm[b] = std::sqrt(dot[(size_t)b * KM]);
+      worst = std::max(worst, rel(b, nrm[b]));
+    }
+    if (!std::isfinite(worst)) return fail(AAO_ENAN, "GMRES residual is not finite");
+    o.res_rel = worst;
+    if (worst <= tol) {
+      conv = true;
+      break;
+    }
+    if (o.steps >= max_steps) break;
+    o.cycles += 1;
+    // v_0 = r0 / ||r0|| per instance (an instance already solved keeps v_0 = 0)
+    for (int b = 0; b < B; ++b) scl[b] = nrm[b] > 0.0 ? 1.0 / nrm[b] : 0.0;
+    s = gmres_axpy(p, w, Vi(0), Vi(0), scl.data(), nullptr, 0, nullptr, nullptr);
+    if (s != AAO_OK) return s;
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    for (int b = 0; b < B; ++b) g[(size_t)b * (m + 1)] = nrm[b];
+    int jj = 0;
+    for (int j = 0; j < m; ++j) {
+      const double alpha = alphas ? alphas[std::min(o.steps, n_alphas - 1)] : a_def;
+      SweepOut so;
+      s = gmres_precond(p, Vi(j), Zi(j), alpha, so);
+      if (s != AAO_OK) return s;
+      // V_{j+1} <- -C z_j, then Gram-Schmidt twice against V_0 .. V_j
+      s = gmres_residual(p, w, Zi(j), Vi(j + 1), true);
+      if (s != AAO_OK) return s;
+      s = gmres_dots(p, w, w.V, j + 1, Vi(j + 1), h1.data());
+      if (s != AAO_OK) return s;
+      std::vector<double> m1(B, -1.0), p1(B, 1.0);
+      s = gmres_axpy(p, w, Vi(j + 1), Vi(j + 1), m1.data(), w.V, j + 1, h1.data(), nullptr);
+      if (s != AAO_OK) return s;
+      s = gmres_dots(p, w, w.V, j + 1, Vi(j + 1), h2.data());
+      if (s != AAO_OK) return s;
+      for (size_t q = 0; q < h2.size(); ++q) h2[q] = -h2[q];
+      s = gmres_axpy(p, w, Vi(j + 1), Vi(j + 1), p1.data(), w.V, j + 1, h2.data(), nrm.data());
+      if (s != AAO_OK) return s;
+      double worst_est = 0.0;
+      for (int b = 0; b < B; ++b) {
+        for (int i = 0; i <= j; ++i) h(b, i, j) = -h1[(size_t)b * KM + i] - h2[(size_t)b * KM + i];
+        const double hn = std::sqrt(nrm[b]);
+        h(b, j + 1, j) = hn;
+        scl[b] = hn > 0.0 ? 1.0 / hn : 0.0;
+        // earlier rotations, then a new one that zeroes h(j + 1, j)
+        for (int i = 0; i < j; ++i) {
+          const double a0 = h(b, i, j), a1 = h(b, i + 1, j);
+          h(b, i, j) = cs[(size_t)b * m + i] * a0 + sn[(size_t)b * m + i] * a1;
+          h(b, i + 1, j) = -sn[(size_t)b * m + i] * a0 + cs[(size_t)b * m + i] * a1;
+        }
+        const double r = std::hypot(h(b, j, j), h(b, j + 1, j));
+        const double c = r > 0.0 ? h(b, j, j) / r : 1.0, sj = r > 0.0 ? h(b, j + 1, j) / r : 0.0;
+        cs[(size_t)b * m + j] = c;
+        sn[(size_t)b * m + j] = sj;
+        h(b, j, j) = r;
+        h(b, j + 1, j) = 0.0;
+        double& gj = g[(size_t)b * (m + 1) + j];
+        g[(size_t)b * (m + 1) + j + 1] = -sj * gj;
+        gj = c * gj;
+        worst_est = std::max(worst_est, rel(b, std::fabs(g[(size_t)b * (m + 1) + j + 1])));
+      }
+      s = gmres_axpy(p, w, Vi(j + 1), Vi(j + 1), scl.data(), nullptr, 0, nullptr, nullptr);
+      if (s != AAO_OK) return s;
+      if (o.steps < AAO_MAX_HIST) {
+        o.alpha[o.steps] = alpha;
+        o.res_est[o.steps] = worst_est;
+        o.inner_mean[o.steps] = so.inner_mean;
+        o.inner_max[o.steps] = so.inner_max;
+      }
+      o.steps += 1;
+      jj = j + 1;
+      if (!std::isfinite(worst_est)) return fail(AAO_ENAN, "GMRES least-squares residual is not finite");
+      if (worst_est <= tol || o.steps >= max_steps) break;
+    }
+    // y = R^{-1} g (upper triangular jj x jj per instance); u += Z y
+    for (int b = 0; b < B; ++b) {
+      for (int i = jj - 1; i >= 0; --i) {
+        double acc = g[(size_t)b * (m + 1) + i];
+        for (int k = i + 1; k < jj; ++k) acc -= h(b, i, k) * y[(size_t)b * KM + k];
+        y[(size_t)b * KM + i] = h(b, i, i) != 0.0 ? acc / h(b, i, i) : 0.0;
+      }
+    }
+    std::vector<double> one(B, 1.0);
+    s = gmres_axpy(p, w, u, u, one.data(), w.Z, jj, y.data(), nullptr);
+    if (s != AAO_OK) return s;
+  }
+  o.converged = conv ? 1 : 0;
+  if (!conv) return fail(AAO_ENOCONV, "GMRES: max_steps reached without meeting tol");
+  return AAO_OK;
+}
+
 aao_status aao_solve_windows(aao_plan_t p, double* u, int n_windows, const double* frc_all, const double* alphas,
                              int n_alphas, double m0, double tol, int stop_rule, int max_iter,
                              aao_solve_info* infos) {
@@ -1332,6 +1617,7 @@ aao_status aao_reset_stats(aao_plan_t p) {
   std::memset(&p->stats, 0, sizeof(p->stats));
   std::memset(p->work_first, 0, sizeof(p->work_first));
   std::memset(p->work_later, 0, sizeof(p->work_later));
+  std::memset(p->bytes_direct, 0, sizeof(p->bytes_direct));
   return AAO_OK;
 }
 
@@ -1357,6 +1643,7 @@ aao_status aao_get_stats(aao_plan_t p, aao_kernel_stats* out) {
     out->elements[k.c] = p->work_first[k.c] + p->work_later[k.c];
     out->bytes[k.c] = cs * (k.later * p->work_later[k.c] + k.first * p->work_first[k.c]);
   }
+  for (int c = 0; c < AAO_NUM_KERNELS; ++c) out->bytes[c] += p->bytes_direct[c];
   return AAO_OK;
 }
 
@@ -1404,6 +1691,7 @@ void aao_destroy(aao_plan_t p) {
   if (p->htab) (void)hipHostFree(p->htab);
   if (p->hread) (void)hipHostFree(p->hread);
   if (p->hlist) (void)hipHostFree(p->hlist);
+  if (p->hgm) (void)hipHostFree(p->hgm);
   for (auto e : p->slot_ev)
     if (e) (void)hipEventDestroy(e);
   delete p;

@@ -141,7 +141,7 @@ enum PartialQ {
 
 enum KernelClass {
   KC_FWD = 0, KC_BWD, KC_COCG_A, KC_COCG_B, KC_BICG_1, KC_BICG_2, KC_BICG_3,
-  KC_FFT_INNER, KC_RESIDUAL, KC_MISC, KC_INIT, KC_GRAD
+  KC_FFT_INNER, KC_RESIDUAL, KC_MISC, KC_INIT, KC_GRAD, KC_GMRES
 };
 
 // Launchers (return hipSuccess or the launch error).
@@ -160,6 +160,17 @@ hipError_t launch_norms_bn(const double* v, int B, int N, double* part, int npar
 hipError_t launch_wnorms(int M, const FwdArgs& a, int B, double* part, int nparts, hipStream_t st);
 hipError_t launch_cg_init(bool f32, const CgArgs& a, int nact, hipStream_t st);
 hipError_t launch_cg_pass(bool f32, const CgArgs& a, int k, int nact, hipStream_t st);
+
+// Outer flexible GMRES (Gram-Schmidt over [B][D] FP64 vectors, basis vector i
+// at i * stride): part[(b nblk + blk) K + i] with K = gmres_bucket(nvec) holds
+// block shares of <V_i[b], t[b]>; out = s[b] in + sum_i c[b][i] V_i with
+// block shares of ||out[b]||^2 in part[b nblk + blk] (part may be null).
+constexpr int kGmresMax = 32;
+int gmres_bucket(int nvec);
+hipError_t launch_mdot(const double* V, size_t stride, int nvec, const double* t, int64_t D, int B, double* part,
+                       int nblk, hipStream_t st);
+hipError_t launch_maxpy(double* out, const double* in, const double* s, const double* V, size_t stride, int nvec,
+                        const double* c, int64_t D, int B, double* part, int nblk, hipStream_t st);
 hipError_t launch_cg_scalars(const CgArgs& a, int k, int nact, hipStream_t st);
 size_t cg_lds_bytes(bool f32, const CgArgs& a);
 int cg_ring_slots(const CgArgs& a);
