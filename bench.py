@@ -33,6 +33,7 @@ def parse():
     ap.add_argument("--no-speedup", action="store_true", help="skip the mixed-vs-FP64 comparison")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel events in the timed region")
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain device copy (counter scale)")
+    ap.add_argument("--no-gmres", action="store_true", help="skip the outer-GMRES comparison")
     ap.add_argument("--all-configs", action="store_true",
                     help="also time every workload once against the oracle (adds about a minute)")
     return ap.parse_args()
@@ -140,6 +141,28 @@ def speedup_block(np, torch, wl, plan_for, with_oracle):
         out["speedup"] = out["fp64"]["time_to_solution_s"] / out["mixed"]["time_to_solution_s"]
         res[inner] = out
     return res
+
+
+def gmres_block(np, torch, w, plan, u0, ref, richardson_s):
+    """The same workload solved by flexible GMRES(10) with C_alpha as right
+    preconditioner (default alpha), to a relative residual of 1e-12, beside
+    the Richardson time; error against the oracle when it was computed."""
+    u = torch.empty(plan.shape, dtype=torch.float64, device="cuda")
+    plan.solve_gmres(u, restart=10, tol=1e-12, max_steps=60)  # warm-up (workspace allocation)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = 3
+    for _ in range(n):
+        _, info = plan.solve_gmres(u, restart=10, tol=1e-12, max_steps=60)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / n
+    r = {"restart": 10, "tol_rel_residual": 1e-12, "time_to_solution_s": el, "steps": info["steps"],
+         "alpha": float("%.3e" % info["alpha"][0]), "res_rel": info["res_rel"],
+         "inner_iters_mean": [round(v, 1) for v in info["inner_mean"]],
+         "richardson_time_to_solution_s": richardson_s, "speedup_vs_richardson": richardson_s / el}
+    if ref is not None:
+        r["rel_l2_vs_oracle"] = float(np.linalg.norm(u.cpu().numpy() - ref) / np.linalg.norm(ref))
+    return r
 
 
 def copy_bandwidth(torch):
@@ -307,6 +330,10 @@ def main():
             "time_to_solution_s": t_or}
         out["parity"] = {"rel_l2_vs_oracle": float(np.linalg.norm(u_gpu - ref) / np.linalg.norm(ref))}
         out["gpu_time_to_solution_s"] = elapsed / args.steps
+    if not args.no_gmres:
+        print("bench: outer GMRES on %s" % w.name, file=sys.stderr, flush=True)
+        out["outer_gmres"] = gmres_block(np, torch, w, plan, u0, None if args.no_cpu_baseline else ref,
+                                         elapsed / args.steps)
     if not args.no_speedup:
         out["mixed_vs_fp64"] = speedup_block(np, torch, wl, plan_for, not args.no_cpu_baseline)
     if args.all_configs:
