@@ -192,8 +192,7 @@ def all_configs(np, torch, wl, plan_for):
     runs = []
     for name, w in wl.WORKLOADS.items():
         runs.append((name, w))
-        pow2 = (w.nx & (w.nx - 1)) == 0 and (w.ny & (w.ny - 1)) == 0
-        if pow2 and w.inner != "fft":  # the spatial-FFT direct inner solve on the same problem
+        if w.inner != "fft":  # the spatial-FFT direct inner solve on the same problem (any grid size)
             runs.append((name + "+fft", w.with_(inner="fft", inner_tol=1e-15 if w.precision == "fp64" else 1e-7)))
     for name, w in runs:
         print("bench: config %s" % name, file=sys.stderr, flush=True)

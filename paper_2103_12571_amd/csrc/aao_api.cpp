@@ -37,6 +37,25 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Bluestein length of a transform of n points: 0 if n is a power of two, else
+// the smallest power of two >= 2n - 1.
+int64_t blue_len(int64_t n) {
+  if (is_pow2(n)) return 0;
+  int64_t P = 1;
+  while (P < 2 * n - 1) P <<= 1;
+  return P;
+}
+
+// Points of one transform line held in LDS.
+int64_t fft_line(int64_t n) { return is_pow2(n) ? n : blue_len(n); }
+
+// Largest divisor of n that is at most cap (at least 1).
+int largest_divisor(int n, int cap) {
+  for (int d = std::max(1, std::min(n, cap)); d > 1; --d)
+    if (n % d == 0) return d;
+  return 1;
+}
+
 int ilog2(int64_t v) {
   int l = 0;
   while ((int64_t(1) << l) < v) ++l;
@@ -97,6 +116,7 @@ struct aao_plan {
   int cgTX = 1, cgTY = 1, cg_ntx = 1, cg_nty = 1, cg_ntiles = 1, Rx = 0, Ry = 0;
   int cgTXs = 0, cgTYs = 0, cg_ntxs = 0, cg_ntiles_s = 0;  // small tiling (cg_ntiles_s = 0: none)
   int fft_rows = 1, fft_cols = 1;
+  int Px = 0, Py = 0;  // Bluestein lengths of x / y for the FFT inner solve (0: power of two)
   int* hlist = nullptr;      // pinned: (count, tag) of the active-system snapshots, per slot
   int snap_tag = 0;          // tag of the latest snapshot
   bool f32 = false;
@@ -104,7 +124,7 @@ struct aao_plan {
   // library-owned device tables and pinned staging
   char* dtab = nullptr;
   size_t off_tw = 0, off_sf = 0, off_sb = 0, off_m1 = 0, off_m2 = 0, off_sh = 0, off_q = 0,
-         off_wx = 0, off_wy = 0, off_hostend = 0, tab_bytes = 0;
+         off_wx = 0, off_wy = 0, off_bx = 0, off_by = 0, off_hostend = 0, tab_bytes = 0;
   char* htab = nullptr;      // pinned mirror of the alpha-dependent tables (two slots)
   char* hread = nullptr;     // pinned readback area
   size_t hread_bytes = 0;
@@ -537,6 +557,20 @@ aao_status inner_solve_fft(aao_plan* p, int adj, int nsys) {
   f.rows = p->fft_rows;
   f.cols = p->fft_cols;
   f.norm = (double)p->N;
+  auto blue = [&](int n, int P, size_t off) {
+    aao::BlueDim d{};
+    if (!P) return d;
+    const double2* base = reinterpret_cast<const double2*>(p->dtab + off);
+    d.P = P;
+    d.logP = ilog2(P);
+    d.W = base;
+    d.ch = base + P;
+    d.Bf = base + P + n;
+    d.Bi = base + 2 * P + n;
+    return d;
+  };
+  f.bx = blue(p->nx, p->Px, p->off_bx);
+  f.by = blue(p->ny, p->Py, p->off_by);
   HIPCHK(timed(p, aao::KC_FFT_INNER, [&] { return aao::launch_fft_solve(p->f32, f, nsys, p->stream); }));
   p->work_later[aao::KC_FFT_INNER] += (double)nsys * p->N;
   return AAO_OK;
@@ -661,6 +695,20 @@ aao_status alloc_tables(aao_plan* p) {
   HIPCHK(hipMemcpyAsync(p->dtab + p->off_wx, wx.data(), wx.size() * sizeof(double2), hipMemcpyHostToDevice, p->stream));
   close_run(p);
   HIPCHK(hipMemcpyAsync(p->dtab + p->off_wy, wy.data(), wy.size() * sizeof(double2), hipMemcpyHostToDevice, p->stream));
+  // Bluestein tables of the dimensions that are not powers of two
+  std::vector<double2> bt[2];
+  for (int dim = 0; dim < 2; ++dim) {
+    const int n = dim == 0 ? p->nx : p->ny, P = dim == 0 ? p->Px : p->Py;
+    if (!P) continue;
+    std::vector<aao::cd> W, ch, Bf, Bi;
+    aao::bluestein_tables(n, P, W, ch, Bf, Bi);
+    std::vector<double2>& b = bt[dim];
+    for (const auto* v : {&W, &ch, &Bf, &Bi})
+      for (const aao::cd& z : *v) b.push_back(make_double2(z.real(), z.imag()));
+    close_run(p);
+    HIPCHK(hipMemcpyAsync(p->dtab + (dim == 0 ? p->off_bx : p->off_by), b.data(), b.size() * sizeof(double2),
+                          hipMemcpyHostToDevice, p->stream));
+  }
   close_run(p);
   HIPCHK(hipStreamSynchronize(p->stream));
   p->slot_alpha[0] = p->slot_alpha[1] = -1;
@@ -776,9 +824,11 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   if (cfg->inner != AAO_INNER_COCG && cfg->inner != AAO_INNER_BICGSTAB && cfg->inner != AAO_INNER_FFT)
     return fail(AAO_EINVAL, "unknown inner solver");
   if (cfg->inner == AAO_INNER_FFT) {
+    // one transform line (n, or the Bluestein length P >= 2n - 1) must fit 64 KiB of LDS
     const int64_t cs = cfg->precision == AAO_MIXED ? 8 : 16;
-    if (!is_pow2(nx) || !is_pow2(ny) || nx * cs > 65536 || ny * cs > 65536)
-      return fail(AAO_EINVAL, "FFT inner solve needs nx, ny powers of two with n * sizeof(complex) <= 64 KiB");
+    if (fft_line(nx) * cs > 65536 || fft_line(ny) * cs > 65536)
+      return fail(AAO_EINVAL, "FFT inner solve: a transform line (n if a power of two, else the Bluestein "
+                              "length P >= 2n - 1) times sizeof(complex) must not exceed 64 KiB");
   }
   if (!(cfg->inner_tol > 0) || cfg->inner_maxit < 1) return fail(AAO_EINVAL, "bad inner tolerance / iteration cap");
 
@@ -848,10 +898,16 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   // batched inner solves: S systems, wps workgroups per system
   p->S = p->B * p->Lh * p->M;
   p->nvec = (p->inner == AAO_INNER_COCG) ? 5 : (p->inner == AAO_INNER_FFT ? 2 : 9);
+  if (p->inner == AAO_INNER_FFT) {
+    p->Px = (int)blue_len(p->nx);
+    p->Py = p->ny > 1 ? (int)blue_len(p->ny) : 0;
+  }
   if (p->inner == AAO_INNER_FFT && p->ny > 1) {
+    // rows (columns) per workgroup: a divisor of ny (nx) within the LDS budget
     const int cs = (int)p->csize;
-    p->fft_rows = std::max(1, std::min(p->ny, AAO_FFT_ROW_LDS_KB * 1024 / (p->nx * cs)));
-    p->fft_cols = std::max(1, std::min(p->nx, AAO_FFT_COL_LDS_KB * 1024 / (p->ny * cs)));
+    const int lx = (int)fft_line(p->nx), ly = (int)fft_line(p->ny);
+    p->fft_rows = largest_divisor(p->ny, AAO_FFT_ROW_LDS_KB * 1024 / (lx * cs));
+    p->fft_cols = largest_divisor(p->nx, AAO_FFT_COL_LDS_KB * 1024 / (ly * cs));
   }
   {
     const int target = 4096;
@@ -947,6 +1003,11 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   t = align256(t + (size_t)p->nx * sizeof(double2));
   p->off_wy = t;
   t = align256(t + (size_t)p->ny * sizeof(double2));
+  // Bluestein blocks: W (P), ch (n), Bf (P), Bi (P)
+  p->off_bx = t;
+  t = align256(t + (p->Px ? (size_t)(3 * p->Px + p->nx) * sizeof(double2) : 0));
+  p->off_by = t;
+  t = align256(t + (p->Py ? (size_t)(3 * p->Py + p->ny) * sizeof(double2) : 0));
   p->off_sf = t;
   t = align256(t + (size_t)p->L * sizeof(double));
   p->off_sb = t;

@@ -286,4 +286,55 @@ std::string freq_table(const std::vector<double>& t, const std::vector<double>& 
   return "";
 }
 
+namespace {
+
+// In-place unnormalised forward DFT (e^{-2 pi i jk / P}) of a power-of-two
+// length: bit-reversal permutation, then radix-2 butterflies.
+void dft_pow2(std::vector<cd>& v) {
+  const int P = (int)v.size();
+  for (int i = 1, j = 0; i < P; ++i) {
+    int bit = P >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(v[i], v[j]);
+  }
+  for (int len = 2; len <= P; len <<= 1) {
+    for (int k = 0; k < len / 2; ++k) {
+      const double ang = -2.0 * M_PI * k / len;
+      const cd w(std::cos(ang), std::sin(ang));
+      for (int i = 0; i < P; i += len) {
+        const cd a = v[i + k], b = w * v[i + k + len / 2];
+        v[i + k] = a + b;
+        v[i + k + len / 2] = a - b;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+void bluestein_tables(int n, int P, std::vector<cd>& W, std::vector<cd>& ch, std::vector<cd>& Bf,
+                      std::vector<cd>& Bi) {
+  W.resize(P);
+  for (int k = 0; k < P; ++k) W[k] = cd(std::cos(2.0 * M_PI * k / P), std::sin(2.0 * M_PI * k / P));
+  ch.resize(n);
+  for (int j = 0; j < n; ++j) {
+    const long long q = ((long long)j * j) % (2LL * n);  // e^{-i pi j^2 / n} has period 2n in j^2
+    const double ang = -M_PI * (double)q / n;
+    ch[j] = cd(std::cos(ang), std::sin(ang));
+  }
+  Bf.assign(P, cd(0, 0));
+  Bi.assign(P, cd(0, 0));
+  for (int m = 0; m < n; ++m) {
+    Bf[m] = std::conj(ch[m]);
+    Bi[m] = ch[m];
+    if (m > 0) {
+      Bf[P - m] = std::conj(ch[m]);
+      Bi[P - m] = ch[m];
+    }
+  }
+  dft_pow2(Bf);
+  dft_pow2(Bi);
+}
+
 }  // namespace aao

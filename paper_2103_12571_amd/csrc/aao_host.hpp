@@ -42,4 +42,12 @@ std::string freq_table(const std::vector<double>& t, const std::vector<double>& 
 // Small dense complex inverse (Gauss-Jordan, partial pivoting).  False if singular.
 bool invert(int n, const std::vector<cd>& A, std::vector<cd>& Ainv);
 
+// Tables of Bluestein's chirp-z DFT of length n through cyclic convolutions of
+// length P (a power of two >= 2n - 1): W[k] = e^{+2 pi i k / P} (k < P),
+// ch[j] = e^{-i pi j^2 / n} (j < n, with j^2 reduced mod 2n first), and the
+// length-P DFTs Bf of the forward filter (conj(ch_m) at m and P - m) and Bi of
+// the inverse filter (ch_m at m and P - m).
+void bluestein_tables(int n, int P, std::vector<cd>& W, std::vector<cd>& ch, std::vector<cd>& Bf,
+                      std::vector<cd>& Bi);
+
 }  // namespace aao

@@ -120,6 +120,16 @@ struct KrylovArgs {
   int maxit;
 };
 
+// A spatial dimension of length n that is not a power of two is transformed
+// by Bluestein's chirp-z algorithm: cyclic convolutions of length P (a power
+// of two, P >= 2n - 1).  W[k] = e^{+2 pi i k / P} (k < P); ch[j] = e^{-i pi
+// j^2 / n} (j < n); Bf, Bi: length-P DFTs of the forward filter (conj(ch) at
+// m and P - m) and of the inverse filter (ch).  P = 0: radix-2 directly.
+struct BlueDim {
+  int P, logP;
+  const double2 *W, *ch, *Bf, *Bi;
+};
+
 // Spatial-FFT direct solve (row a3 for periodic constant-coefficient A).
 struct FftArgs {
   void* R;                // right-hand sides, overwritten (2D)
@@ -129,8 +139,9 @@ struct FftArgs {
   const double2* Wy;      // e^{+2 pi i k / ny}, k < ny
   Taps taps;
   int nx, ny, N, lognx, logny;
-  int rows, cols;         // rows / columns per workgroup in the 2D passes
+  int rows, cols;         // rows / columns per workgroup in the 2D passes (divide ny / nx)
   double norm;            // nx * ny
+  BlueDim bx, by;         // Bluestein data of x / y (P = 0 where n is a power of two)
 };
 
 // Partial-sum quantities of the Krylov kernels: part[q][system][chunk].

@@ -68,7 +68,9 @@ def test_setup_is_host_only_and_destroy():
     (dict(nodes=[0.3, 0.8, 0.9]), bd.AAO_EINVAL),  # last node must be 1
     (dict(nodes=[0.5, 0.2, 1.0]), bd.AAO_EINVAL),
     (dict(inner=bd.AAO_INNER_FFT), bd.AAO_OK),                     # nx = 16: power of two
-    (dict(inner=bd.AAO_INNER_FFT, nx=12), bd.AAO_EINVAL),           # FFT needs powers of two
+    (dict(inner=bd.AAO_INNER_FFT, nx=12), bd.AAO_OK),               # Bluestein: P = 32
+    (dict(inner=bd.AAO_INNER_FFT, nx=2048), bd.AAO_OK),             # 2048 x 16 B = 32 KiB
+    (dict(inner=bd.AAO_INNER_FFT, nx=2049), bd.AAO_EINVAL),         # Bluestein P = 8192: 128 KiB of LDS
     (dict(inner=bd.AAO_INNER_FFT, nx=8192), bd.AAO_EINVAL),         # row exceeds 64 KiB of LDS
     (dict(prec=7), bd.AAO_EINVAL),
 ])

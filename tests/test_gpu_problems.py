@@ -95,7 +95,10 @@ def test_upwind_advection_parity(name, w):
     assert e < 1e-10
 
 
-@pytest.mark.parametrize("w,tol", [(HEAT, 1e-9), (ADV, 1e-9)])
+@pytest.mark.parametrize("w,tol", [(HEAT, 1e-9), (ADV, 1e-9),
+                                   (HEAT.with_(inner="fft", inner_tol=1e-15), 1e-9),
+                                   (ADV.with_(inner="fft", inner_tol=1e-15), 1e-9)],
+                         ids=["heat_cocg", "adv_bicgstab", "heat_fft", "adv_fft"])
 def test_table1_middle_column_reaches_tolerance(w, tol):
     """Table 1 (tolerance 1e-9): the GPU solution at T is within 1e-9 of the
     exact solution and matches the sequential oracle."""
