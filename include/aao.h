@@ -76,7 +76,9 @@ enum { AAO_INNER_COCG = 0,      /* batched COCG: needs A = A^T (complex-symmetri
                                    shifted systems) */
        AAO_INNER_BICGSTAB = 1,  /* batched BiCGStab: any A */
        AAO_INNER_FFT = 2        /* spatial-FFT direct solve (exact for periodic
-                                   constant-coefficient A); nx, ny powers of two */ };
+                                   constant-coefficient A); any nx, ny: lengths that are
+                                   not powers of two use Bluestein's chirp-z transform
+                                   (length P = the power of two >= 2n - 1) */ };
 
 enum { AAO_STOP_LASTSTEP = 0,   /* ||u_L^{k+1} - u_L^k||_inf <= tol (Sec. 3.2, Alg. 2) */
        AAO_STOP_RESIDUAL = 1    /* ||w - C u||_2 / ||w||_2 <= tol */ };
@@ -137,7 +139,8 @@ typedef struct {
  * Computes nodes and Q (eq. (collocation)) on the host, uploads the stencil and
  * the DFT twiddles.  hip_stream: a hipStream_t (NULL = default stream).
  * Errors: EINVAL for bad sizes/pointers, COCG with a non-symmetric stencil,
- * FFT inner solve with non-power-of-two nx/ny; EHIP. */
+ * FFT inner solve whose transform line (n, or P >= 2n - 1 for Bluestein) times
+ * sizeof(complex) exceeds 64 KiB; EHIP. */
 aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stream,
                      aao_plan_t* out);
 
