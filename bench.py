@@ -140,6 +140,32 @@ def speedup_block(np, torch, wl, plan_for, with_oracle):
             torch.cuda.empty_cache()
         out["speedup"] = out["fp64"]["time_to_solution_s"] / out["mixed"]["time_to_solution_s"]
         res[inner] = out
+    # the same comparison with the outer flexible GMRES (COCG inner, default
+    # alpha from each path's inner tolerance), to a relative residual of 1e-9
+    out = {}
+    for name, w in (("fp64", base.with_(precision="fp64", inner="cocg", inner_tol=1e-12)),
+                    ("mixed", base.with_(precision="mixed", inner="cocg", inner_tol=1e-6))):
+        plan = plan_for(w)
+        plan.set_u0(torch.as_tensor(u0, device="cuda"))
+        u = torch.empty(plan.shape, dtype=torch.float64, device="cuda")
+        print("bench: outer GMRES %s path on %s" % (name, w.name), file=sys.stderr, flush=True)
+        plan.solve_gmres(u, restart=10, tol=1e-9, max_steps=40)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            _, info = plan.solve_gmres(u, restart=10, tol=1e-9, max_steps=40)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / 2
+        r = {"time_to_solution_s": el, "steps": info["steps"], "inner_tol": w.inner_tol,
+             "alpha": float("%.3e" % info["alpha"][0]), "res_rel": info["res_rel"],
+             "inner_iters_mean": [round(v, 1) for v in info["inner_mean"]]}
+        if ref is not None:
+            r["rel_l2_vs_oracle"] = float(np.linalg.norm(u.cpu().numpy() - ref) / np.linalg.norm(ref))
+        out[name] = r
+        del plan, u
+        torch.cuda.empty_cache()
+    out["speedup"] = out["fp64"]["time_to_solution_s"] / out["mixed"]["time_to_solution_s"]
+    res["cocg_outer_gmres"] = out
     return res
 
 
