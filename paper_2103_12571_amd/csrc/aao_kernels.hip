@@ -248,16 +248,17 @@ __global__ __launch_bounds__(kBlock) void k_bwd(BwdArgs a) {
   const int ncol = M * P;
   const InV* in = reinterpret_cast<const InV*>(a.in);
 
+  const int logP = a.logTN - 1;
   for (int idx = threadIdx.x; idx < a.Lh * P; idx += kBlock) {
-    const int j = idx / P;
-    const int p = idx - j * P;
+    const int j = idx >> logP;
+    const int p = idx & (P - 1);
     const int n = n0 + 2 * p;
+    const InV* ij = in + ((size_t)b * a.Lh + j) * M * N + n;
     double2 xa[M], xb[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-      const size_t o = (((size_t)b * a.Lh + j) * M + m) * (size_t)N + n;
-      xa[m] = (n < N) ? to_d2(in[o]) : mk(0, 0);
-      xb[m] = (n + 1 < N) ? to_d2(in[o + 1]) : mk(0, 0);
+      xa[m] = (n < N) ? to_d2(ij[m * N]) : mk(0, 0);
+      xb[m] = (n + 1 < N) ? to_d2(ij[m * N + 1]) : mk(0, 0);
     }
     const double2* mx = a.mix + (size_t)j * M * M;
     const bool selfconj = (j == 0) || (2 * j == L);
@@ -292,20 +293,22 @@ __global__ __launch_bounds__(kBlock) void k_bwd(BwdArgs a) {
   }
   lds_fft<true>(cre, cim, twr, twi, L, a.logL, ncol);
 
+  // as in k_fwd every row lm this thread visits is at the same spatial point
   const int lmon = ADJ ? 0 : L - 1;
   double dmax = 0.0;
-  for (int idx = threadIdx.x; idx < L * M * TN; idx += kBlock) {
-    const int nl = idx & (TN - 1);
-    const int lm = idx >> a.logTN;
-    const int m = lm % M;
-    const int l = lm / M;
-    const int n = n0 + nl;
-    if (n >= N) continue;
-    const double d = ((nl & 1) ? cim : cre)[lm * P + (nl >> 1)] * a.scale[l];
-    const size_t o = (((size_t)b * L + l) * M + m) * (size_t)N + n;
-    if (MODE == 0) a.u[o] += d;
-    else a.u[o] = d;
-    if (l == lmon) dmax = fmax(dmax, fabs(d));
+  const int nl = threadIdx.x & (TN - 1);
+  const int n = n0 + nl;
+  if (n < N) {
+    const double* src = ((nl & 1) ? cim : cre) + (nl >> 1);
+    double* ub = a.u + (size_t)b * L * M * N + n;  // this instance's u at point n
+    for (int lm = threadIdx.x >> a.logTN; lm < L * M; lm += (kBlock >> a.logTN)) {
+      const int l = lm / M;
+      const double d = src[lm * P] * a.scale[l];
+      double* o = ub + (size_t)lm * N;
+      if (MODE == 0) *o += d;
+      else *o = d;
+      if (l == lmon) dmax = fmax(dmax, fabs(d));
+    }
   }
   dmax = block_max(dmax, sh);
   if (threadIdx.x == 0) a.part[(size_t)blockIdx.y * gridDim.x + tile] = dmax;
