@@ -266,11 +266,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   }
   // the state is read with workgroup-uniform addresses (scalar loads)
   const SysState* st0 = a.st + s;
-  const int act0 = st0->active;
   // A system that stopped in an earlier pass can still be on the lagged
-  // list; it leaves before its vectors are requested (nothing below writes
-  // for it).  The flag is workgroup-uniform.
-  if (!act0) return;
+  // list; its workgroups leave before requesting any vector (nothing below
+  // writes for it).  Every wave reads the flag itself, so it must not change
+  // during this pass: in fused mode tile 0 of this very pass may stop the
+  // system, so the test is on the pass that stopped it (a concurrent write
+  // can only turn "never" into k, and neither leaves early); in non-fused
+  // mode a separate kernel stops systems between passes.
+  if (a.fused ? st0->stop_pass < k : !st0->active) return;
   const double bb0 = a.fused ? st0->bb : 0.0;
   const double2 s0 = a.fused ? st0->gamma2[(k + 1) & 1] : st0->alpha;
   const double2 s1 = a.fused ? st0->alpha2[(k + 1) & 1] : st0->beta;
@@ -304,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
     if (t == 0) {
       int go = 0;
       CgStep c{0, mk(0, 0), mk(0, 0)};
-      if (act0) {
+      {
         const double bb = (k == 0) ? pv[4] : bb0;
         c = cg_advance(k, mk(pv[0], pv[1]), mk(pv[2], pv[3]), pv[4], bb, a.tol2, a.maxit, s0, s1);
         go = c.dec == 0;
@@ -319,6 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
             st->active = 0;
             st->iters = k;
             st->flag = c.dec - 1;
+            st->stop_pass = k;
           }
         }
       }
@@ -327,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
       sc[1] = c.be;
     }
   } else if (t == 0) {
-    act = act0;
+    act = 1;  // non-fused: an inactive system left above
     sc[0] = s0;
     sc[1] = s1;
   }

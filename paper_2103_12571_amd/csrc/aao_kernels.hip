@@ -648,6 +648,7 @@ __global__ void k_krylov_init(SysState* st, int n) {
     z.iters = 0;
     z.flag = 0;
     z.breakdown = 0;
+    z.stop_pass = 0x7fffffff;
     z.rho = mk(1, 0);
     z.alpha = mk(1, 0);
     z.omega = mk(1, 0);

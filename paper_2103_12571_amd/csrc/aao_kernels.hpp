@@ -28,6 +28,7 @@ struct SysState {
   int iters;      // iterations done when it stopped
   int flag;       // 0 converged, 1 hit the iteration cap, 2 breakdown
   int breakdown;  // set by an update kernel, consumed by the next matvec kernel
+  int stop_pass;  // fused COCG: the pass that stopped the system (INT_MAX while active)
   double2 rho;    // BiCGStab: rho_k
   double2 alpha;  // BiCGStab, COCG: alpha_k
   double2 omega;  // BiCGStab: omega_k
