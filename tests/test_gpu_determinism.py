@@ -31,6 +31,7 @@ def test_solves_are_bitwise_reproducible_under_concurrency(name, w):
         plans[0].solve(us[0], tol=w.tol, max_iter=50)
     streams[0].synchronize()
     ref = us[0].clone()
+    torch.cuda.synchronize()  # the copy is read from the other streams below
     bad = []
 
     def run(i, n):
