@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel events in the timed region")
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain device copy (counter scale)")
     ap.add_argument("--no-gmres", action="store_true", help="skip the outer-GMRES comparison")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (row a7) timing")
     ap.add_argument("--all-configs", action="store_true",
                     help="also time every workload once against the oracle (adds about a minute)")
     return ap.parse_args()
@@ -189,6 +190,54 @@ def gmres_block(np, torch, w, plan, u0, ref, richardson_s):
     if ref is not None:
         r["rel_l2_vs_oracle"] = float(np.linalg.norm(u.cpu().numpy() - ref) / np.linalg.norm(ref))
     return r
+
+
+def adjoint_block(np, torch, wl, plan_for, with_oracle):
+    """Row a7 at the adjoint workload (2D advection-diffusion 512^2, nu = 5e-3,
+    v = (1, 0.5), L = 64, M = 3, B = 8, complex64 inner solves): forward solve,
+    adjoint solve of C^T lambda = e_{L,M} (x) (u_{L,M} - u_target) and both
+    gradients, timed to the gradients; instance 0 against the oracle."""
+    w = wl.WORKLOADS["advdiff2d_512_adj"]
+    plan = plan_for(w)
+    u0 = wl.initial_batch(w)
+    plan.set_u0(torch.as_tensor(u0, device="cuda"))
+    ut = wl.target_batch(w)
+    utd = torch.as_tensor(ut, device="cuda")
+    al = [w.alpha] if w.alpha > 0 else None
+
+    def once():
+        u, info = plan.solve(tol=w.tol, stop=w.stop, max_iter=50, alphas=al)
+        lam, ainfo = plan.adjoint_solve(u[:, -1, -1, :] - utd, tol=w.tol, max_iter=50)
+        gu0, gnu = plan.grad(u, lam)
+        return u, lam, gu0, gnu, info, ainfo
+
+    print("bench: adjoint on %s" % w.name, file=sys.stderr, flush=True)
+    once()  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = 2
+    for _ in range(n):
+        u, lam, gu0, gnu, info, ainfo = once()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / n
+    sw = info["iterations"] + ainfo["iterations"]
+    res = {"workload": w.name, "dof": w.dof, "batch": w.batch, "precision": w.precision, "inner": w.inner,
+           "time_to_gradient_s": el, "forward_sweeps": info["iterations"], "adjoint_sweeps": ainfo["iterations"],
+           "dof_sweeps_per_s": w.dof * sw / el}
+    if with_oracle:
+        import oracle
+        op = oracle.stencil_for(w.kind, w.nx, w.ny, nu=w.nu, c=w.vel, order=w.order)
+        Q = oracle.collocation_matrix(oracle.radau_right_nodes(w.M))
+        t1 = time.perf_counter()
+        Uo = oracle.sequential_solve(op, Q, w.dt, u0[0], w.L, backend="spectral")
+        lo = oracle.adjoint_solve(op, Q, w.dt, Uo[-1, -1] - ut[0], w.L, backend="spectral")
+        g0, gn = oracle.gradients(op, Q, w.dt, Uo, lo)
+        res["oracle_instance_time_s"] = time.perf_counter() - t1
+        rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        res["instance0_rel_l2_vs_oracle"] = {"u": rel(u[0].cpu().numpy(), Uo), "lambda": rel(lam[0].cpu().numpy(), lo),
+                                             "dJ_du0": rel(gu0[0].cpu().numpy(), g0),
+                                             "dJ_dnu": abs(float(gnu[0]) - gn) / abs(gn)}
+    return res
 
 
 def copy_bandwidth(torch):
@@ -361,6 +410,8 @@ def main():
                                          elapsed / args.steps)
     if not args.no_speedup:
         out["mixed_vs_fp64"] = speedup_block(np, torch, wl, plan_for, not args.no_cpu_baseline)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_block(np, torch, wl, plan_for, not args.no_cpu_baseline)
     if args.all_configs:
         out["configs"] = all_configs(np, torch, wl, plan_for)
     print(json.dumps(out), flush=True)
