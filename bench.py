@@ -300,8 +300,8 @@ def all_configs(np, torch, wl, plan_for):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the hot path is built and measured on a single "
-              "MI355X; multi-GPU sharding is a design note, not part of this build.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs the sweep on a single MI355X "
+              "(sharding the time steps across GPUs is designed, not implemented).", file=sys.stderr)
         sys.exit(2)
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     import numpy as np

@@ -197,3 +197,15 @@ def test_test_problem_stencils_match_oracle(kind, order):
     assert set(mine) == set(op.weights)
     for k, v in op.weights.items():
         assert abs(mine[k] - v) <= 1e-13 * max(1.0, abs(v)), (k, mine[k], v)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asking for more exits with a message (and
+    touches no GPU on the way)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
