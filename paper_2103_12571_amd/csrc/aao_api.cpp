@@ -155,7 +155,8 @@ struct aao_plan {
   // elements processed per kernel class (first iteration / later iterations),
   // from the per-system iteration counts read back after each inner solve
   double work_first[AAO_NUM_KERNELS] = {}, work_later[AAO_NUM_KERNELS] = {};
-  double bytes_direct[AAO_NUM_KERNELS] = {};  // algorithmic bytes counted at launch (outer GMRES)
+  double bytes_direct[AAO_NUM_KERNELS] = {};  // algorithmic bytes counted directly (outer GMRES, fused COCG)
+  double elems_direct[AAO_NUM_KERNELS] = {};
   double* hgm = nullptr;                      // pinned: GMRES partial sums down, coefficients up
   size_t hgm_bytes = 0;
 
@@ -489,6 +490,21 @@ aao_status lag_begin(aao_plan* p, LagCheck& c, int nsys) {
   return AAO_OK;
 }
 
+// Complex words per element that the fused COCG passes of one system move
+// when it stopped in pass ks: pass k reads r (and p_{k-1} after the first)
+// and writes r and p; odd passes also write x (and read it after pass 1); a
+// stop in an odd pass applies the pending x update (reads p, writes x, reads
+// x after pass 1).
+double cocg_fused_words(int ks) {
+  double w = 0;
+  for (int k = 0; k < ks; ++k) {
+    w += (k > 0) ? 4 : 3;
+    if (k & 1) w += (k >= 3) ? 2 : 1;
+  }
+  if (ks & 1) w += (ks >= 3) ? 3 : 2;
+  return w;
+}
+
 // Single-pass COCG over all nsys systems.
 aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
   aao::CgArgs a = cg_args(p, adj, nsys);
@@ -648,8 +664,15 @@ aao_status read_back(aao_plan* p, int nsys, bool want_norms, SweepOut& o) {
       // counted in inner_solve_fft
     } else if (p->inner == AAO_INNER_COCG) {
       p->work_first[aao::KC_COCG_B] += n * nsys;  // init pass
-      p->work_first[aao::KC_COCG_A] += n * nsys;
-      p->work_later[aao::KC_COCG_A] += n * later;
+      if (p->cg_ntiles <= aao::kBlock) {  // fused passes: x every other pass
+        double words = 0;
+        for (int s = 0; s < nsys; ++s) words += cocg_fused_words(hs[s].iters);
+        p->bytes_direct[aao::KC_COCG_A] += n * words * (double)p->csize;
+        p->elems_direct[aao::KC_COCG_A] += n * sum;
+      } else {
+        p->work_first[aao::KC_COCG_A] += n * nsys;
+        p->work_later[aao::KC_COCG_A] += n * later;
+      }
     } else {
       for (int c : {aao::KC_BICG_1, aao::KC_BICG_2, aao::KC_BICG_3}) {
         p->work_first[c] += n * nsys;
@@ -1679,6 +1702,7 @@ aao_status aao_reset_stats(aao_plan_t p) {
   std::memset(p->work_first, 0, sizeof(p->work_first));
   std::memset(p->work_later, 0, sizeof(p->work_later));
   std::memset(p->bytes_direct, 0, sizeof(p->bytes_direct));
+  std::memset(p->elems_direct, 0, sizeof(p->elems_direct));
   return AAO_OK;
 }
 
@@ -1704,7 +1728,10 @@ aao_status aao_get_stats(aao_plan_t p, aao_kernel_stats* out) {
     out->elements[k.c] = p->work_first[k.c] + p->work_later[k.c];
     out->bytes[k.c] = cs * (k.later * p->work_later[k.c] + k.first * p->work_first[k.c]);
   }
-  for (int c = 0; c < AAO_NUM_KERNELS; ++c) out->bytes[c] += p->bytes_direct[c];
+  for (int c = 0; c < AAO_NUM_KERNELS; ++c) {
+    out->bytes[c] += p->bytes_direct[c];
+    out->elements[c] += p->elems_direct[c];
+  }
   return AAO_OK;
 }
 

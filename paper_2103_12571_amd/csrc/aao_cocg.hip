@@ -16,7 +16,12 @@
 //
 // Scalars live in SysState.  When a system has at most 256 tiles every pass
 // reduces the previous pass's tile sums itself (fused); otherwise a small
-// per-system kernel does it between passes.  Sums run in a fixed order, so
+// per-system kernel does it between passes.  Fused passes move x every other
+// pass: pass k reads p_{k-1} anyway, so an odd pass applies
+//   x_{k+1} = (x_{k-1} + alpha_{k-1} p_{k-1}) + alpha_k p_k
+// (the same two roundings in the same order as one update per pass) and an
+// even pass neither reads nor writes x; a system that stops in an odd pass
+// applies the update still pending from the pass before.  Sums run in a fixed order, so
 // results are bitwise reproducible.  A fused solve may change its tiling
 // between passes (small tiles once few systems remain): a pass reduces the
 // sums of the previous pass's tiling.
@@ -228,16 +233,22 @@ __device__ __forceinline__ void ring_slot(const CgArgs& a, const TileGeo& G, int
                                                                                      : -1;
 }
 
+// x in a pass: XM_EVERY x_{k+1} = x_k + alpha_k p_k (non-fused), XM_SKIP x
+// untouched (fused, k even), XM_TWO both updates (fused, k odd).
+enum : int { XM_EVERY = 0, XM_SKIP = 1, XM_TWO = 2 };
+
 // One COCG iteration for one tile of one system.  Thread t owns tile points
 // t + 256 j (j < NI) and points t + 256 j of the two-hop ring around the
 // tile (j < NH); it keeps r_k and then r_{k+1} of its points in registers across
 // the stages.  NT > 0: the stencil has NT taps (unrolled).  NI = 1 (tiles of
 // at most 256 points, used when few systems remain and the pass is bound by
-// latency, not bandwidth) also requests x_k together with r_k and p_{k-1}.
-template <typename T, int NI, int NH, int NT>
+// latency, not bandwidth) also requests x together with r_k and p_{k-1}.
+template <typename T, int NI, int NH, int NT, int XM>
 __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   using V = typename cvec<T>::type;
   constexpr bool kEarlyX = NI == 1;
+  // x is read: every pass after the first, or odd passes after the first one
+  const bool xread = XM == XM_EVERY ? k > 0 : XM == XM_TWO && k >= 3;
   extern __shared__ char smem[];
   __shared__ double sh[4 * kQ];
   __shared__ int act;
@@ -276,7 +287,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   if (a.fused ? st0->stop_pass < k : !st0->active) return;
   const double bb0 = a.fused ? st0->bb : 0.0;
   const double2 s0 = a.fused ? st0->gamma2[(k + 1) & 1] : st0->alpha;
-  const double2 s1 = a.fused ? st0->alpha2[(k + 1) & 1] : st0->beta;
+  const double2 s1 = a.fused ? st0->alpha2[(k + 1) & 1] : st0->beta;  // fused: alpha_{k-1}
 
   // 2. r_k and p_{k-1} at the tile points and on the two-hop ring.  Tile
   //    points of a ragged last tile that fall outside the grid hold their
@@ -289,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
     tile_slot(a, G, t, j, g, l, q, own);
     ri[j] = Rin[g];
     pi[j] = (k > 0) ? Pold[g] : vzero<V>();
-    if (kEarlyX) xi[j] = (k > 0 && own) ? X[g] : vzero<V>();
+    if (kEarlyX && XM != XM_SKIP) xi[j] = (xread && own) ? X[g] : vzero<V>();
   }
 #pragma unroll
   for (int j = 0; j < NH; ++j) {
@@ -336,7 +347,22 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
     sc[1] = s1;
   }
   __syncthreads();
-  if (!act) return;
+  if (!act) {
+    if (XM == XM_TWO) {  // stopped: apply the update pending from pass k-1
+      const V alp = from_d2<V>(s1);
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        int g, l, q;
+        bool own;
+        tile_slot(a, G, t, j, g, l, q, own);
+        if (own) {
+          const V x0 = kEarlyX ? xi[j] : (xread ? X[g] : vzero<V>());
+          X[g] = vadd(x0, vmul(alp, pi[j]));
+        }
+      }
+    }
+    return;
+  }
   const V al = from_d2<V>(uniform(sc[0]));
   const V be = from_d2<V>(uniform(sc[1]));
   const V sft = from_d2<V>(a.shift[s]);
@@ -366,9 +392,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
 #pragma unroll
   for (int j = 0; j < NH; ++j)
     if (lh[j] >= 0) Pt.st(lh[j], (k > 0) ? vadd(rh[j], vmul(be, ph[j])) : rh[j]);
-  if (!kEarlyX) {
+  if (!kEarlyX && XM != XM_SKIP) {
 #pragma unroll
-    for (int j = 0; j < NI; ++j) xi[j] = (k > 0 && gi[j] >= 0) ? X[gi[j]] : vzero<V>();
+    for (int j = 0; j < NI; ++j) xi[j] = (xread && gi[j] >= 0) ? X[gi[j]] : vzero<V>();
+  }
+  if (XM == XM_TWO) {  // x_k = x_{k-1} + alpha_{k-1} p_{k-1}
+    const V alp = from_d2<V>(s1);
+#pragma unroll
+    for (int j = 0; j < NI; ++j) xi[j] = vadd(xi[j], vmul(alp, pi[j]));
   }
   __syncthreads();
 
@@ -383,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
       if (gi[j] >= 0) {
         Rout[gi[j]] = ri[j];
         Pnew[gi[j]] = p;
-        X[gi[j]] = vadd(xi[j], vmul(al, p));
+        if (XM != XM_SKIP) X[gi[j]] = vadd(xi[j], vmul(al, p));
       }
     }
     // one point at a time: keeps the stencil operands of different points
@@ -510,10 +541,16 @@ hipError_t launch_cg_pass(bool f32, const CgArgs& a, int k, int nact, hipStream_
   const int nh = cg_ring_slots(a);
   const int nt = (a.taps.n == 3 || a.taps.n == 5) ? a.taps.n : 0;
   const bool one = a.TX * a.TY <= kBlock;
-#define AAO_CGP3(NI, NH, NT)                                                                          \
-  do {                                                                                                \
-    if (f32) hipLaunchKernelGGL((k_cg_pass<float, NI, NH, NT>), grid, dim3(kBlock), lds, st, a, k);   \
-    else hipLaunchKernelGGL((k_cg_pass<double, NI, NH, NT>), grid, dim3(kBlock), lds, st, a, k);      \
+#define AAO_CGP4(NI, NH, NT, XM)                                                                        \
+  do {                                                                                                  \
+    if (f32) hipLaunchKernelGGL((k_cg_pass<float, NI, NH, NT, XM>), grid, dim3(kBlock), lds, st, a, k); \
+    else hipLaunchKernelGGL((k_cg_pass<double, NI, NH, NT, XM>), grid, dim3(kBlock), lds, st, a, k);    \
+  } while (0)
+#define AAO_CGP3(NI, NH, NT)                      \
+  do {                                            \
+    if (!a.fused) AAO_CGP4(NI, NH, NT, XM_EVERY); \
+    else if (k & 1) AAO_CGP4(NI, NH, NT, XM_TWO); \
+    else AAO_CGP4(NI, NH, NT, XM_SKIP);           \
   } while (0)
 #define AAO_CGP2(NH, NT)         \
   do {                           \
@@ -531,6 +568,7 @@ hipError_t launch_cg_pass(bool f32, const CgArgs& a, int k, int nact, hipStream_
   else if (nh <= 4) AAO_CGP(4);
   else if (nh <= 8) AAO_CGP(8);
   else return hipErrorInvalidValue;
+#undef AAO_CGP4
 #undef AAO_CGP3
 #undef AAO_CGP2
 #undef AAO_CGP

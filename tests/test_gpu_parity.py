@@ -105,6 +105,38 @@ def test_shifted_solve_parity(inner, kind, prec):
     assert np.all(its > 0)
 
 
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_shifted_solve_cocg_exact_in_few_steps(prec):
+    """A right-hand side made of m Fourier modes with distinct eigenvalues of
+    the periodic 5-point Laplacian makes COCG exact after m iterations, so the
+    systems stop after passes 1 .. 5: odd and even stopping passes, the first
+    one included, in one batch (x moves every other pass in fused tilings)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    need_gpu()
+    say("shifted exact", prec)
+    w = wl.Workload("t", "heat2d", 24, 20, 8, 3, 1e-3, nu=1e-2, inner="cocg", precision=prec)
+    p = plan_for(w, inner_tol=1e-13 if prec == "fp64" else 1e-6)
+    xg, yg = np.meshgrid(np.arange(w.nx), np.arange(w.ny))
+    modes = [(1, 0), (2, 1), (0, 3), (3, 2), (4, 4)]  # distinct eigenvalues on 24 x 20
+    lam = [np.sin(np.pi * kx / w.nx) ** 2 + np.sin(np.pi * ky / w.ny) ** 2 for kx, ky in modes]
+    assert len(set(np.round(lam, 12))) == len(lam)
+    shifts = np.array([0.02 + 0.01j, 0.03 - 0.02j, 0.01 + 0.04j, 0.05 + 0.0j, 0.02 - 0.03j])
+    b = np.zeros((len(modes), w.N), dtype=np.complex128)
+    for s in range(len(modes)):  # system s: the first s + 1 modes
+        for j, (kx, ky) in enumerate(modes[:s + 1]):
+            b[s] += (1.0 + 0.5j * j) * np.cos(2 * np.pi * (kx * xg / w.nx + ky * yg / w.ny)).reshape(-1)
+    x, its = p.shifted_solve(shifts, torch.as_tensor(b, device="cuda"))
+    x = x.cpu().numpy()
+    A = _oracle_op(w).matrix()
+    say("  iterations", its.tolist())
+    for s in range(len(modes)):
+        xo = spla.spsolve((sp.identity(w.N) - shifts[s] * A).tocsc(), b[s])
+        assert rel_l2(x[s], xo) < (1e-12 if prec == "fp64" else 5e-6), (s, rel_l2(x[s], xo))
+        if prec == "fp64":
+            assert its[s] == s + 1, its
+
 def _solve_and_compare(w, tol_rel, **solve_kw):
     p = plan_for(w)
     u0 = wl.initial_batch(w)
