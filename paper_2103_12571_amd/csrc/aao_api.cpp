@@ -490,12 +490,12 @@ aao_status lag_begin(aao_plan* p, LagCheck& c, int nsys) {
   return AAO_OK;
 }
 
-// Complex words per element that the fused COCG passes of one system move
-// when it stopped in pass ks: pass k reads r (and p_{k-1} after the first)
-// and writes r and p; odd passes also write x (and read it after pass 1); a
-// stop in an odd pass applies the pending x update (reads p, writes x, reads
-// x after pass 1).
-double cocg_fused_words(int ks) {
+// Complex words per element that the COCG passes of one system move when it
+// made ks iterations: pass k reads r (and p_{k-1} after the first) and writes
+// r and p; odd passes also write x (and read it after pass 1); if the last
+// pass was even, its x update is applied afterwards (in the stopping pass when
+// fused, else in the closing kernel: reads p, writes x, reads x after pass 1).
+double cocg_words(int ks) {
   double w = 0;
   for (int k = 0; k < ks; ++k) {
     w += (k > 0) ? 4 : 3;
@@ -547,6 +547,10 @@ aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
     int n;
     aao_status s = lag_check(c, nact, a.sys_list, n, true);
     if (s != AAO_OK) return s;
+  }
+  if (!a.fused) {  // x updates left pending by a last even pass
+    close_run(p);
+    HIPCHK(timed(p, aao::KC_MISC, [&] { return aao::launch_cg_xfix(p->f32, a, nsys, p->stream); }));
   }
   return AAO_OK;
 }
@@ -664,15 +668,10 @@ aao_status read_back(aao_plan* p, int nsys, bool want_norms, SweepOut& o) {
       // counted in inner_solve_fft
     } else if (p->inner == AAO_INNER_COCG) {
       p->work_first[aao::KC_COCG_B] += n * nsys;  // init pass
-      if (p->cg_ntiles <= aao::kBlock) {  // fused passes: x every other pass
-        double words = 0;
-        for (int s = 0; s < nsys; ++s) words += cocg_fused_words(hs[s].iters);
-        p->bytes_direct[aao::KC_COCG_A] += n * words * (double)p->csize;
-        p->elems_direct[aao::KC_COCG_A] += n * sum;
-      } else {
-        p->work_first[aao::KC_COCG_A] += n * nsys;
-        p->work_later[aao::KC_COCG_A] += n * later;
-      }
+      double words = 0;  // x moves every other pass
+      for (int s = 0; s < nsys; ++s) words += cocg_words(hs[s].iters);
+      p->bytes_direct[aao::KC_COCG_A] += n * words * (double)p->csize;
+      p->elems_direct[aao::KC_COCG_A] += n * sum;
     } else {
       for (int c : {aao::KC_BICG_1, aao::KC_BICG_2, aao::KC_BICG_3}) {
         p->work_first[c] += n * nsys;
@@ -1718,11 +1717,14 @@ aao_status aao_get_stats(aao_plan_t p, aao_kernel_stats* out) {
   out->elements[aao::KC_BWD] = dof * out->launches[aao::KC_BWD];
   out->bytes[aao::KC_BWD] = (16.0 * dof + cs * freq) * out->launches[aao::KC_BWD];
   // Krylov kernels: complex words read + written per element processed in
-  // iterations after the first / in the first iteration.
+  // iterations after the first / in the first iteration (COCG passes: per
+  // system, counted directly, see cocg_words).
   // FFT inner solve: read and write the vector once per pass (1 pass in 1D, 3 in 2D)
   const double fftw = p->ny > 1 ? 6.0 : 2.0;
+  out->elements[aao::KC_COCG_A] = 0;
+  out->bytes[aao::KC_COCG_A] = 0;
   struct { int c; double later, first; } kw[] = {
-      {aao::KC_COCG_A, 6, 4}, {aao::KC_COCG_B, 1, 1}, {aao::KC_BICG_1, 6, 4},
+      {aao::KC_COCG_B, 1, 1}, {aao::KC_BICG_1, 6, 4},
       {aao::KC_BICG_2, 4, 4}, {aao::KC_BICG_3, 7, 6}, {aao::KC_FFT_INNER, fftw, fftw}};
   for (auto& k : kw) {
     out->elements[k.c] = p->work_first[k.c] + p->work_later[k.c];

@@ -16,12 +16,14 @@
 //
 // Scalars live in SysState.  When a system has at most 256 tiles every pass
 // reduces the previous pass's tile sums itself (fused); otherwise a small
-// per-system kernel does it between passes.  Fused passes move x every other
-// pass: pass k reads p_{k-1} anyway, so an odd pass applies
+// per-system kernel does it between passes.  Passes move x every other pass:
+// pass k reads p_{k-1} anyway, so an odd pass applies
 //   x_{k+1} = (x_{k-1} + alpha_{k-1} p_{k-1}) + alpha_k p_k
 // (the same two roundings in the same order as one update per pass) and an
-// even pass neither reads nor writes x; a system that stops in an odd pass
-// applies the update still pending from the pass before.  Sums run in a fixed order, so
+// even pass neither reads nor writes x.  A fused system that stops in an odd
+// pass applies the update still pending from the pass before; with a scalar
+// kernel between passes a last kernel does it for systems whose last pass was
+// even.  Sums run in a fixed order, so
 // results are bitwise reproducible.  A fused solve may change its tiling
 // between passes (small tiles once few systems remain): a pass reduces the
 // sums of the previous pass's tiling.
@@ -233,9 +235,8 @@ __device__ __forceinline__ void ring_slot(const CgArgs& a, const TileGeo& G, int
                                                                                      : -1;
 }
 
-// x in a pass: XM_EVERY x_{k+1} = x_k + alpha_k p_k (non-fused), XM_SKIP x
-// untouched (fused, k even), XM_TWO both updates (fused, k odd).
-enum : int { XM_EVERY = 0, XM_SKIP = 1, XM_TWO = 2 };
+// x in a pass: XM_SKIP x untouched (k even), XM_TWO both updates (k odd).
+enum : int { XM_SKIP = 1, XM_TWO = 2 };
 
 // One COCG iteration for one tile of one system.  Thread t owns tile points
 // t + 256 j (j < NI) and points t + 256 j of the two-hop ring around the
@@ -247,8 +248,7 @@ template <typename T, int NI, int NH, int NT, int XM>
 __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   using V = typename cvec<T>::type;
   constexpr bool kEarlyX = NI == 1;
-  // x is read: every pass after the first, or odd passes after the first one
-  const bool xread = XM == XM_EVERY ? k > 0 : XM == XM_TWO && k >= 3;
+  const bool xread = XM == XM_TWO && k >= 3;  // x read: odd passes after the first
   extern __shared__ char smem[];
   __shared__ double sh[4 * kQ];
   __shared__ int act;
@@ -288,6 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   const double bb0 = a.fused ? st0->bb : 0.0;
   const double2 s0 = a.fused ? st0->gamma2[(k + 1) & 1] : st0->alpha;
   const double2 s1 = a.fused ? st0->alpha2[(k + 1) & 1] : st0->beta;  // fused: alpha_{k-1}
+  const double2 sap = a.fused ? s1 : st0->alpha_prev;                 // alpha_{k-1}
 
   // 2. r_k and p_{k-1} at the tile points and on the two-hop ring.  Tile
   //    points of a ragged last tile that fall outside the grid hold their
@@ -349,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   __syncthreads();
   if (!act) {
     if (XM == XM_TWO) {  // stopped: apply the update pending from pass k-1
-      const V alp = from_d2<V>(s1);
+      const V alp = from_d2<V>(sap);
 #pragma unroll
       for (int j = 0; j < NI; ++j) {
         int g, l, q;
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
     for (int j = 0; j < NI; ++j) xi[j] = (xread && gi[j] >= 0) ? X[gi[j]] : vzero<V>();
   }
   if (XM == XM_TWO) {  // x_k = x_{k-1} + alpha_{k-1} p_{k-1}
-    const V alp = from_d2<V>(s1);
+    const V alp = from_d2<V>(sap);
 #pragma unroll
     for (int j = 0; j < NI; ++j) xi[j] = vadd(xi[j], vmul(alp, pi[j]));
   }
@@ -486,6 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_scalars(CgArgs a, int k) {
     st->beta = mk(0, 0);
     const double d2 = del.x * del.x + del.y * del.y;
     st->alpha = (rr > 0.0 && d2 > 0.0) ? cdiv(gam, del) : mk(0, 0);  // b = 0: x stays 0
+    st->alpha_prev = mk(0, 0);
     return;
   }
   st->iters = k + 1;
@@ -510,8 +512,27 @@ __global__ __launch_bounds__(kBlock) void k_cg_scalars(CgArgs a, int k) {
     return;
   }
   st->beta = be;
+  st->alpha_prev = a0;
   st->alpha = cdiv(gam, den);
   st->gamma = gam;
+}
+
+// The update a system's last pass k = iters - 1 left pending when k is even:
+// x_{k+1} = x_k + alpha_k p_k (x_k = 0 when k = 0); alpha_k is still in the
+// state (a stopping scalar step leaves it), p_k in P[k & 1].
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_xfix(CgArgs a) {
+  using V = typename cvec<T>::type;
+  const int s = blockIdx.y;
+  const SysState* st = a.st + s;
+  const int k = st->iters - 1;
+  if (k < 0 || (k & 1)) return;
+  const size_t off = (size_t)s * a.g.N;
+  const V* Pk = reinterpret_cast<const V*>(a.P[k & 1]) + off;
+  V* X = reinterpret_cast<V*>(a.X) + off;
+  const V al = from_d2<V>(st->alpha);
+  for (int n = blockIdx.x * kBlock + threadIdx.x; n < a.g.N; n += gridDim.x * kBlock)
+    X[n] = vadd(k > 0 ? X[n] : vzero<V>(), vmul(al, Pk[n]));
 }
 
 }  // namespace
@@ -546,11 +567,10 @@ hipError_t launch_cg_pass(bool f32, const CgArgs& a, int k, int nact, hipStream_
     if (f32) hipLaunchKernelGGL((k_cg_pass<float, NI, NH, NT, XM>), grid, dim3(kBlock), lds, st, a, k); \
     else hipLaunchKernelGGL((k_cg_pass<double, NI, NH, NT, XM>), grid, dim3(kBlock), lds, st, a, k);    \
   } while (0)
-#define AAO_CGP3(NI, NH, NT)                      \
-  do {                                            \
-    if (!a.fused) AAO_CGP4(NI, NH, NT, XM_EVERY); \
-    else if (k & 1) AAO_CGP4(NI, NH, NT, XM_TWO); \
-    else AAO_CGP4(NI, NH, NT, XM_SKIP);           \
+#define AAO_CGP3(NI, NH, NT)                 \
+  do {                                       \
+    if (k & 1) AAO_CGP4(NI, NH, NT, XM_TWO); \
+    else AAO_CGP4(NI, NH, NT, XM_SKIP);      \
   } while (0)
 #define AAO_CGP2(NH, NT)         \
   do {                           \
@@ -577,6 +597,15 @@ hipError_t launch_cg_pass(bool f32, const CgArgs& a, int k, int nact, hipStream_
 
 hipError_t launch_cg_scalars(const CgArgs& a, int k, int nact, hipStream_t st) {
   hipLaunchKernelGGL(k_cg_scalars, dim3(nact), dim3(kBlock), 0, st, a, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_xfix(bool f32, const CgArgs& a, int nsys, hipStream_t st) {
+  if (nsys < 1 || nsys > 65535) return hipErrorInvalidValue;
+  const int blocks = std::max(1, std::min((a.g.N + kBlock - 1) / kBlock, 1024));
+  dim3 grid(blocks, nsys);
+  if (f32) hipLaunchKernelGGL(k_cg_xfix<float>, grid, dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL(k_cg_xfix<double>, grid, dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ struct SysState {
   double2 omega;  // BiCGStab: omega_k
   double2 beta;   // COCG: beta_k
   double2 gamma;  // COCG: gamma_k = r_k^T r_k
+  double2 alpha_prev;  // COCG, scalar kernel between passes: alpha_{k-1}
   double bb;      // ||b||^2
   double rr;      // ||r_k||^2
   double2 gamma2[2];  // COCG, fused scalar update: gamma_k and alpha_k by parity of k
@@ -184,6 +185,9 @@ hipError_t launch_mdot(const double* V, size_t stride, int nvec, const double* t
 hipError_t launch_maxpy(double* out, const double* in, const double* s, const double* V, size_t stride, int nvec,
                         const double* c, int64_t D, int B, double* part, int nblk, hipStream_t st);
 hipError_t launch_cg_scalars(const CgArgs& a, int k, int nact, hipStream_t st);
+// After the last pass of a solve with a scalar kernel between passes: x of the
+// systems (all nsys) whose last pass left x alone gets that pass's update.
+hipError_t launch_cg_xfix(bool f32, const CgArgs& a, int nsys, hipStream_t st);
 size_t cg_lds_bytes(bool f32, const CgArgs& a);
 int cg_ring_slots(const CgArgs& a);
 hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, int nact, hipStream_t st);

@@ -46,6 +46,22 @@ def test_fullsize_solve(name, tol):
     assert e <= tol
 
 
+def test_fullsize_solve_heat2d_1024_fp64():
+    """The 1024^2 workload on the FP64 path (COCG, tau = 1e-9, a scalar kernel
+    between passes), as bench.py times it beside the mixed path."""
+    need_gpu()
+    w = wl.WORKLOADS["heat2d_1024_mixed"].with_(precision="fp64", inner_tol=1e-9)
+    say("fullsize heat2d_1024 fp64 DOF", w.dof)
+    p, u0, u, info = _solve(w)
+    say("  sweeps", info["iterations"], "inner mean", ["%.1f" % v for v in info["inner_mean"]])
+    assert info["converged"]
+    op, Q = _oracle(w)
+    uo = oracle.sequential_solve(op, Q, w.dt, u0[0], w.L, backend="spectral")
+    e = rel_l2(host(u)[0], uo)
+    say("  rel l2 vs oracle %.3e" % e)
+    assert e <= 1e-8
+
+
 def test_fullsize_adjoint_gradients():
     """Workload advdiff2d_512_adj (B = 8, complex64 inner solves): forward
     solve, adjoint solve and gradients; instances 0 and 7 against the oracle."""

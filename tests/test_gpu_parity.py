@@ -106,35 +106,52 @@ def test_shifted_solve_parity(inner, kind, prec):
 
 
 
+@pytest.mark.parametrize("nx,ny", [(24, 20), (1024, 320)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_shifted_solve_cocg_exact_in_few_steps(prec):
+def test_shifted_solve_cocg_exact_in_few_steps(prec, nx, ny):
     """A right-hand side made of m Fourier modes with distinct eigenvalues of
-    the periodic 5-point Laplacian makes COCG exact after m iterations, so the
-    systems stop after passes 1 .. 5: odd and even stopping passes, the first
-    one included, in one batch (x moves every other pass in fused tilings)."""
-    import scipy.sparse as sp
-    import scipy.sparse.linalg as spla
+    the periodic 5-point Laplacian makes COCG exact after m iterations, so on
+    24 x 20 (one fused reduction per system, 2 tiles) the systems stop after
+    1 .. 5 iterations: odd and even last passes, the first one included, in
+    one batch (x moves every other pass).  On 1024 x 320 (a scalar kernel
+    between passes, 320 tiles) round-off spoils the exact steps beyond the
+    first mode (|c A| reaches about 2000) and the systems stop after tens of
+    iterations.  Each cosine mode is an eigenvector of A = nu Lap_h with
+    eigenvalue -nu lam, so the exact solution is sum_j b_j / (1 + c nu lam_j);
+    with Re c >= 0, ||(I - c A)^{-1}|| <= 1 bounds the error by the true
+    residual, which a complex64 x cannot bring below about eps_32 |c A| here."""
     need_gpu()
-    say("shifted exact", prec)
-    w = wl.Workload("t", "heat2d", 24, 20, 8, 3, 1e-3, nu=1e-2, inner="cocg", precision=prec)
-    p = plan_for(w, inner_tol=1e-13 if prec == "fp64" else 1e-6)
+    say("shifted exact", prec, nx, ny)
+    w = wl.Workload("t", "heat2d", nx, ny, 8, 3, 1e-3, nu=1e-2, inner="cocg", precision=prec)
+    small = w.N <= 1000
+    tau = (1e-13 if small else 1e-10) if prec == "fp64" else 1e-6
+    p = plan_for(w, inner_tol=tau)
     xg, yg = np.meshgrid(np.arange(w.nx), np.arange(w.ny))
-    modes = [(1, 0), (2, 1), (0, 3), (3, 2), (4, 4)]  # distinct eigenvalues on 24 x 20
-    lam = [np.sin(np.pi * kx / w.nx) ** 2 + np.sin(np.pi * ky / w.ny) ** 2 for kx, ky in modes]
-    assert len(set(np.round(lam, 12))) == len(lam)
+    modes = [(1, 0), (2, 1), (0, 3), (3, 2), (4, 4)]  # distinct eigenvalues on both grids
+    lam = [4.0 * nx * nx * np.sin(np.pi * kx / nx) ** 2 + 4.0 * ny * ny * np.sin(np.pi * ky / ny) ** 2
+           for kx, ky in modes]
+    assert min(abs(a - b) for i, a in enumerate(lam) for b in lam[i + 1:]) > 1e-6 * max(lam)
     shifts = np.array([0.02 + 0.01j, 0.03 - 0.02j, 0.01 + 0.04j, 0.05 + 0.0j, 0.02 - 0.03j])
     b = np.zeros((len(modes), w.N), dtype=np.complex128)
+    xe = np.zeros_like(b)
     for s in range(len(modes)):  # system s: the first s + 1 modes
         for j, (kx, ky) in enumerate(modes[:s + 1]):
-            b[s] += (1.0 + 0.5j * j) * np.cos(2 * np.pi * (kx * xg / w.nx + ky * yg / w.ny)).reshape(-1)
+            e = (1.0 + 0.5j * j) * np.cos(2 * np.pi * (kx * xg / w.nx + ky * yg / w.ny)).reshape(-1)
+            b[s] += e
+            xe[s] += e / (1.0 + shifts[s] * w.nu * lam[j])
     x, its = p.shifted_solve(shifts, torch.as_tensor(b, device="cuda"))
     x = x.cpu().numpy()
     A = _oracle_op(w).matrix()
     say("  iterations", its.tolist())
     for s in range(len(modes)):
-        xo = spla.spsolve((sp.identity(w.N) - shifts[s] * A).tocsc(), b[s])
-        assert rel_l2(x[s], xo) < (1e-12 if prec == "fp64" else 5e-6), (s, rel_l2(x[s], xo))
+        res = np.linalg.norm(b[s] - (x[s] - shifts[s] * (A @ x[s]))) / np.linalg.norm(b[s])
+        err = rel_l2(x[s], xe[s])
+        say("  system %d: true residual %.2e, error %.2e" % (s, res, err))
         if prec == "fp64":
+            assert res < (1e-12 if small else 2e-10) and err < (1e-12 if small else 1e-9), (s, res, err)
+        else:
+            assert err < (5e-6 if small else 1e-4), (s, res, err)
+        if prec == "fp64" and small:
             assert its[s] == s + 1, its
 
 def _solve_and_compare(w, tol_rel, **solve_kw):
