@@ -101,7 +101,7 @@ typedef struct {
   int M;                /* collocation nodes per step, 1..8 */
   const double* nodes;  /* NULL: Radau-right nodes (Sec. 2.1, Sec. 2.3); else M
                            increasing nodes in (0, 1] with nodes[M-1] == 1 */
-  int L;                /* steps solved at once; power of two, 1..1024 */
+  int L;                /* steps solved at once; power of two, 1..1024, L * M <= 2048 */
   double dt;            /* step size dT > 0 */
   int batch;            /* B >= 1 independent instances sharing A */
   int precision;        /* AAO_FP64 | AAO_MIXED */

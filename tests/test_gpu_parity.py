@@ -172,6 +172,39 @@ def _solve_and_compare(w, tol_rel, **solve_kw):
     return info, errs
 
 
+
+# the plan's limits: M <= 8 nodes, L <= 1024 steps, L * M <= 2048
+LIMIT_CASES = [
+    ("heat1d_N40_L16_M8", wl.WORKLOADS["heat1d_64"].with_(nx=40, L=16, M=8, nu=0.05)),
+    ("heat2d_8x6_L256_M8", wl.WORKLOADS["heat2d_256"].with_(nx=8, ny=6, L=256, M=8)),
+    ("heat1d_N16_L1024_M2", wl.WORKLOADS["heat1d_64"].with_(nx=16, L=1024, M=2, nu=0.05)),
+]
+
+
+@pytest.mark.parametrize("alpha", [1e-4, 0.1])
+@pytest.mark.parametrize("name,w", LIMIT_CASES, ids=[c[0] for c in LIMIT_CASES])
+def test_precond_parity_at_size_limits(name, w, alpha):
+    """Rows a2-a4 at the largest M and L the plan accepts."""
+    need_gpu()
+    say("precond limits", name, alpha)
+    p = plan_for(w, inner_tol=1e-14, inner_maxit=4000)
+    r = _rand((w.batch, w.L, w.M, w.N), 5)
+    d = host(p.precond(dev(r), alpha))
+    op, Q = _oracle_op(w), _Q(w.M)
+    do = oracle.precond_solve(op, Q, w.dt, alpha, r[0])
+    tol = 1e-12 * max(1.0, w.L / alpha) ** 0.5 * 10  # round-off grows like L / alpha (Theorem 2)
+    say("  rel l2 %.2e (bound %.1e)" % (rel_l2(d[0], do), max(tol, 1e-11)))
+    assert rel_l2(d[0], do) < max(tol, 1e-11)
+
+
+@pytest.mark.parametrize("name,w", LIMIT_CASES, ids=[c[0] for c in LIMIT_CASES])
+def test_solve_at_size_limits(name, w):
+    """Alg. 2 at the largest M and L against sequential collocation."""
+    need_gpu()
+    say("solve limits", name)
+    info, _ = _solve_and_compare(w, 1e-9, tol=1e-12, max_iter=40)
+    assert info["converged"]
+
 def test_solve_heat1d_64_fixed_alpha_residual_stop():
     """Workload heat1d_64: fixed alpha = 1e-3, stop at relative residual 1e-12."""
     need_gpu()
