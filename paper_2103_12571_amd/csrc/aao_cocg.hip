@@ -55,45 +55,6 @@ __device__ __forceinline__ double* cg_part(const CgArgs& a, int q, int s) {
   return a.part + ((size_t)q * a.num_sys + s) * a.ntiles;
 }
 
-// gamma_0 = b^T b, delta_0 = b^T A_s b, ||b||^2 over one tile (neighbours from
-// global memory: this pass runs once per solve).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
-  using V = typename cvec<T>::type;
-  __shared__ double sh[4 * kQ];
-  const int s = a.sys_list[blockIdx.y];
-  const V* Rb = reinterpret_cast<const V*>(a.R[0]) + (size_t)s * a.g.N;
-  const V sft = from_d2<V>(a.shift[s]);
-  int tile = blockIdx.x;
-  if (a.xcd_band > 0) tile = (tile & 7) * a.xcd_band + (tile >> 3);
-  const int ty = fdiv(tile, a.m_ntx), tx = tile - ty * a.ntx;
-  const int x0 = tx * a.TX, y0 = ty * a.TY;
-  double v[kQ] = {0, 0, 0, 0, 0};
-  for (int i = threadIdx.x; i < a.TX * a.TY; i += kBlock) {
-    const int x = x0 + i % a.TX, y = y0 + i / a.TX;
-    if (x >= a.g.nx || y >= a.g.ny) continue;
-    const int n = y * a.g.nx + x;
-    const V b = Rb[n];
-    V acc = vzero<V>();
-    for (int t = 0; t < a.taps.n; ++t) {
-      const int nb = wrap_index(x, y, a.taps.dx[t], a.taps.dy[t], a.g);
-      acc = vadd(acc, vscale(Rb[nb], (T)a.taps.c[t]));
-    }
-    const V w = vsub(b, vmul(sft, acc));
-    v[0] += (double)b.x * b.x - (double)b.y * b.y;
-    v[1] += 2.0 * (double)b.x * b.y;
-    v[2] += (double)b.x * w.x - (double)b.y * w.y;
-    v[3] += (double)b.x * w.y + (double)b.y * w.x;
-    v[4] += (double)b.x * b.x + (double)b.y * b.y;
-  }
-  block_sum_wave0<kQ>(v, sh);
-  if (threadIdx.x == 0) {
-    double* pb = a.part + (a.fused ? a.part_stride : 0);
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) pb[((size_t)q * a.num_sys + s) * a.ntiles + tile] = v[q];
-  }
-}
-
 // Taps applied to an LDS tile with row pitch W: NT > 0 unrolls a fixed count.
 template <int NT, typename T, typename V>
 __device__ __forceinline__ V tile_stencil(const CgArgs& a, const LdsCplx<V>& buf, int c, int W) {
@@ -237,6 +198,61 @@ __device__ __forceinline__ void ring_slot(const CgArgs& a, const TileGeo& G, int
 
 // x in a pass: XM_SKIP x untouched (k even), XM_TWO both updates (k odd).
 enum : int { XM_SKIP = 1, XM_TWO = 2 };
+
+// gamma_0 = b^T b, delta_0 = b^T A_s b, ||b||^2 over one tile: b on the tile
+// and its one-hop ring in LDS (the two-hop layout of the passes), A_s b at
+// the tile points.
+template <typename T, int NI, int NH, int NT>
+__global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
+  using V = typename cvec<T>::type;
+  extern __shared__ char smem[];
+  __shared__ double sh[4 * kQ];
+  const int t = threadIdx.x;
+  const int s = a.sys_list[blockIdx.y];
+  const int tile = tile_of_block(a);
+  const TileGeo G = tile_geo(a, tile);
+  const V* Rb = reinterpret_cast<const V*>(a.R[0]) + (size_t)s * a.g.N;
+  const LdsCplx<V> Bt(smem, G.PW * G.PH);
+  V bi[NI];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    int g, l, q;
+    bool own;
+    tile_slot(a, G, t, j, g, l, q, own);
+    bi[j] = Rb[g];
+    if (l >= 0) Bt.st(l, bi[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < NH; ++j) {
+    int g, l, q;
+    ring_slot(a, G, t, j, g, l, q);
+    if (q >= 0) Bt.st(l, Rb[g]);  // the one-hop ring is enough for one stencil
+  }
+  __syncthreads();
+  const V sft = from_d2<V>(a.shift[s]);
+  double v[kQ] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    int g, l, q;
+    bool own;
+    tile_slot(a, G, t, j, g, l, q, own);
+    if (own) {
+      const V b = bi[j];
+      const V w = vsub(b, vmul(sft, tile_stencil<NT, T>(a, Bt, l, G.PW)));
+      v[0] += (double)b.x * b.x - (double)b.y * b.y;
+      v[1] += 2.0 * (double)b.x * b.y;
+      v[2] += (double)b.x * w.x - (double)b.y * w.y;
+      v[3] += (double)b.x * w.y + (double)b.y * w.x;
+      v[4] += (double)b.x * b.x + (double)b.y * b.y;
+    }
+  }
+  block_sum_wave0<kQ>(v, sh);
+  if (t == 0) {
+    double* pb = a.part + (a.fused ? a.part_stride : 0);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) pb[((size_t)q * a.num_sys + s) * a.ntiles + tile] = v[q];
+  }
+}
 
 // One COCG iteration for one tile of one system.  Thread t owns tile points
 // t + 256 j (j < NI) and points t + 256 j of the two-hop ring around the
@@ -548,9 +564,36 @@ int cg_ring_slots(const CgArgs& a) {
 }
 
 hipError_t launch_cg_init(bool f32, const CgArgs& a, int nact, hipStream_t st) {
+  if (a.TX * a.TY > kInside * kBlock) return hipErrorInvalidValue;
   dim3 grid(a.ntiles, nact);
-  if (f32) hipLaunchKernelGGL(k_cg_init<float>, grid, dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL(k_cg_init<double>, grid, dim3(kBlock), 0, st, a);
+  const size_t lds = cg_lds_bytes(f32, a);
+  const int nh = cg_ring_slots(a);
+  const int nt = (a.taps.n == 3 || a.taps.n == 5) ? a.taps.n : 0;
+  const bool one = a.TX * a.TY <= kBlock;
+#define AAO_CGI3(NI, NH, NT)                                                                        \
+  do {                                                                                              \
+    if (f32) hipLaunchKernelGGL((k_cg_init<float, NI, NH, NT>), grid, dim3(kBlock), lds, st, a);    \
+    else hipLaunchKernelGGL((k_cg_init<double, NI, NH, NT>), grid, dim3(kBlock), lds, st, a);       \
+  } while (0)
+#define AAO_CGI2(NH, NT)             \
+  do {                               \
+    if (one) AAO_CGI3(1, NH, NT);    \
+    else AAO_CGI3(kInside, NH, NT);  \
+  } while (0)
+#define AAO_CGI(NH)                      \
+  do {                                   \
+    if (nt == 3) AAO_CGI2(NH, 3);        \
+    else if (nt == 5) AAO_CGI2(NH, 5);   \
+    else AAO_CGI2(NH, 0);                \
+  } while (0)
+  if (nh <= 1) AAO_CGI(1);
+  else if (nh <= 2) AAO_CGI(2);
+  else if (nh <= 4) AAO_CGI(4);
+  else if (nh <= 8) AAO_CGI(8);
+  else return hipErrorInvalidValue;
+#undef AAO_CGI3
+#undef AAO_CGI2
+#undef AAO_CGI
   return hipGetLastError();
 }
 
