@@ -139,10 +139,22 @@ def test_shifted_solve_cocg_exact_in_few_steps(prec, nx, ny):
             e = (1.0 + 0.5j * j) * np.cos(2 * np.pi * (kx * xg / w.nx + ky * yg / w.ny)).reshape(-1)
             b[s] += e
             xe[s] += e / (1.0 + shifts[s] * w.nu * lam[j])
+    p.reset_stats()
     x, its = p.shifted_solve(shifts, torch.as_tensor(b, device="cuda"))
     x = x.cpu().numpy()
     A = _oracle_op(w).matrix()
     say("  iterations", its.tolist())
+    # algorithmic bytes the library reports for the passes: per element, pass
+    # k reads r (and p_{k-1} after pass 0) and writes r, p; odd passes also
+    # write x (and read it after pass 1); after an even last pass the pending
+    # x update reads p (and x after pass 1) and writes x
+    def words(ks):
+        w_ = sum((3 if k == 0 else 4) + ((2 if k >= 3 else 1) if k % 2 else 0) for k in range(ks))
+        return w_ + ((3 if ks >= 3 else 2) if ks % 2 else 0)
+    st = p.stats()["cocg_pass"]
+    csize = 16 if prec == "fp64" else 8
+    assert st["bytes"] == w.N * csize * sum(words(int(k)) for k in its), (st, its)
+    assert st["elements"] == w.N * int(np.sum(its))
     for s in range(len(modes)):
         res = np.linalg.norm(b[s] - (x[s] - shifts[s] * (A @ x[s]))) / np.linalg.norm(b[s])
         err = rel_l2(x[s], xe[s])
