@@ -7,7 +7,7 @@ Sec. 2.1, eq. (seq_collocation_problem): for l = 1..L solve
 starting from u_0, where b_l holds the source b(t) at the step's collocation
 times t_{l-1} + tau_m dT (eq. (collocation); b = 0 unless ``forcing`` is given).  The result U is the unique solution of the composite
 system C U = w (eq. (globalsys)); it is the converged answer of the
-alpha-circulant Richardson iteration, which therefore is judged only on U.
+alpha-circulant Richardson iteration, which therefore is compared with it on U only.
 """
 import numpy as np
 import scipy.sparse as sp
