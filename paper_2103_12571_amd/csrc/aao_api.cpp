@@ -113,6 +113,7 @@ struct aao_plan {
   int TN = 2, logTN = 1, ntiles = 0;
   // inner solves
   int S = 0, wps = 1, chunk = 256, nvec = 0;
+  int wps_max = 1;  // BiCGStab: most workgroups per system (partial-sum stride)
   int cgTX = 1, cgTY = 1, cg_ntx = 1, cg_nty = 1, cg_ntiles = 1, Rx = 0, Ry = 0;
   int cgTXs = 0, cgTYs = 0, cg_ntxs = 0, cg_ntiles_s = 0;  // small tiling (cg_ntiles_s = 0: none)
   int fft_rows = 1, fft_cols = 1;
@@ -370,6 +371,19 @@ aao::BwdArgs bwd_args(aao_plan* p, double* u) {
   return a;
 }
 
+// BiCGStab chunking for nact active systems: as many workgroups in all as the
+// plan uses with every system active (wps per system), spread over the
+// systems still active (at most wps_max per system).
+void krylov_chunks(const aao_plan* p, int nact, aao::KrylovArgs& a) {
+  const int64_t total = (int64_t)p->wps * p->S;
+  const int na = std::max(nact, 1);
+  int want = (int)std::min<int64_t>(p->wps_max, std::max<int64_t>(p->wps, (total + na - 1) / na));
+  int chunk = (p->N + want - 1) / want;
+  chunk = ((chunk + aao::kBlock - 1) / aao::kBlock) * aao::kBlock;
+  a.chunk = chunk;
+  a.wps = (p->N + chunk - 1) / chunk;
+}
+
 aao::KrylovArgs krylov_args(aao_plan* p, int adj, int nsys) {
   aao::KrylovArgs a{};
   a.X = p->vec(0);
@@ -389,8 +403,10 @@ aao::KrylovArgs krylov_args(aao_plan* p, int adj, int nsys) {
   a.g = {p->nx, p->ny, p->N};
   a.taps = adj ? p->tapsT : p->taps;
   a.num_sys = nsys;
-  a.wps = p->wps;
-  a.chunk = p->chunk;
+  krylov_chunks(p, nsys, a);
+  a.wps_stride = p->wps_max;
+  a.wps_rho = a.wps;
+  a.wps_bb = a.wps;
   a.tol2 = p->inner_tol * p->inner_tol;
   a.maxit = p->inner_maxit;
   return a;
@@ -614,6 +630,7 @@ aao_status inner_solve(aao_plan* p, int adj, int nsys) {
     if (k < p->inner_maxit) {
       HIPCHK(timed(p, aao::KC_BICG_2, [&] { return aao::launch_bicg(2, p->f32, a, k, nact, p->stream); }));
       HIPCHK(timed(p, aao::KC_BICG_3, [&] { return aao::launch_bicg(3, p->f32, a, k, nact, p->stream); }));
+      a.wps_rho = a.wps;  // rho_{k+1} and ||r_{k+1}||^2 were written by a.wps chunks
     }
     if (k + 1 == next_check) {
       next_check += (k < 16) ? 4 : 8;
@@ -621,6 +638,7 @@ aao_status inner_solve(aao_plan* p, int adj, int nsys) {
       aao_status s = lag_check(c, nact, a.sys_list, n, false);
       if (s != AAO_OK) return s;
       if (n == 0) break;
+      krylov_chunks(p, nact, a);  // wider launches once fewer systems remain
     }
   }
   if (c.pending >= 0) {
@@ -939,6 +957,10 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
     chunk = ((chunk + aao::kBlock - 1) / aao::kBlock) * aao::kBlock;
     p->chunk = chunk;
     p->wps = (p->N + chunk - 1) / chunk;
+    // as systems converge the grid would shrink to (active) x wps workgroups;
+    // the launches widen back towards wps x S workgroups, down to one point
+    // per thread, at most 256 chunks (one partial per thread in a reduction)
+    p->wps_max = std::max(p->wps, std::min(256, (p->N + aao::kBlock - 1) / aao::kBlock));
   }
   // COCG tiles: TX x TY points per workgroup; Rx, Ry: stencil reach
   for (int i = 0; i < A->ntaps; ++i) {
@@ -993,7 +1015,7 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   p->off_vec = off;
   off = align256(off + (size_t)p->nvec * p->S * p->N * p->csize);
   p->off_part = off;
-  off = align256(off + std::max((size_t)aao::QP_COUNT * p->S * p->wps, (size_t)2 * 5 * p->S * std::max(p->cg_ntiles, p->cg_ntiles_s)) *
+  off = align256(off + std::max((size_t)aao::QP_COUNT * p->S * p->wps_max, (size_t)2 * 5 * p->S * std::max(p->cg_ntiles, p->cg_ntiles_s)) *
                            sizeof(double));
   p->off_list = off;  // three lists of active systems (two alternating snapshots, the initial one)
   off = align256(off + (size_t)3 * p->S * sizeof(int));

@@ -417,17 +417,19 @@ __global__ __launch_bounds__(kBlock) void k_wnorms(FwdArgs a, int B, double* par
 // partial sums by every workgroup in the same fixed order (bitwise identical),
 // so no grid-wide synchronisation and no host round trip is needed.
 __device__ __forceinline__ double* qpart(const KrylovArgs& a, int q, int s) {
-  return a.part + ((size_t)q * a.num_sys + s) * a.wps;
+  return a.part + ((size_t)q * a.num_sys + s) * a.wps_stride;
 }
 
+// Sum quantity qs[i] over the nw[i] chunks that wrote it (fixed order).
 template <int K>
-__device__ __forceinline__ void reduce_parts(const KrylovArgs& a, const int (&qs)[K], int s,
+__device__ __forceinline__ void reduce_parts(const KrylovArgs& a, const int (&qs)[K], const int (&nw)[K], int s,
                                              double (&v)[K], double* sh) {
 #pragma unroll
   for (int i = 0; i < K; ++i) v[i] = 0.0;
-  for (int c = threadIdx.x; c < a.wps; c += kBlock) {
+  for (int c = threadIdx.x; c < a.wps_stride; c += kBlock) {
 #pragma unroll
-    for (int i = 0; i < K; ++i) v[i] += qpart(a, qs[i], s)[c];
+    for (int i = 0; i < K; ++i)
+      if (c < nw[i]) v[i] += qpart(a, qs[i], s)[c];
   }
   block_sum<K>(v, sh);
 }
@@ -501,8 +503,9 @@ __global__ __launch_bounds__(kBlock) void k_bicg1(KrylovArgs a, int k) {
     if (threadIdx.x == 0) qpart(a, QP_RHO0_IM, s)[blockIdx.x] = 0.0;
   } else {
     const int qs[4] = {QP_RHO0_RE + 2 * cur, QP_RHO0_IM + 2 * cur, QP_RR0 + cur, QP_BB};
+    const int nw[4] = {a.wps_rho, a.wps_rho, a.wps_rho, a.wps_bb};
     double v[4];
-    reduce_parts<4>(a, qs, s, v, sh);
+    reduce_parts<4>(a, qs, nw, s, v, sh);
     const bool conv = v[2] <= a.tol2 * v[3];
     if (conv || k >= a.maxit || st->breakdown) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -550,7 +553,8 @@ __global__ __launch_bounds__(kBlock) void k_bicg2(KrylovArgs a, int k) {
   double v[4];
   {
     const int qs[4] = {QP_RHO0_RE + 2 * cur, QP_RHO0_IM + 2 * cur, QP_A_RE, QP_A_IM};
-    reduce_parts<4>(a, qs, s, v, sh);
+    const int nw[4] = {a.wps_rho, a.wps_rho, a.wps, a.wps};  // rho: the previous iteration (k = 0: this one)
+    reduce_parts<4>(a, qs, nw, s, v, sh);
   }
   const double2 rho = mk(v[0], v[1]);
   const double2 hv = mk(v[2], v[3]);
@@ -604,7 +608,8 @@ __global__ __launch_bounds__(kBlock) void k_bicg3(KrylovArgs a, int k) {
   double v[3];
   {
     const int qs[3] = {QP_B_RE, QP_B_IM, QP_TT};
-    reduce_parts<3>(a, qs, s, v, sh);
+    const int nw[3] = {a.wps, a.wps, a.wps};
+    reduce_parts<3>(a, qs, nw, s, v, sh);
   }
   double2 om = mk(0, 0);
   if (v[2] > 0.0) om = mk(v[0] / v[2], v[1] / v[2]);
@@ -905,6 +910,9 @@ hipError_t launch_wnorms(int M, const FwdArgs& a, int B, double* part, int npart
 }
 
 hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, int nact, hipStream_t st) {
+  if (a.wps < 1 || a.wps > a.wps_stride || a.wps_rho < 1 || a.wps_rho > a.wps_stride || a.wps_bb < 1 ||
+      a.wps_bb > a.wps_stride || (int64_t)a.wps * a.chunk < a.g.N || (int64_t)(a.wps - 1) * a.chunk >= a.g.N)
+    return hipErrorInvalidValue;
   dim3 grid(a.wps, nact);
   switch (phase) {
     case 1:

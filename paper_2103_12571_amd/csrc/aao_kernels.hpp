@@ -112,12 +112,16 @@ struct KrylovArgs {
   void* T;       // BiCGStab: A s
   const double2* shift;  // [num_sys] shifted operator is I - shift * A
   SysState* st;
-  double* part;  // [quantity][num_sys][wps]
+  double* part;  // [quantity][num_sys][wps_stride]
   unsigned long long* work;  // element counters per kernel class
   const int* sys_list;       // systems of this launch (grid.y entries)
   Geo g;
   Taps taps;
-  int num_sys, wps, chunk;
+  // BiCGStab: wps workgroups per system, each over chunk points; wps may grow
+  // between iterations as systems drop out.  Partial sums have a fixed
+  // stride; wps_rho is the count that wrote rho and ||r||^2 (the previous
+  // iteration's last kernel), wps_bb the count of the first iteration.
+  int num_sys, wps, chunk, wps_stride, wps_rho, wps_bb;
   double tol2;
   int maxit;
 };
