@@ -196,34 +196,45 @@ def adjoint_block(np, torch, wl, plan_for, with_oracle):
     """Row a7 at the adjoint workload (2D advection-diffusion 512^2, nu = 5e-3,
     v = (1, 0.5), L = 64, M = 3, B = 8, complex64 inner solves): forward solve,
     adjoint solve of C^T lambda = e_{L,M} (x) (u_{L,M} - u_target) and both
-    gradients, timed to the gradients; instance 0 against the oracle."""
+    gradients, timed to the gradients; instance 0 against the oracle.  The
+    same with the spatial-FFT direct inner solve (exact for this periodic
+    constant-coefficient operator) under "fft_inner"."""
     w = wl.WORKLOADS["advdiff2d_512_adj"]
-    plan = plan_for(w)
     u0 = wl.initial_batch(w)
-    plan.set_u0(torch.as_tensor(u0, device="cuda"))
     ut = wl.target_batch(w)
     utd = torch.as_tensor(ut, device="cuda")
     al = [w.alpha] if w.alpha > 0 else None
 
-    def once():
-        u, info = plan.solve(tol=w.tol, stop=w.stop, max_iter=50, alphas=al)
-        lam, ainfo = plan.adjoint_solve(u[:, -1, -1, :] - utd, tol=w.tol, max_iter=50)
-        gu0, gnu = plan.grad(u, lam)
-        return u, lam, gu0, gnu, info, ainfo
+    def run(wk):
+        plan = plan_for(wk)
+        plan.set_u0(torch.as_tensor(u0, device="cuda"))
 
-    print("bench: adjoint on %s" % w.name, file=sys.stderr, flush=True)
-    once()  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    n = 2
-    for _ in range(n):
-        u, lam, gu0, gnu, info, ainfo = once()
-    torch.cuda.synchronize()
-    el = (time.perf_counter() - t0) / n
-    sw = info["iterations"] + ainfo["iterations"]
-    res = {"workload": w.name, "dof": w.dof, "batch": w.batch, "precision": w.precision, "inner": w.inner,
-           "time_to_gradient_s": el, "forward_sweeps": info["iterations"], "adjoint_sweeps": ainfo["iterations"],
-           "dof_sweeps_per_s": w.dof * sw / el}
+        def once():
+            u, info = plan.solve(tol=wk.tol, stop=wk.stop, max_iter=50, alphas=al)
+            lam, ainfo = plan.adjoint_solve(u[:, -1, -1, :] - utd, tol=wk.tol, max_iter=50)
+            gu0, gnu = plan.grad(u, lam)
+            return u, lam, gu0, gnu, info, ainfo
+
+        print("bench: adjoint on %s (%s inner)" % (wk.name, wk.inner), file=sys.stderr, flush=True)
+        once()  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = 2
+        for _ in range(n):
+            u, lam, gu0, gnu, info, ainfo = once()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / n
+        sw = info["iterations"] + ainfo["iterations"]
+        res = {"workload": wk.name, "dof": wk.dof, "batch": wk.batch, "precision": wk.precision, "inner": wk.inner,
+               "time_to_gradient_s": el, "forward_sweeps": info["iterations"], "adjoint_sweeps": ainfo["iterations"],
+               "dof_sweeps_per_s": wk.dof * sw / el}
+        out = (u[0].cpu().numpy(), lam[0].cpu().numpy(), gu0[0].cpu().numpy(), float(gnu[0]))
+        del plan
+        torch.cuda.empty_cache()
+        return res, out
+
+    res, got = run(w)
+    res_fft, got_fft = run(w.with_(inner="fft"))
     if with_oracle:
         import oracle
         op = oracle.stencil_for(w.kind, w.nx, w.ny, nu=w.nu, c=w.vel, order=w.order)
@@ -234,9 +245,10 @@ def adjoint_block(np, torch, wl, plan_for, with_oracle):
         g0, gn = oracle.gradients(op, Q, w.dt, Uo, lo)
         res["oracle_instance_time_s"] = time.perf_counter() - t1
         rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
-        res["instance0_rel_l2_vs_oracle"] = {"u": rel(u[0].cpu().numpy(), Uo), "lambda": rel(lam[0].cpu().numpy(), lo),
-                                             "dJ_du0": rel(gu0[0].cpu().numpy(), g0),
-                                             "dJ_dnu": abs(float(gnu[0]) - gn) / abs(gn)}
+        for r_, (uu, ll, gg, gv) in ((res, got), (res_fft, got_fft)):
+            r_["instance0_rel_l2_vs_oracle"] = {"u": rel(uu, Uo), "lambda": rel(ll, lo), "dJ_du0": rel(gg, g0),
+                                                "dJ_dnu": abs(gv - gn) / abs(gn)}
+    res["fft_inner"] = res_fft
     return res
 
 
