@@ -429,6 +429,7 @@ void cg_tiling(aao::CgArgs& a, const aao_plan* p, bool small) {
 
 aao::CgArgs cg_args(aao_plan* p, int adj, int nsys) {
   aao::CgArgs a{};
+  a.snap_row = -1;  // no snapshot row unless a pass is given one
   a.X = p->vec(0);
   a.R[0] = p->vec(1);
   a.R[1] = p->vec(2);
@@ -466,11 +467,14 @@ struct LagCheck {
   int nsys;
   int tag[2] = {0, 0};
   int pending = -1, cur = 0;
+  int deferred = -1;  // slot of a snapshot that the next fused COCG pass takes (-1: none)
 };
 
 // Start a new snapshot; if an earlier one is outstanding, wait for it first
-// and make its list current (n_out = its count, else -1).
-aao_status lag_check(LagCheck& c, int& nact, const int*& list, int& n_out, bool final_check) {
+// and make its list current (n_out = its count, else -1).  defer: the next
+// fused COCG pass takes the snapshot (one extra workgroup) instead of a
+// kernel of its own.
+aao_status lag_check(LagCheck& c, int& nact, const int*& list, int& n_out, bool final_check, bool defer = false) {
   aao_plan* p = c.p;
   n_out = -1;
   if (c.pending >= 0) {
@@ -492,9 +496,13 @@ aao_status lag_check(LagCheck& c, int& nact, const int*& list, int& n_out, bool 
     if (n == 0 || final_check) return AAO_OK;
   }
   c.tag[c.cur] = ++p->snap_tag;
-  close_run(p);
-  HIPCHK(aao::launch_compact_active(p->st(), c.nsys, p->dlist(c.cur), p->hlist + 2 * c.cur, c.tag[c.cur],
-                                    p->stream));
+  if (defer) {
+    c.deferred = c.cur;
+  } else {
+    close_run(p);
+    HIPCHK(aao::launch_compact_active(p->st(), c.nsys, p->dlist(c.cur), p->hlist + 2 * c.cur, c.tag[c.cur],
+                                      p->stream));
+  }
   c.pending = c.cur;
   c.cur ^= 1;
   return AAO_OK;
@@ -541,14 +549,25 @@ aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
   // only records the iteration cap); else a scalar kernel follows each pass
   const int last = a.fused ? p->inner_maxit : p->inner_maxit - 1;
   for (int k = 0; k <= last; ++k) {
+    a.snap_row = -1;
+    if (c.deferred >= 0) {  // this pass also lists the systems still iterating after pass k - 1
+      a.snap_row = nact;
+      a.snap_k = k - 1;
+      a.snap_n = nsys;
+      a.snap_tag = c.tag[c.deferred];
+      a.snap_list = p->dlist(c.deferred);
+      a.snap_host = p->hlist + 2 * c.deferred;
+      c.deferred = -1;
+    }
     HIPCHK(timed(p, aao::KC_COCG_A, [&] { return aao::launch_cg_pass(p->f32, a, k, nact, p->stream); }));
+    a.snap_row = -1;
     a.ntiles_prev = a.ntiles;
     if (!a.fused)
       HIPCHK(timed(p, aao::KC_MISC, [&] { return aao::launch_cg_scalars(a, k, nact, p->stream); }));
     if (k + 1 == next_check) {
       next_check += (k < 16) ? 4 : 8;
       int n;
-      aao_status s = lag_check(c, nact, a.sys_list, n, false);
+      aao_status s = lag_check(c, nact, a.sys_list, n, false, a.fused != 0);
       if (s != AAO_OK) return s;
       if (n == 0) break;
       // few systems left: the passes are bound by latency, and small tiles
@@ -558,6 +577,10 @@ aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
         small = true;
       }
     }
+  }
+  if (c.deferred >= 0) {  // requested after the last pass: no pass takes it
+    c.deferred = -1;
+    c.pending = -1;
   }
   if (c.pending >= 0) {  // drain the last outstanding snapshot
     int n;

@@ -196,6 +196,35 @@ __device__ __forceinline__ void ring_slot(const CgArgs& a, const TileGeo& G, int
                                                                                      : -1;
 }
 
+// Snapshot of the systems still iterating after pass snap_k, taken by one
+// extra workgroup of the next pass: stop_pass is "never" while a system
+// iterates and is set once, to the pass that stops it, so a system counts as
+// active iff stop_pass > snap_k, also while this very pass may be stopping it
+// (that write only turns "never" into snap_k + 1).  The list is therefore the
+// same as reading the active flags after pass snap_k.
+__device__ __forceinline__ void cg_snapshot(const CgArgs& a) {
+  __shared__ int wcnt[kBlock / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int total = 0;
+  for (int base = 0; base < a.snap_n; base += kBlock) {
+    const int i = base + t;
+    const bool act = i < a.snap_n && a.st[i].stop_pass > a.snap_k;
+    const unsigned long long bal = __ballot(act);
+    if (lane == 0) wcnt[w] = __popcll(bal);
+    __syncthreads();
+    int o = total;
+    for (int j = 0; j < w; ++j) o += wcnt[j];
+    if (act) a.snap_list[o + __popcll(bal & ((1ull << lane) - 1))] = i;
+    total += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+  }
+  if (t == 0) {
+    a.snap_host[0] = total;
+    __threadfence_system();
+    a.snap_host[1] = a.snap_tag;
+  }
+}
+
 // x in a pass: XM_SKIP x untouched (k even), XM_TWO both updates (k odd).
 enum : int { XM_SKIP = 1, XM_TWO = 2 };
 
@@ -269,6 +298,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
   __shared__ double sh[4 * kQ];
   __shared__ int act;
   __shared__ double2 sc[2];
+  if ((int)blockIdx.y == a.snap_row) {  // the extra row: one workgroup takes the snapshot
+    if (blockIdx.x == 0) cg_snapshot(a);
+    return;
+  }
   const int t = threadIdx.x;
   const int s = a.sys_list[blockIdx.y];
   const int tile = tile_of_block(a);
@@ -600,7 +633,10 @@ hipError_t launch_cg_init(bool f32, const CgArgs& a, int nact, hipStream_t st) {
 hipError_t launch_cg_pass(bool f32, const CgArgs& a, int k, int nact, hipStream_t st) {
   if (a.TX * a.TY > kInside * kBlock) return hipErrorInvalidValue;
   if (a.fused && (a.ntiles > kBlock || a.ntiles_prev < 1 || a.ntiles_prev > kBlock)) return hipErrorInvalidValue;
-  dim3 grid(a.ntiles, nact);
+  if (a.snap_row >= 0 && (!a.fused || a.snap_row != nact || !a.snap_list || !a.snap_host || a.snap_n < 1 ||
+                          a.snap_n > a.num_sys))
+    return hipErrorInvalidValue;
+  dim3 grid(a.ntiles, nact + (a.snap_row >= 0 ? 1 : 0));
   const size_t lds = cg_lds_bytes(f32, a);
   const int nh = cg_ring_slots(a);
   const int nt = (a.taps.n == 3 || a.taps.n == 5) ? a.taps.n : 0;

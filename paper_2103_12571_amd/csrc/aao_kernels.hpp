@@ -70,6 +70,13 @@ struct CgArgs {
   size_t part_stride;
   double tol2;
   int maxit;
+  // fused passes: when snap_row >= 0 the launch has one more row of
+  // workgroups (row snap_row == the active count); its first workgroup lists
+  // the systems with stop_pass > snap_k (still iterating after pass snap_k)
+  // into snap_list, then writes their count and snap_tag to snap_host
+  int snap_row, snap_k, snap_n, snap_tag;
+  int* snap_list;
+  int* snap_host;
 };
 
 // Forward transform + fused residual (rows a1, a2).
