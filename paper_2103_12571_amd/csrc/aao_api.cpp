@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -118,7 +119,9 @@ struct aao_plan {
   int cgTXs = 0, cgTYs = 0, cg_ntxs = 0, cg_ntiles_s = 0;  // small tiling (cg_ntiles_s = 0: none)
   int fft_rows = 1, fft_cols = 1;
   int Px = 0, Py = 0;  // Bluestein lengths of x / y for the FFT inner solve (0: power of two)
-  int* hlist = nullptr;      // pinned: (count, tag) of the active-system snapshots, per slot
+  int* hlist = nullptr;      // pinned: (count, tag) of the active-system snapshots, per slot; from
+                             // byte 64 the end-of-sweep report (k_sweep_report)
+  int rep_tag = 0;           // tag of the latest end-of-sweep report
   int snap_tag = 0;          // tag of the latest snapshot
   bool f32 = false;
   size_t csize = 16;
@@ -678,6 +681,25 @@ struct SweepOut {
   int inner_max = 0, inner_fail = 0;
 };
 
+// Work of the inner solves of one sweep: sum and sum of max(iters - 1, 0)
+// over the systems, and (COCG) the words of cocg_words summed.
+void account_inner(aao_plan* p, int nsys, double sum, double later, double words) {
+  if (nsys <= 0) return;
+  const double n = (double)p->N;
+  if (p->inner == AAO_INNER_FFT) {
+    // counted in inner_solve_fft
+  } else if (p->inner == AAO_INNER_COCG) {
+    p->work_first[aao::KC_COCG_B] += n * nsys;  // init pass
+    p->bytes_direct[aao::KC_COCG_A] += n * words * (double)p->csize;
+    p->elems_direct[aao::KC_COCG_A] += n * sum;
+  } else {
+    for (int c : {aao::KC_BICG_1, aao::KC_BICG_2, aao::KC_BICG_3}) {
+      p->work_first[c] += n * nsys;
+      p->work_later[c] += n * later;
+    }
+  }
+}
+
 // Read norms and per-system Krylov statistics (synchronises the stream).
 aao_status read_back(aao_plan* p, int nsys, bool want_norms, SweepOut& o) {
   close_run(p);
@@ -703,23 +725,35 @@ aao_status read_back(aao_plan* p, int nsys, bool want_norms, SweepOut& o) {
     if (hs[s].flag != 0) o.inner_fail += 1;
   }
   o.inner_mean = nsys ? sum / nsys : 0;
-  if (nsys > 0) {
-    const double n = (double)p->N;
-    if (p->inner == AAO_INNER_FFT) {
-      // counted in inner_solve_fft
-    } else if (p->inner == AAO_INNER_COCG) {
-      p->work_first[aao::KC_COCG_B] += n * nsys;  // init pass
-      double words = 0;  // x moves every other pass
-      for (int s = 0; s < nsys; ++s) words += cocg_words(hs[s].iters);
-      p->bytes_direct[aao::KC_COCG_A] += n * words * (double)p->csize;
-      p->elems_direct[aao::KC_COCG_A] += n * sum;
-    } else {
-      for (int c : {aao::KC_BICG_1, aao::KC_BICG_2, aao::KC_BICG_3}) {
-        p->work_first[c] += n * nsys;
-        p->work_later[c] += n * later;
-      }
+  double words = 0;  // x moves every other pass
+  if (p->inner == AAO_INNER_COCG)
+    for (int s = 0; s < nsys; ++s) words += cocg_words(hs[s].iters);
+  account_inner(p, nsys, sum, later, words);
+  return AAO_OK;
+}
+
+// Wait for the end-of-sweep report tag (spin briefly, then block on the
+// stream) and take the norms and iteration statistics from it.
+aao_status read_report(aao_plan* p, int nsys, int tag, SweepOut& o) {
+  close_run(p);
+  const double* hr = reinterpret_cast<const double*>(reinterpret_cast<char*>(p->hlist) + 64);
+  volatile const int* ht = reinterpret_cast<volatile const int*>(hr + 8);
+  const auto t0 = std::chrono::steady_clock::now();
+  while (*ht != tag) {
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
+      HIPCHK(hipStreamSynchronize(p->stream));
+      if (*ht != tag) return fail(AAO_EHIP, "end-of-sweep report did not reach host memory");
+      break;
     }
   }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  o.res2 = hr[0];
+  o.dmax = hr[1];
+  const double sum = hr[2], later = hr[3];
+  o.inner_max = (int)hr[4];
+  o.inner_fail = (int)hr[5];
+  o.inner_mean = nsys ? sum / nsys : 0;
+  account_inner(p, nsys, sum, later, hr[6]);
   return AAO_OK;
 }
 
@@ -730,7 +764,7 @@ aao_status alloc_tables(aao_plan* p) {
   HIPCHK(hipMalloc(&p->dtab, p->tab_bytes));
   HIPCHK(hipHostMalloc(&p->htab, 2 * p->atab_stride, hipHostMallocDefault));
   HIPCHK(hipHostMalloc(&p->hread, p->hread_bytes, hipHostMallocDefault));
-  HIPCHK(hipHostMalloc(&p->hlist, 64, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc(&p->hlist, 256, hipHostMallocDefault));
   std::memset(p->hlist, 0, 64);  // tags start at 1
   std::vector<double2> tw(p->L / 2 + 1);
   for (int k = 0; k < (int)tw.size(); ++k) {
@@ -813,12 +847,15 @@ aao_status do_sweep(aao_plan* p, double* u, double alpha, int adj, double res_st
   if (s != AAO_OK) return s;
   aao::BwdArgs ba = bwd_args(p, u);
   HIPCHK(timed(p, aao::KC_BWD, [&] { return aao::launch_bwd(p->M, adj, false, f32, ba, p->B, p->stream); }));
+  const int tag = ++p->rep_tag;
+  double* hr = reinterpret_cast<double*>(reinterpret_cast<char*>(p->hlist) + 64);
   HIPCHK(timed(p, aao::KC_MISC, [&] {
-    return aao::launch_finalize(p->fb(), nt, p->fb() + p->fb_slots, nt, p->norms(), p->stream);
+    return aao::launch_sweep_report(p->fb(), nt, p->fb() + p->fb_slots, nt, p->norms(), p->st(), p->S,
+                                    p->inner == AAO_INNER_COCG, hr, tag, p->stream);
   }));
   if (next_alpha > 0) prefetch_tables(p, next_alpha, adj);
   double keep = o.res2;
-  s = read_back(p, p->S, true, o);
+  s = read_report(p, p->S, tag, o);
   if (s != AAO_OK) return s;
   if (res_stop > 0) o.res2 = keep;
   if (!std::isfinite(o.res2) || !std::isfinite(o.dmax)) return fail(AAO_ENAN, "sweep produced a non-finite norm");
@@ -1238,15 +1275,36 @@ aao_status aao_sweep(aao_plan_t p, double* u, double alpha, double* res_rel, dou
   SweepOut o;
   bool stopped;
   s = do_sweep(p, u, alpha, 0, 0.0, 0.0, o, stopped);
+  close_run(p);
+  const hipError_t e = hipStreamSynchronize(p->stream);
+  collect_timing(p);
   if (s != AAO_OK) return s;
+  if (e != hipSuccess) return fail(AAO_EHIP, std::string("HIP: ") + hipGetErrorString(e));
   if (res_rel) *res_rel = std::sqrt(o.res2) / std::sqrt(p->w2);
   if (dlast_inf) *dlast_inf = o.dmax;
   return AAO_OK;
 }
 
+static aao_status run_solve_sweeps(aao_plan_t p, double* u, const double* alphas, int n_alphas, double m0,
+                                   double tol, int stop_rule, int max_iter, aao_solve_info* info, int adj,
+                                   double gnorm_inf);
+
+// The sweeps read their reports without synchronising the stream; the timing
+// events of the solve are collected once at its end.
 static aao_status run_solve(aao_plan_t p, double* u, const double* alphas, int n_alphas, double m0,
                             double tol, int stop_rule, int max_iter, aao_solve_info* info, int adj,
                             double gnorm_inf) {
+  aao_status s = run_solve_sweeps(p, u, alphas, n_alphas, m0, tol, stop_rule, max_iter, info, adj, gnorm_inf);
+  close_run(p);
+  hipError_t e = hipStreamSynchronize(p->stream);
+  collect_timing(p);
+  if (s == AAO_OK && e != hipSuccess) return fail(AAO_EHIP, std::string("HIP: ") + hipGetErrorString(e));
+  return s;
+}
+
+static aao_status run_solve_sweeps(aao_plan_t p, double* u, const double* alphas, int n_alphas, double m0,
+                                   double tol, int stop_rule, int max_iter, aao_solve_info* info, int adj,
+                                   double gnorm_inf) {
   if (!info) return fail(AAO_EINVAL, "null info");
   if (max_iter < 1) return fail(AAO_EINVAL, "max_iter must be >= 1");
   if (alphas && n_alphas < 1) return fail(AAO_EINVAL, "n_alphas must be >= 1");

@@ -330,6 +330,57 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* ps, int ns, c
   }
 }
 
+// Complex words per element that the COCG passes of a system with ks
+// iterations moved (x moves every other pass; see the pass kernel).
+__device__ __forceinline__ double cocg_words_dev(int ks) {
+  double w = 0;
+  for (int k = 0; k < ks; ++k) {
+    w += (k > 0) ? 4 : 3;
+    if (k & 1) w += (k >= 3) ? 2 : 1;
+  }
+  if (ks & 1) w += (ks >= 3) ? 3 : 2;
+  return w;
+}
+
+// End of a sweep: the norms of k_finalize, and the per-system iteration
+// statistics (sum, sum of max(iters - 1, 0), max, count with flag != 0, and
+// with cocg the bytes words), written to out and then to pinned host memory
+// rep[0 .. 6] followed, after a system-scope fence, by the tag in rep[8].
+__global__ __launch_bounds__(kBlock) void k_sweep_report(const double* ps, int ns, const double* pm, int nm,
+                                                         double* out, const SysState* st, int nsys, int cocg,
+                                                         double* rep, int tag) {
+  __shared__ double sh[4 * 8];
+  double s = 0.0, mx = 0.0;
+  for (int i = threadIdx.x; i < ns; i += kBlock) s += ps[i];
+  for (int i = threadIdx.x; i < nm; i += kBlock) mx = fmax(mx, pm[i]);
+  double v[5] = {s, 0.0, 0.0, 0.0, 0.0};
+  double imax = 0.0;
+  for (int i = threadIdx.x; i < nsys; i += kBlock) {
+    const int it = st[i].iters;
+    v[1] += it;
+    v[2] += it > 1 ? it - 1 : 0;
+    v[3] += st[i].flag != 0 ? 1.0 : 0.0;
+    if (cocg) v[4] += cocg_words_dev(it);
+    imax = fmax(imax, (double)it);
+  }
+  block_sum<5>(v, sh);
+  mx = block_max(mx, sh);
+  imax = block_max(imax, sh);
+  if (threadIdx.x == 0) {
+    out[0] = v[0];
+    out[1] = mx;
+    rep[0] = v[0];
+    rep[1] = mx;
+    rep[2] = v[1];
+    rep[3] = v[2];
+    rep[4] = imax;
+    rep[5] = v[3];
+    rep[6] = v[4];
+    __threadfence_system();
+    reinterpret_cast<volatile int*>(rep + 8)[0] = tag;
+  }
+}
+
 __global__ void k_init_u(double* u, const double* u0, int B, int L, int M, int N) {
   const size_t total = (size_t)B * L * M * N;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
@@ -865,6 +916,13 @@ int residual_blocks(int B, int L, int N) { return grid_for((int64_t)B * L * N, k
 hipError_t launch_finalize(const double* ps, int ns, const double* pm, int nm, double* out,
                            hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, ps, ns, pm, nm, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_report(const double* ps, int ns, const double* pm, int nm, double* out, const SysState* sst,
+                               int nsys, bool cocg, double* rep, int tag, hipStream_t st) {
+  hipLaunchKernelGGL(k_sweep_report, dim3(1), dim3(kBlock), 0, st, ps, ns, pm, nm, out, sst, nsys, cocg ? 1 : 0, rep,
+                     tag);
   return hipGetLastError();
 }
 

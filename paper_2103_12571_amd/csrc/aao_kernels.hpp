@@ -177,6 +177,10 @@ hipError_t launch_residual(int M, bool adj, const FwdArgs& a, double* r_out, int
 hipError_t launch_finalize(const double* part_sum, int n_sum, const double* part_max, int n_max,
                            double* out, hipStream_t st);
 hipError_t launch_init_u(double* u, const double* u0, int B, int L, int M, int N, hipStream_t st);
+// launch_finalize plus the sweep's iteration statistics, all also written to
+// pinned host memory rep[0..6], then tag to rep[8] (as an int).
+hipError_t launch_sweep_report(const double* ps, int ns, const double* pm, int nm, double* out, const SysState* sst,
+                               int nsys, bool cocg, double* rep, int tag, hipStream_t st);
 hipError_t launch_last_node(const double* u, double* out, int B, int L, int M, int N, hipStream_t st);
 hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t st);
 hipError_t launch_norms_bn(const double* v, int B, int N, double* part, int nparts,
