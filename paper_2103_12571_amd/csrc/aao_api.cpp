@@ -536,12 +536,15 @@ double cocg_words(int ks) {
 aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
   aao::CgArgs a = cg_args(p, adj, nsys);
   aao::KrylovArgs ka = krylov_args(p, adj, nsys);
-  close_run(p);
-  HIPCHK(aao::launch_krylov_init(ka, p->stream));  // all active: the initial list is 0 .. nsys-1
-  close_run(p);
-  HIPCHK(aao::launch_compact_active(p->st(), nsys, p->dlist(2), nullptr, 0, p->stream));
-  int nact = nsys;
+  int nact = nsys;  // all active: the initial list is 0 .. nsys - 1
+  if (a.fused) {
+    a.init_list = p->dlist(2);  // the init pass writes the fresh states and the list
+  } else {
+    close_run(p);
+    HIPCHK(aao::launch_krylov_init(ka, p->stream, p->dlist(2)));
+  }
   HIPCHK(timed(p, aao::KC_COCG_B, [&] { return aao::launch_cg_init(p->f32, a, nact, p->stream); }));
+  a.init_list = nullptr;
   if (!a.fused) HIPCHK(timed(p, aao::KC_MISC, [&] { return aao::launch_cg_scalars(a, -1, nact, p->stream); }));
   LagCheck c;
   aao_status ls = lag_begin(p, c, nsys);
@@ -643,9 +646,7 @@ aao_status inner_solve(aao_plan* p, int adj, int nsys) {
   if (p->inner == AAO_INNER_FFT) return inner_solve_fft(p, adj, nsys);
   aao::KrylovArgs a = krylov_args(p, adj, nsys);
   close_run(p);
-  HIPCHK(aao::launch_krylov_init(a, p->stream));
-  close_run(p);
-  HIPCHK(aao::launch_compact_active(p->st(), nsys, p->dlist(2), nullptr, 0, p->stream));
+  HIPCHK(aao::launch_krylov_init(a, p->stream, p->dlist(2)));  // all active: the list is 0 .. nsys - 1
   int nact = nsys;
   LagCheck c;
   aao_status ls = lag_begin(p, c, nsys);

@@ -237,8 +237,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
   extern __shared__ char smem[];
   __shared__ double sh[4 * kQ];
   const int t = threadIdx.x;
-  const int s = a.sys_list[blockIdx.y];
+  const int s = a.init_list ? (int)blockIdx.y : a.sys_list[blockIdx.y];
   const int tile = tile_of_block(a);
+  if (a.init_list && tile == 0 && t == 0) {  // read by the passes, after this kernel
+    a.st[s] = fresh_state();
+    a.init_list[s] = s;
+  }
   const TileGeo G = tile_geo(a, tile);
   const V* Rb = reinterpret_cast<const V*>(a.R[0]) + (size_t)s * a.g.N;
   const LdsCplx<V> Bt(smem, G.PW * G.PH);

@@ -697,24 +697,10 @@ __global__ __launch_bounds__(kBlock) void k_bicg3(KrylovArgs a, int k) {
   write_parts<3>(a, qs, s, w, sh);
 }
 
-__global__ void k_krylov_init(SysState* st, int n) {
+__global__ void k_krylov_init(SysState* st, int n, int* list) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    SysState z;
-    z.active = 1;
-    z.iters = 0;
-    z.flag = 0;
-    z.breakdown = 0;
-    z.stop_pass = 0x7fffffff;
-    z.rho = mk(1, 0);
-    z.alpha = mk(1, 0);
-    z.omega = mk(1, 0);
-    z.beta = mk(0, 0);
-    z.gamma = mk(0, 0);
-    z.bb = 0.0;
-    z.rr = 0.0;
-    z.gamma2[0] = z.gamma2[1] = mk(0, 0);
-    z.alpha2[0] = z.alpha2[1] = mk(0, 0);
-    st[i] = z;
+    st[i] = fresh_state();
+    if (list) list[i] = i;
   }
 }
 
@@ -989,8 +975,8 @@ hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, int nact
   return hipGetLastError();
 }
 
-hipError_t launch_krylov_init(const KrylovArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_krylov_init, dim3(grid_for(a.num_sys)), dim3(kBlock), 0, st, a.st, a.num_sys);
+hipError_t launch_krylov_init(const KrylovArgs& a, hipStream_t st, int* list) {
+  hipLaunchKernelGGL(k_krylov_init, dim3(grid_for(a.num_sys)), dim3(kBlock), 0, st, a.st, a.num_sys, list);
   return hipGetLastError();
 }
 

@@ -41,6 +41,20 @@ struct SysState {
   double2 alpha2[2];
 };
 
+// State of a system before its first Krylov iteration.
+__host__ __device__ inline SysState fresh_state() {
+  SysState z{};
+  z.active = 1;
+  z.iters = 0;
+  z.flag = 0;
+  z.breakdown = 0;
+  z.stop_pass = 0x7fffffff;
+  z.rho = double2{1.0, 0.0};
+  z.alpha = double2{1.0, 0.0};
+  z.omega = double2{1.0, 0.0};
+  return z;
+}
+
 // Single-pass COCG over 2D tiles (row a3).  Pass k reads R[k&1], P[(k+1)&1]
 // and X, writes R[(k+1)&1], P[k&1] and X; the LDS tile holds p on a two-hop
 // halo and r_{k+1} on a one-hop halo so that s = (I - cA) p and
@@ -68,6 +82,9 @@ struct CgArgs {
   // partial buffers (5 num_sys times the larger tile count)
   int ntiles_prev;
   size_t part_stride;
+  // first init pass of a solve: workgroup row y is system y (every system
+  // active), and tile 0 writes its fresh state and init_list[y] = y
+  int* init_list;
   double tol2;
   int maxit;
   // fused passes: when snap_row >= 0 the launch has one more row of
@@ -206,7 +223,9 @@ hipError_t launch_cg_xfix(bool f32, const CgArgs& a, int nsys, hipStream_t st);
 size_t cg_lds_bytes(bool f32, const CgArgs& a);
 int cg_ring_slots(const CgArgs& a);
 hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, int nact, hipStream_t st);
-hipError_t launch_krylov_init(const KrylovArgs& a, hipStream_t st);
+// Fresh state for systems 0 .. num_sys - 1, and list[i] = i when list is given
+// (every system starts active).
+hipError_t launch_krylov_init(const KrylovArgs& a, hipStream_t st, int* list = nullptr);
 hipError_t launch_fft_solve(bool f32, const FftArgs& a, int nsys, hipStream_t st);
 hipError_t launch_compact_active(const SysState* st, int n, int* list, int* count_tag, int tag, hipStream_t s);
 hipError_t launch_copy_c128_in(void* dst, bool f32, const double* src, int64_t n, hipStream_t st);
