@@ -989,7 +989,7 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   }
   for (int i = 0; i < A->ntaps; ++i) p->Anorm_inf += std::abs(A->coef[i]);
 
-  // tiling of the DFT over l: TN spatial points per workgroup, LDS <= 48 KB
+  // tiling of the DFT over l: TN spatial points per workgroup, LDS planes <= AAO_XFORM_LDS_KB
   int TN = 64;
   while (TN > 2 && (size_t)p->L * p->M * TN * 8 > AAO_XFORM_LDS_KB * 1024) TN >>= 1;
   p->TN = TN;

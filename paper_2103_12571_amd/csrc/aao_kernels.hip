@@ -47,11 +47,21 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
     twi[i] = a.tw[i].y;
   }
 
+  // TN divides kBlock, so the spatial point of a thread is the same in every
+  // row l it visits: its coordinates and the unrolled taps' neighbour offsets
+  // are computed once.  Two rows per loop trip (their loads in flight together)
+  // also keep the register count below that of the per-row form.
+  const int nl = threadIdx.x & (TN - 1);
+  const int n = n0 + nl;
+  const int x = n % a.g.nx, y = n / a.g.nx;
+  int nbs[NT > 0 ? NT : 1];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) nbs[t] = wrap_index(x, y, a.taps.dx[t], a.taps.dy[t], a.g);
+  double* dst = ((nl & 1) ? cim : cre) + (nl >> 1);
+
   double res2 = 0.0;
-  for (int idx = threadIdx.x; idx < L * TN; idx += kBlock) {
-    const int l = idx >> a.logTN;
-    const int nl = idx & (TN - 1);
-    const int n = n0 + nl;
+#pragma unroll 2
+  for (int l = threadIdx.x >> a.logTN; l < L; l += (kBlock >> a.logTN)) {
     double rv[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) rv[m] = 0.0;
@@ -62,21 +72,19 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
         for (int m = 0; m < M; ++m) rv[m] = a.u[base + (size_t)m * N + n];
       } else {
         const double* ul = a.u + base;
-        const int x = n % a.g.nx, y = n / a.g.nx;
         double v[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) v[m] = 0.0;
-        auto tap = [&](int t) {
-          const int nb = wrap_index(x, y, a.taps.dx[t], a.taps.dy[t], a.g);
+        auto tap = [&](int t, int nb) {
           const double ct = a.taps.c[t];
 #pragma unroll
           for (int m = 0; m < M; ++m) v[m] = fma(ct, ul[(size_t)m * N + nb], v[m]);
         };
         if (NT > 0) {
 #pragma unroll
-          for (int t = 0; t < NT; ++t) tap(t);
+          for (int t = 0; t < NT; ++t) tap(t, nbs[t]);
         } else {
-          for (int t = 0; t < a.taps.n; ++t) tap(t);
+          for (int t = 0; t < a.taps.n; ++t) tap(t, wrap_index(x, y, a.taps.dx[t], a.taps.dy[t], a.g));
         }
         double f[M];  // source at the collocation times (eq. (collocation): dT Q b_l)
 #pragma unroll
@@ -115,7 +123,6 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
     }
     const double sc = a.scale[l];
     const int lr = bitrev(l, a.logL);
-    double* dst = ((nl & 1) ? cim : cre) + (nl >> 1);
 #pragma unroll
     for (int m = 0; m < M; ++m) dst[((size_t)lr * M + m) * P] = rv[m] * sc;
   }
@@ -124,9 +131,10 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
   lds_fft<false>(cre, cim, twr, twi, L, a.logL, ncol);
 
   OutV* out = reinterpret_cast<OutV*>(a.out);
+  const int logP = a.logTN - 1;
   for (int idx = threadIdx.x; idx < a.Lh * P; idx += kBlock) {
-    const int j = idx / P;
-    const int p = idx - j * P;
+    const int j = idx >> logP;
+    const int p = idx & (P - 1);
     const int jm = (L - j) & (L - 1);
     double2 A[M], Bv[M];
 #pragma unroll
