@@ -126,7 +126,7 @@ typedef struct {
 /* Per kernel class: launches, elements processed, event-timed milliseconds and
  * algorithmic bytes moved.  Timing is collected only while enabled by
  * aao_set_timing(plan, 1).  Classes: see aao_kernel_name(). */
-#define AAO_NUM_KERNELS 13
+#define AAO_NUM_KERNELS 14
 typedef struct {
   int64_t launches[AAO_NUM_KERNELS];
   double elements[AAO_NUM_KERNELS];

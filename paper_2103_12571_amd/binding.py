@@ -18,7 +18,7 @@ AAO_FP64, AAO_MIXED = 0, 1
 AAO_INNER_COCG, AAO_INNER_BICGSTAB, AAO_INNER_FFT = 0, 1, 2
 AAO_STOP_LASTSTEP, AAO_STOP_RESIDUAL = 0, 1
 AAO_MAX_HIST = 64
-AAO_NUM_KERNELS = 13
+AAO_NUM_KERNELS = 14
 
 STATUS_NAMES = {0: "AAO_OK", -1: "AAO_EINVAL", -2: "AAO_EHIP", -3: "AAO_ENODIAG", -4: "AAO_ENOCONV",
                 -5: "AAO_ESTAGNATE", -6: "AAO_EWORKSPACE", -7: "AAO_ENAN", -8: "AAO_ESTATE"}

@@ -645,6 +645,10 @@ aao_status inner_solve(aao_plan* p, int adj, int nsys) {
   if (p->inner == AAO_INNER_COCG) return inner_solve_cg(p, adj, nsys);
   if (p->inner == AAO_INNER_FFT) return inner_solve_fft(p, adj, nsys);
   aao::KrylovArgs a = krylov_args(p, adj, nsys);
+  if (aao::bicg_wg_fits(p->N)) {  // one workgroup runs every iteration of one system
+    HIPCHK(timed(p, aao::KC_BICG_WG, [&] { return aao::launch_bicg_wg(p->f32, a, nsys, p->stream); }));
+    return AAO_OK;
+  }
   close_run(p);
   HIPCHK(aao::launch_krylov_init(a, p->stream, p->dlist(2)));  // all active: the list is 0 .. nsys - 1
   int nact = nsys;
@@ -693,6 +697,9 @@ void account_inner(aao_plan* p, int nsys, double sum, double later, double words
     p->work_first[aao::KC_COCG_B] += n * nsys;  // init pass
     p->bytes_direct[aao::KC_COCG_A] += n * words * (double)p->csize;
     p->elems_direct[aao::KC_COCG_A] += n * sum;
+  } else if (aao::bicg_wg_fits(p->N)) {  // reads b, writes x and the last residual
+    p->bytes_direct[aao::KC_BICG_WG] += 3.0 * n * nsys * (double)p->csize;
+    p->elems_direct[aao::KC_BICG_WG] += n * sum;
   } else {
     for (int c : {aao::KC_BICG_1, aao::KC_BICG_2, aao::KC_BICG_3}) {
       p->work_first[c] += n * nsys;
@@ -897,7 +904,7 @@ const char* aao_kernel_name(int c) {
   static const char* names[AAO_NUM_KERNELS] = {
       "fwd_residual_dft_l", "bwd_idft_l_update", "cocg_pass", "cocg_init",
       "bicgstab_p_matvec", "bicgstab_s_matvec", "bicgstab_update", "fft_inner",
-      "residual", "misc", "init", "grad", "gmres_orth"};
+      "residual", "misc", "init", "grad", "gmres_orth", "bicgstab_wg"};
   return (c >= 0 && c < AAO_NUM_KERNELS) ? names[c] : "";
 }
 

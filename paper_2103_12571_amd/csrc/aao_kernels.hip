@@ -705,6 +705,194 @@ __global__ __launch_bounds__(kBlock) void k_bicg3(KrylovArgs a, int k) {
   write_parts<3>(a, qs, s, w, sh);
 }
 
+// BiCGStab for a whole system in one workgroup, for systems of at most
+// kWgCap points: the iteration of k_bicg1..3 (same scalars, same
+// stopping test at the start of each iteration k >= 1, same breakdown flags),
+// with thread t of BLK owning the points t + BLK j (j < kWgCap / BLK), the
+// vectors r, p, v, t, x of
+// its points in registers, the vector that the stencil reads in LDS, and
+// block-wide sums in place of the chunk partial sums.  One launch runs every
+// iteration of every system, one workgroup each; nothing is shared between
+// workgroups, and each loop ends at the iteration cap at the latest.
+// complex128 takes 1024 threads (four points each), complex64 512 (eight):
+// the largest workgroups whose vectors stay in registers without spills.
+constexpr int kWgCap = 4096;
+template <typename T> struct WgShape { static constexpr int BLK = 1024; };
+template <> struct WgShape<float> { static constexpr int BLK = 512; };
+
+// Sum of K values over the BLK threads in a fixed order; every thread gets
+// the same bits.  The wave sums go through sh ((BLK / 64) * K doubles), and
+// each wave then adds them up with one lane per wave (one LDS read per value
+// and lane, so the reduction holds K values per lane, not BLK / 64 * K).
+template <int BLK, int K>
+__device__ __forceinline__ void wg_sum(double (&v)[K], double* sh) {
+  constexpr int NW = BLK / 64;
+#pragma unroll
+  for (int i = 0; i < K; ++i) v[i] = wave_sum(v[i]);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();  // the previous sum's readers are done with sh
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) sh[wid * K + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < K; ++i) v[i] = wave_sum(lane < NW ? sh[lane * K + i] : 0.0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
+  using V = typename cvec<T>::type;
+  constexpr int kWgBlock = WgShape<T>::BLK;
+  constexpr int kWgPts = kWgCap / kWgBlock;
+  extern __shared__ double wg_lds[];
+  __shared__ double sh[(kWgBlock / 64) * 4];
+  const int N = a.g.N;
+  const int s = blockIdx.x;
+  const size_t off = (size_t)s * N;
+  const V* B = reinterpret_cast<const V*>(a.R) + off;  // b = r_0 = r_hat
+  V* Rout = reinterpret_cast<V*>(a.R) + off;
+  V* X = reinterpret_cast<V*>(a.X) + off;
+  const LdsCplx<V> W(wg_lds, N);
+  const V sft = from_d2<V>(a.shift[s]);
+  const int t0 = threadIdx.x;
+  // (x, y) of each owned point, packed (N <= 4096, so both fit 16 bits)
+  int xy[kWgPts];
+#pragma unroll
+  for (int j = 0; j < kWgPts; ++j) {
+    const int n = t0 + j * kWgBlock;
+    xy[j] = (n % a.g.nx) | ((n / a.g.nx) << 16);
+  }
+  // out = (I - c A) in at the owned points, the neighbours read from LDS
+  auto apply = [&](const V (&in)[kWgPts], V (&out)[kWgPts]) {
+    __syncthreads();  // the previous apply's readers are done with the LDS copy
+#pragma unroll
+    for (int j = 0; j < kWgPts; ++j) {
+      const int n = t0 + j * kWgBlock;
+      if (n < N) W.st(n, in[j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kWgPts; ++j) out[j] = vzero<V>();
+#pragma unroll 1
+    for (int q = 0; q < a.taps.n; ++q) {
+      const int dx = a.taps.dx[q], dy = a.taps.dy[q];
+      const T c = (T)a.taps.c[q];
+#pragma unroll
+      for (int j = 0; j < kWgPts; ++j) {
+        const int n = t0 + j * kWgBlock;
+        if (n < N) out[j] = vadd(out[j], vscale(W.ld(wrap_index(xy[j] & 0xffff, xy[j] >> 16, dx, dy, a.g)), c));
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kWgPts; ++j) out[j] = vsub(in[j], vmul(sft, out[j]));
+  };
+  auto dot = [](V u, V w, double& re, double& im) {  // conj(u) w
+    re += (double)u.x * w.x + (double)u.y * w.y;
+    im += (double)u.x * w.y - (double)u.y * w.x;
+  };
+  auto rhat = [&](int j) {
+    const int n = t0 + j * kWgBlock;
+    return (n < N) ? B[n] : vzero<V>();
+  };
+  V r[kWgPts], p[kWgPts], v[kWgPts], x[kWgPts];
+#pragma unroll
+  for (int j = 0; j < kWgPts; ++j) {
+    r[j] = rhat(j);
+    p[j] = r[j];
+    x[j] = vzero<V>();
+  }
+  // k = 0: r_hat = r_0 = b, p_0 = b, rho_0 = ||b||^2
+  apply(p, v);
+  double w4[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < kWgPts; ++j) {
+    dot(r[j], v[j], w4[0], w4[1]);
+    w4[2] += (double)r[j].x * r[j].x + (double)r[j].y * r[j].y;
+  }
+  wg_sum<kWgBlock, 4>(w4, sh);
+  const double bb = w4[2];
+  double2 rho = mk(bb, 0.0), hv = mk(w4[0], w4[1]);
+  double2 al = mk(1, 0), om = mk(1, 0);
+  double rr = bb;
+  bool brk = false;
+  int k = 0, flag = 1;
+  for (;; ++k) {
+    if (k > 0) {
+      const bool conv = rr <= a.tol2 * bb;
+      if (conv || k >= a.maxit || brk) {
+        flag = conv ? 0 : (brk ? 2 : 1);
+        break;
+      }
+      // rho_k = <r_hat, r_k> is in w4[0..1] from the end of the last iteration
+      const double2 rho_k = mk(w4[0], w4[1]);
+      const double2 beta = cmul(cdiv(rho_k, rho), cdiv(al, om));
+      rho = rho_k;
+      const V bt = from_d2<V>(beta), ov = from_d2<V>(om);
+#pragma unroll
+      for (int j = 0; j < kWgPts; ++j) p[j] = vadd(r[j], vmul(bt, vsub(p[j], vmul(ov, v[j]))));
+      apply(p, v);
+      double w2[2] = {0, 0};
+#pragma unroll
+      for (int j = 0; j < kWgPts; ++j) dot(rhat(j), v[j], w2[0], w2[1]);
+      wg_sum<kWgBlock, 2>(w2, sh);
+      hv = mk(w2[0], w2[1]);
+    }
+    // alpha = rho_k / <r_hat, v>; s = r - alpha v (kept in r); t = (I - cA) s
+    al = mk(0, 0);
+    if (hv.x * hv.x + hv.y * hv.y > 0.0) al = cdiv(rho, hv);
+    else if (rho.x != 0.0 || rho.y != 0.0) brk = true;
+    const V av = from_d2<V>(al);
+#pragma unroll
+    for (int j = 0; j < kWgPts; ++j) r[j] = vsub(r[j], vmul(av, v[j]));
+    V tv[kWgPts];
+    apply(r, tv);
+    double w3[3] = {0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < kWgPts; ++j) {
+      dot(tv[j], r[j], w3[0], w3[1]);
+      w3[2] += (double)tv[j].x * tv[j].x + (double)tv[j].y * tv[j].y;
+    }
+    wg_sum<kWgBlock, 3>(w3, sh);
+    // omega = <t, s> / <t, t>; x += alpha p + omega s; r = s - omega t
+    om = mk(0, 0);
+    if (w3[2] > 0.0) om = mk(w3[0] / w3[2], w3[1] / w3[2]);
+    if (w3[2] > 0.0 && om.x == 0.0 && om.y == 0.0) brk = true;
+    const V ov = from_d2<V>(om);
+    w4[0] = w4[1] = w4[2] = w4[3] = 0.0;
+#pragma unroll
+    for (int j = 0; j < kWgPts; ++j) {
+      const V inc = vadd(vmul(av, p[j]), vmul(ov, r[j]));
+      x[j] = (k == 0) ? inc : vadd(x[j], inc);
+      r[j] = vsub(r[j], vmul(ov, tv[j]));
+      dot(rhat(j), r[j], w4[0], w4[1]);
+      w4[2] += (double)r[j].x * r[j].x + (double)r[j].y * r[j].y;
+    }
+    wg_sum<kWgBlock, 4>(w4, sh);
+    rr = w4[2];
+  }
+#pragma unroll
+  for (int j = 0; j < kWgPts; ++j) {
+    const int n = t0 + j * kWgBlock;
+    if (n < N) {
+      X[n] = x[j];
+      Rout[n] = r[j];
+    }
+  }
+  if (t0 == 0) {
+    SysState* st = a.st + s;
+    st->active = 0;
+    st->iters = k;
+    st->flag = flag;
+    st->breakdown = brk ? 1 : 0;
+    st->rho = rho;
+    st->alpha = al;
+    st->omega = om;
+    st->rr = rr;
+    st->bb = bb;
+  }
+}
+
 __global__ void k_krylov_init(SysState* st, int n, int* list) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     st[i] = fresh_state();
@@ -980,6 +1168,18 @@ hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, int nact
       else hipLaunchKernelGGL(k_bicg3<double>, grid, dim3(kBlock), 0, st, a, k);
       break;
   }
+  return hipGetLastError();
+}
+
+bool bicg_wg_fits(int N) { return N >= 1 && N <= kWgCap; }
+
+hipError_t launch_bicg_wg(bool f32, const KrylovArgs& a, int nsys, hipStream_t st) {
+  if (!bicg_wg_fits(a.g.N) || nsys < 1) return hipErrorInvalidValue;
+  if (f32)
+    hipLaunchKernelGGL(k_bicg_wg<float>, dim3(nsys), dim3(WgShape<float>::BLK), LdsCplx<float2>::bytes(a.g.N), st, a);
+  else
+    hipLaunchKernelGGL(k_bicg_wg<double>, dim3(nsys), dim3(WgShape<double>::BLK), LdsCplx<double2>::bytes(a.g.N), st,
+                       a);
   return hipGetLastError();
 }
 

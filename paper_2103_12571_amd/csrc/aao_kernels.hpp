@@ -182,7 +182,7 @@ enum PartialQ {
 
 enum KernelClass {
   KC_FWD = 0, KC_BWD, KC_COCG_A, KC_COCG_B, KC_BICG_1, KC_BICG_2, KC_BICG_3,
-  KC_FFT_INNER, KC_RESIDUAL, KC_MISC, KC_INIT, KC_GRAD, KC_GMRES
+  KC_FFT_INNER, KC_RESIDUAL, KC_MISC, KC_INIT, KC_GRAD, KC_GMRES, KC_BICG_WG
 };
 
 // Launchers (return hipSuccess or the launch error).
@@ -226,6 +226,10 @@ hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, int nact
 // Fresh state for systems 0 .. num_sys - 1, and list[i] = i when list is given
 // (every system starts active).
 hipError_t launch_krylov_init(const KrylovArgs& a, hipStream_t st, int* list = nullptr);
+// BiCGStab with one workgroup per system (all nsys systems, every iteration in
+// one launch) for systems small enough to sit in one workgroup's registers.
+bool bicg_wg_fits(int N);
+hipError_t launch_bicg_wg(bool f32, const KrylovArgs& a, int nsys, hipStream_t st);
 hipError_t launch_fft_solve(bool f32, const FftArgs& a, int nsys, hipStream_t st);
 hipError_t launch_compact_active(const SysState* st, int n, int* list, int* count_tag, int tag, hipStream_t s);
 hipError_t launch_copy_c128_in(void* dst, bool f32, const double* src, int64_t n, hipStream_t st);

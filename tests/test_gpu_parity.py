@@ -105,6 +105,38 @@ def test_shifted_solve_parity(inner, kind, prec):
     assert np.all(its > 0)
 
 
+@pytest.mark.parametrize("kind,nx,ny", [("advdiff2d", 64, 64), ("advdiff2d", 65, 64),
+                                        ("adv1d_c4", 4096, 1), ("adv1d_c4", 4100, 1)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_shifted_solve_bicgstab_both_paths(kind, nx, ny, prec):
+    """Row a3 with BiCGStab on both sides of the 4096-point limit: smaller
+    systems run every iteration in one workgroup per system (one launch),
+    larger ones in the chunked three-kernel form.  Shifts of |c| up to 10 /
+    (Gershgorin bound of A), against a sparse direct solve."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    need_gpu()
+    say("bicgstab paths", kind, nx, ny, prec)
+    w = wl.Workload("t", kind, nx, ny, 8, 3, 1e-3, nu=1e-2, vel=(1.0, 0.5), inner="bicgstab", precision=prec)
+    p = plan_for(w, inner_tol=1e-13 if prec == "fp64" else 1e-6)
+    A = _oracle_op(w).matrix()
+    rho = abs(A).sum(axis=1).max()
+    S = 6
+    rng = np.random.default_rng(11)
+    shifts = (rng.uniform(0.0, 7.0, S) + 1j * rng.uniform(-7.0, 7.0, S)) / rho
+    b = rng.standard_normal((S, w.N)) + 1j * rng.standard_normal((S, w.N))
+    p.reset_stats()
+    x, its = p.shifted_solve(shifts, torch.as_tensor(b, device="cuda"))
+    x = x.cpu().numpy()
+    st = p.stats()
+    assert ("bicgstab_wg" in st) == (w.N <= 4096), sorted(st)
+    assert ("bicgstab_p_matvec" in st) == (w.N > 4096), sorted(st)
+    for s in range(S):
+        xo = spla.spsolve((sp.identity(w.N) - shifts[s] * A).tocsc(), b[s])
+        assert rel_l2(x[s], xo) < (1e-11 if prec == "fp64" else 5e-5), (s, rel_l2(x[s], xo))
+    assert np.all(its > 0)
+
+
 
 @pytest.mark.parametrize("nx,ny", [(24, 20), (1024, 320)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
