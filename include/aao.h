@@ -74,7 +74,9 @@ enum { AAO_FP64 = 0,   /* every step in FP64 / complex128 */
 
 enum { AAO_INNER_COCG = 0,      /* batched COCG: needs A = A^T (complex-symmetric
                                    shifted systems) */
-       AAO_INNER_BICGSTAB = 1,  /* batched BiCGStab: any A */
+       AAO_INNER_BICGSTAB = 1,  /* batched BiCGStab: any A; systems of at most 4096
+                                   points run every iteration in one launch, one
+                                   workgroup per system */
        AAO_INNER_FFT = 2        /* spatial-FFT direct solve (exact for periodic
                                    constant-coefficient A); any nx, ny: lengths that are
                                    not powers of two use Bluestein's chirp-z transform

@@ -714,8 +714,11 @@ __global__ __launch_bounds__(kBlock) void k_bicg3(KrylovArgs a, int k) {
 // block-wide sums in place of the chunk partial sums.  One launch runs every
 // iteration of every system, one workgroup each; nothing is shared between
 // workgroups, and each loop ends at the iteration cap at the latest.
-// complex128 takes 1024 threads (four points each), complex64 512 (eight):
-// the largest workgroups whose vectors stay in registers without spills.
+// complex128 takes 1024 threads (four points each) and accumulates x in
+// memory (read and written once per iteration by its owner thread): its
+// registers still spill (57 VGPRs), but less than with x in registers (85) or
+// with 512 x 8.  complex64 takes 512 threads (eight points, x in registers,
+// no spills).
 constexpr int kWgCap = 4096;
 template <typename T> struct WgShape { static constexpr int BLK = 1024; };
 template <> struct WgShape<float> { static constexpr int BLK = 512; };
@@ -795,12 +798,13 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
     const int n = t0 + j * kWgBlock;
     return (n < N) ? B[n] : vzero<V>();
   };
-  V r[kWgPts], p[kWgPts], v[kWgPts], x[kWgPts];
+  constexpr bool kXMem = sizeof(T) == sizeof(double);
+  V r[kWgPts], p[kWgPts], v[kWgPts], x[kXMem ? 1 : kWgPts];
 #pragma unroll
   for (int j = 0; j < kWgPts; ++j) {
     r[j] = rhat(j);
     p[j] = r[j];
-    x[j] = vzero<V>();
+    if (!kXMem) x[j] = vzero<V>();
   }
   // k = 0: r_hat = r_0 = b, p_0 = b, rho_0 = ||b||^2
   apply(p, v);
@@ -863,7 +867,12 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
 #pragma unroll
     for (int j = 0; j < kWgPts; ++j) {
       const V inc = vadd(vmul(av, p[j]), vmul(ov, r[j]));
-      x[j] = (k == 0) ? inc : vadd(x[j], inc);
+      if (kXMem) {
+        const int n = t0 + j * kWgBlock;
+        if (n < N) X[n] = (k == 0) ? inc : vadd(X[n], inc);
+      } else {
+        x[j] = (k == 0) ? inc : vadd(x[j], inc);
+      }
       r[j] = vsub(r[j], vmul(ov, tv[j]));
       dot(rhat(j), r[j], w4[0], w4[1]);
       w4[2] += (double)r[j].x * r[j].x + (double)r[j].y * r[j].y;
@@ -875,7 +884,7 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
   for (int j = 0; j < kWgPts; ++j) {
     const int n = t0 + j * kWgBlock;
     if (n < N) {
-      X[n] = x[j];
+      if (!kXMem) X[n] = x[j];
       Rout[n] = r[j];
     }
   }
