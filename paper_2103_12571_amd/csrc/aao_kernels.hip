@@ -714,11 +714,12 @@ __global__ __launch_bounds__(kBlock) void k_bicg3(KrylovArgs a, int k) {
 // block-wide sums in place of the chunk partial sums.  One launch runs every
 // iteration of every system, one workgroup each; nothing is shared between
 // workgroups, and each loop ends at the iteration cap at the latest.
-// complex128 takes 1024 threads (four points each) and accumulates x in
-// memory (read and written once per iteration by its owner thread): its
-// registers still spill (57 VGPRs), but less than with x in registers (85) or
-// with 512 x 8.  complex64 takes 512 threads (eight points, x in registers,
-// no spills).
+// complex128 takes 1024 threads (four points each), accumulates x in memory
+// (read and written once per iteration by its owner thread) and keeps v in a
+// second LDS array (each thread touches only its own points there): its
+// registers still spill (31 VGPRs; 85 with x and v in registers, more with
+// 512 x 8).  complex64 takes 512 threads (eight points, x and v in
+// registers, no spills).
 constexpr int kWgCap = 4096;
 template <typename T> struct WgShape { static constexpr int BLK = 1024; };
 template <> struct WgShape<float> { static constexpr int BLK = 512; };
@@ -799,7 +800,27 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
     return (n < N) ? B[n] : vzero<V>();
   };
   constexpr bool kXMem = sizeof(T) == sizeof(double);
-  V r[kWgPts], p[kWgPts], v[kWgPts], x[kXMem ? 1 : kWgPts];
+  V r[kWgPts], p[kWgPts], v[kXMem ? 1 : kWgPts], x[kXMem ? 1 : kWgPts];
+  const LdsCplx<V> Vl(reinterpret_cast<char*>(wg_lds) + LdsCplx<V>::bytes(N), N);  // v (complex128)
+  auto vget = [&](int j) -> V {
+    if constexpr (kXMem) {
+      const int n = t0 + j * kWgBlock;
+      return (n < N) ? Vl.ld(n) : vzero<V>();
+    } else {
+      return v[j];
+    }
+  };
+  auto vput = [&](const V (&o)[kWgPts]) {
+#pragma unroll
+    for (int j = 0; j < kWgPts; ++j) {
+      if constexpr (kXMem) {
+        const int n = t0 + j * kWgBlock;
+        if (n < N) Vl.st(n, o[j]);
+      } else {
+        v[j] = o[j];
+      }
+    }
+  };
 #pragma unroll
   for (int j = 0; j < kWgPts; ++j) {
     r[j] = rhat(j);
@@ -807,11 +828,15 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
     if (!kXMem) x[j] = vzero<V>();
   }
   // k = 0: r_hat = r_0 = b, p_0 = b, rho_0 = ||b||^2
-  apply(p, v);
+  {
+    V vt[kWgPts];
+    apply(p, vt);
+    vput(vt);
+  }
   double w4[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int j = 0; j < kWgPts; ++j) {
-    dot(r[j], v[j], w4[0], w4[1]);
+    dot(r[j], vget(j), w4[0], w4[1]);
     w4[2] += (double)r[j].x * r[j].x + (double)r[j].y * r[j].y;
   }
   wg_sum<kWgBlock, 4>(w4, sh);
@@ -834,11 +859,15 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
       rho = rho_k;
       const V bt = from_d2<V>(beta), ov = from_d2<V>(om);
 #pragma unroll
-      for (int j = 0; j < kWgPts; ++j) p[j] = vadd(r[j], vmul(bt, vsub(p[j], vmul(ov, v[j]))));
-      apply(p, v);
+      for (int j = 0; j < kWgPts; ++j) p[j] = vadd(r[j], vmul(bt, vsub(p[j], vmul(ov, vget(j)))));
+      {
+        V vt[kWgPts];
+        apply(p, vt);
+        vput(vt);
+      }
       double w2[2] = {0, 0};
 #pragma unroll
-      for (int j = 0; j < kWgPts; ++j) dot(rhat(j), v[j], w2[0], w2[1]);
+      for (int j = 0; j < kWgPts; ++j) dot(rhat(j), vget(j), w2[0], w2[1]);
       wg_sum<kWgBlock, 2>(w2, sh);
       hv = mk(w2[0], w2[1]);
     }
@@ -848,7 +877,7 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
     else if (rho.x != 0.0 || rho.y != 0.0) brk = true;
     const V av = from_d2<V>(al);
 #pragma unroll
-    for (int j = 0; j < kWgPts; ++j) r[j] = vsub(r[j], vmul(av, v[j]));
+    for (int j = 0; j < kWgPts; ++j) r[j] = vsub(r[j], vmul(av, vget(j)));
     V tv[kWgPts];
     apply(r, tv);
     double w3[3] = {0, 0, 0};
@@ -1187,8 +1216,8 @@ hipError_t launch_bicg_wg(bool f32, const KrylovArgs& a, int nsys, hipStream_t s
   if (f32)
     hipLaunchKernelGGL(k_bicg_wg<float>, dim3(nsys), dim3(WgShape<float>::BLK), LdsCplx<float2>::bytes(a.g.N), st, a);
   else
-    hipLaunchKernelGGL(k_bicg_wg<double>, dim3(nsys), dim3(WgShape<double>::BLK), LdsCplx<double2>::bytes(a.g.N), st,
-                       a);
+    hipLaunchKernelGGL(k_bicg_wg<double>, dim3(nsys), dim3(WgShape<double>::BLK), 2 * LdsCplx<double2>::bytes(a.g.N),
+                       st, a);  // the stencil's input and v
   return hipGetLastError();
 }
 
