@@ -728,13 +728,15 @@ template <> struct WgShape<float> { static constexpr int BLK = 512; };
 // the same bits.  The wave sums go through sh ((BLK / 64) * K doubles), and
 // each wave then adds them up with one lane per wave (one LDS read per value
 // and lane, so the reduction holds K values per lane, not BLK / 64 * K).
+// Consecutive sums must use different sh buffers: the one barrier between
+// the writes and the reads of a sum keeps every wave from writing sum i + 1
+// before all have read sum i - 1, not sum i.
 template <int BLK, int K>
 __device__ __forceinline__ void wg_sum(double (&v)[K], double* sh) {
   constexpr int NW = BLK / 64;
 #pragma unroll
   for (int i = 0; i < K; ++i) v[i] = wave_sum(v[i]);
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();  // the previous sum's readers are done with sh
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < K; ++i) sh[wid * K + i] = v[i];
@@ -750,7 +752,12 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
   constexpr int kWgBlock = WgShape<T>::BLK;
   constexpr int kWgPts = kWgCap / kWgBlock;
   extern __shared__ double wg_lds[];
-  __shared__ double sh[(kWgBlock / 64) * 4];
+  __shared__ double sh2[2][(kWgBlock / 64) * 4];  // two buffers, used in turn by the block sums
+  int sb = 0;
+  auto sh = [&]() {
+    sb ^= 1;
+    return sh2[sb];
+  };
   const int N = a.g.N;
   const int s = blockIdx.x;
   const size_t off = (size_t)s * N;
@@ -767,9 +774,10 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
     const int n = t0 + j * kWgBlock;
     xy[j] = (n % a.g.nx) | ((n / a.g.nx) << 16);
   }
-  // out = (I - c A) in at the owned points, the neighbours read from LDS
+  // out = (I - c A) in at the owned points, the neighbours read from LDS.
+  // Between two applies there is always a block sum, whose barrier follows
+  // every wave's reads of the previous copy, so the copy is written at once.
   auto apply = [&](const V (&in)[kWgPts], V (&out)[kWgPts]) {
-    __syncthreads();  // the previous apply's readers are done with the LDS copy
 #pragma unroll
     for (int j = 0; j < kWgPts; ++j) {
       const int n = t0 + j * kWgBlock;
@@ -839,7 +847,7 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
     dot(r[j], vget(j), w4[0], w4[1]);
     w4[2] += (double)r[j].x * r[j].x + (double)r[j].y * r[j].y;
   }
-  wg_sum<kWgBlock, 4>(w4, sh);
+  wg_sum<kWgBlock, 4>(w4, sh());
   const double bb = w4[2];
   double2 rho = mk(bb, 0.0), hv = mk(w4[0], w4[1]);
   double2 al = mk(1, 0), om = mk(1, 0);
@@ -868,7 +876,7 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
       double w2[2] = {0, 0};
 #pragma unroll
       for (int j = 0; j < kWgPts; ++j) dot(rhat(j), vget(j), w2[0], w2[1]);
-      wg_sum<kWgBlock, 2>(w2, sh);
+      wg_sum<kWgBlock, 2>(w2, sh());
       hv = mk(w2[0], w2[1]);
     }
     // alpha = rho_k / <r_hat, v>; s = r - alpha v (kept in r); t = (I - cA) s
@@ -886,7 +894,7 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
       dot(tv[j], r[j], w3[0], w3[1]);
       w3[2] += (double)tv[j].x * tv[j].x + (double)tv[j].y * tv[j].y;
     }
-    wg_sum<kWgBlock, 3>(w3, sh);
+    wg_sum<kWgBlock, 3>(w3, sh());
     // omega = <t, s> / <t, t>; x += alpha p + omega s; r = s - omega t
     om = mk(0, 0);
     if (w3[2] > 0.0) om = mk(w3[0] / w3[2], w3[1] / w3[2]);
@@ -906,7 +914,7 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
       dot(rhat(j), r[j], w4[0], w4[1]);
       w4[2] += (double)r[j].x * r[j].x + (double)r[j].y * r[j].y;
     }
-    wg_sum<kWgBlock, 4>(w4, sh);
+    wg_sum<kWgBlock, 4>(w4, sh());
     rr = w4[2];
   }
 #pragma unroll
