@@ -137,6 +137,40 @@ def test_shifted_solve_bicgstab_both_paths(kind, nx, ny, prec):
     assert np.all(its > 0)
 
 
+@pytest.mark.parametrize("nx", [7, 4100])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_shifted_solve_bicgstab_edge_cases(nx, prec):
+    """BiCGStab edge cases on both paths (7 points: one workgroup per system,
+    most of its threads owning no point; 4100: the chunked form).  A zero
+    right-hand side stops at the first test (one iteration) with x = 0
+    exactly; the others match a sparse direct solve; with an unreachable
+    tolerance every system stops at the iteration cap exactly."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    need_gpu()
+    say("bicgstab edge cases", nx, prec)
+    w = wl.Workload("t", "adv1d_c4", nx, 1, 8, 3, 1e-3, nu=1e-2, vel=(1.0, 0.5), inner="bicgstab", precision=prec)
+    A = _oracle_op(w).matrix()
+    rho = abs(A).sum(axis=1).max()
+    assert rho > 0
+    rng = np.random.default_rng(12)
+    shifts = (np.array([0.5 + 1.0j, 2.0 - 1.0j, 1.0 + 0.0j]) / rho)
+    b = rng.standard_normal((3, w.N)) + 1j * rng.standard_normal((3, w.N))
+    b[1] = 0.0
+    p = plan_for(w, inner_tol=1e-13 if prec == "fp64" else 1e-6)
+    x, its = p.shifted_solve(shifts, torch.as_tensor(b, device="cuda"))
+    x = x.cpu().numpy()
+    assert its[1] == 1 and np.all(x[1] == 0), (its, np.abs(x[1]).max())
+    for s in (0, 2):
+        xo = spla.spsolve((sp.identity(w.N) - shifts[s] * A).tocsc(), b[s])
+        assert rel_l2(x[s], xo) < (1e-11 if prec == "fp64" else 5e-5), (s, rel_l2(x[s], xo))
+    b[1] = rng.standard_normal(w.N)
+    pc = plan_for(w, inner_tol=1e-30, inner_maxit=3)
+    xc, itc = pc.shifted_solve(shifts, torch.as_tensor(b, device="cuda"))
+    assert np.all(itc == 3), itc
+    assert np.all(np.isfinite(xc.cpu().numpy()))
+
+
 
 @pytest.mark.parametrize("nx,ny", [(24, 20), (1024, 320)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
