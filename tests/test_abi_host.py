@@ -25,6 +25,19 @@ def test_header_declares_binding_exports():
     assert sorted(bd.EXPORTS) == _declared()
 
 
+def test_kernel_classes_header_binding_and_names_agree():
+    """The stats arrays' length in the header, the binding's copy of it, and
+    aao_kernel_name: one distinct non-empty name per class, "" past the end."""
+    src = open(os.path.join(ROOT, "include", "aao.h")).read()
+    n = int(re.search(r"#define AAO_NUM_KERNELS (\d+)", src).group(1))
+    assert n == bd.AAO_NUM_KERNELS
+    names = [bd.lib().aao_kernel_name(i).decode() for i in range(n)]
+    assert all(names) and len(set(names)) == n, names
+    assert bd.lib().aao_kernel_name(n).decode() == ""
+    assert bd.lib().aao_kernel_name(-1).decode() == ""
+    assert "bicgstab_wg" in names and "cocg_pass" in names
+
+
 def test_library_exports_every_declared_symbol():
     lib = bd.lib()
     for name in _declared():
