@@ -60,7 +60,10 @@ typedef enum {
   AAO_ENODIAG = -3,     /* Q G_l^{-1} not (well) diagonalisable for this alpha
                            (Sec. 2.3: eigenvalues coalesce, Examples 1-2) */
   AAO_ENOCONV = -4,     /* aao_solve / adjoint: max_iter sweeps without meeting tol */
-  AAO_ESTAGNATE = -5,   /* reserved */
+  AAO_ESTAGNATE = -5,   /* aao_solve / adjoint: the monitored quantity stopped
+                           contracting above tol (Sec. 3.3: consecutive iterates
+                           alone can take stagnation for convergence); see
+                           aao_solve */
   AAO_EWORKSPACE = -6,  /* no workspace set, or smaller than aao_workspace_size */
   AAO_ENAN = -7,        /* a norm became NaN or Inf */
   AAO_ESTATE = -8       /* call order violated (e.g. sweep before aao_set_u0) */
@@ -123,6 +126,9 @@ typedef struct {
   double dlast_inf[AAO_MAX_HIST];    /* ||u_L^{k+1} - u_L^k||_inf of sweep k */
   double inner_mean[AAO_MAX_HIST];   /* mean Krylov iterations per system, sweep k */
   int inner_max[AAO_MAX_HIST];       /* max Krylov iterations over systems, sweep k */
+  int inner_fail[AAO_MAX_HIST];      /* shifted systems of sweep k that stopped without
+                                        meeting tau: iteration cap reached or breakdown */
+  int inner_fail_total;              /* sum of inner_fail over all sweeps */
 } aao_solve_info;
 
 /* Per kernel class: launches, elements processed, event-timed milliseconds and
@@ -202,7 +208,15 @@ aao_status aao_sweep(aao_plan_t plan, double* u_dev, double alpha, double* res_r
  * whose round-off is relative to the current residual: alpha = min(1/2,
  * sqrt(L (3 eps + tau))) with eps = 2^-24 (eq. (minimeq) on a relative model).
  * alphas != NULL: sweep k uses alphas[min(k, n_alphas-1)].
- * Returns ENOCONV (info filled) when max_iter is reached. */
+ * Stopping (Sec. 3.3, Alg. 2): converged when the stop rule holds.  Alg. 2's
+ * own loop exit (error model m_k <= tol) counts as converged only if every
+ * shifted system of the last sweep met tau (gamma assumes it); otherwise the
+ * sweeps go on under the stop rule.  The monitored quantity (the last-step
+ * difference, or the relative residual under AAO_STOP_RESIDUAL) must keep
+ * contracting: when three sweeps in a row each leave it above tol and above
+ * 0.9 times its previous value, the call returns AAO_ESTAGNATE.
+ * Returns ENOCONV when max_iter is reached; info is filled in every case
+ * (info->inner_fail counts the shifted systems that missed tau per sweep). */
 aao_status aao_solve(aao_plan_t plan, double* u_dev, const double* alphas, int n_alphas,
                      double m0, double tol, int stop_rule, int max_iter, aao_solve_info* info);
 

@@ -53,14 +53,16 @@ class aao_solve_info(C.Structure):
     _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("gamma", C.c_double), ("m0", C.c_double),
                 ("alpha", C.c_double * AAO_MAX_HIST), ("m", C.c_double * AAO_MAX_HIST),
                 ("res_rel", C.c_double * AAO_MAX_HIST), ("dlast_inf", C.c_double * AAO_MAX_HIST),
-                ("inner_mean", C.c_double * AAO_MAX_HIST), ("inner_max", C.c_int * AAO_MAX_HIST)]
+                ("inner_mean", C.c_double * AAO_MAX_HIST), ("inner_max", C.c_int * AAO_MAX_HIST),
+                ("inner_fail", C.c_int * AAO_MAX_HIST), ("inner_fail_total", C.c_int)]
 
     def as_dict(self):
         k = min(self.iterations, AAO_MAX_HIST)
         return {"iterations": self.iterations, "converged": bool(self.converged), "gamma": self.gamma,
                 "m0": self.m0, "alpha": list(self.alpha[:k]), "m": list(self.m[:k]),
                 "res_rel": list(self.res_rel[:k]), "dlast_inf": list(self.dlast_inf[:k]),
-                "inner_mean": list(self.inner_mean[:k]), "inner_max": list(self.inner_max[:k])}
+                "inner_mean": list(self.inner_mean[:k]), "inner_max": list(self.inner_max[:k]),
+                "inner_fail": list(self.inner_fail[:k]), "inner_fail_total": self.inner_fail_total}
 
 
 class aao_gmres_info(C.Structure):
@@ -288,6 +290,8 @@ class Plan:
         return res.value, dl.value
 
     def solve(self, u=None, alphas=None, m0=0.0, tol=1e-12, stop="laststep", max_iter=50, raise_on_noconv=True):
+        """aao_solve.  AAO_ENOCONV and AAO_ESTAGNATE raise (with the sweep
+        history) unless raise_on_noconv is False; then info["status"] tells."""
         if u is None:
             u = self.torch.empty(self.shape, dtype=self.torch.float64, device=self.device)
         info = aao_solve_info()
@@ -297,11 +301,14 @@ class Plan:
                             0 if al is None else len(al), float(m0), float(tol),
                             {"laststep": AAO_STOP_LASTSTEP, "residual": AAO_STOP_RESIDUAL}[stop],
                             int(max_iter), C.byref(info))
-        if s != AAO_OK and (raise_on_noconv or s != AAO_ENOCONV):
-            if s == AAO_ENOCONV:
+        noconv = s in (AAO_ENOCONV, AAO_ESTAGNATE)
+        if s != AAO_OK and (raise_on_noconv or not noconv):
+            if noconv:
                 raise AAOError(s, "%s; history %s" % (lib().aao_last_error().decode(), info.as_dict()))
             check(s)
-        return u, info.as_dict()
+        out = info.as_dict()
+        out["status"] = STATUS_NAMES.get(s, s)
+        return u, out
 
     def solve_windows(self, n_windows, sources=None, u=None, alphas=None, m0=0.0, tol=1e-12, stop="laststep",
                       max_iter=50):
@@ -359,7 +366,7 @@ class Plan:
         s = lib().aao_adjoint_solve(self._h, _ptr(g), _ptr(lam), _dptr(al) if al is not None else None,
                                     0 if al is None else len(al), float(m0), float(tol), int(max_iter),
                                     C.byref(info))
-        if s == AAO_ENOCONV:
+        if s in (AAO_ENOCONV, AAO_ESTAGNATE):
             raise AAOError(s, "%s; history %s" % (lib().aao_last_error().decode(), info.as_dict()))
         check(s)
         return lam, info.as_dict()

@@ -2,12 +2,14 @@
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libaao.so")
-SOURCES = ["csrc/aao_kernels.hip", "csrc/aao_cocg.hip", "csrc/aao_fftsolve.hip", "csrc/aao_gmres.hip", "csrc/aao_api.cpp",
-           "csrc/aao_host.cpp"]
+OBJ = os.path.join(ROOT, "_build")
+SOURCES = ["csrc/aao_kernels.hip", "csrc/aao_cocg.hip", "csrc/aao_fftsolve.hip", "csrc/aao_gmres.hip",
+           "csrc/aao_api.cpp", "csrc/aao_host.cpp"]
 
 
 def hipcc():
@@ -17,22 +19,35 @@ def hipcc():
     return "hipcc"
 
 
-def build(verbose=False):
-    """Compile every source into paper_2103_12571_amd/libaao.so (always rebuilds)."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-           # packed FP32 instructions are kept out of every code object
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-command-line-argument",
-           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
-    cmd += [os.path.join(HERE, s) for s in SOURCES]
-    cmd += ["-o", tmp]
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+         # packed FP32 instructions are kept out of every code object
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wno-unused-command-line-argument"]
+
+
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, cwd=HERE, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libaao.so")
+        raise RuntimeError("hipcc failed: " + " ".join(cmd[-3:]))
+
+
+def build(verbose=False, jobs=None):
+    """Compile every source (in parallel, one object each) and link
+    paper_2103_12571_amd/libaao.so (always rebuilds)."""
+    os.makedirs(OBJ, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    srcs = SOURCES
+    objs = [os.path.join(OBJ, os.path.basename(s) + ".o") for s in srcs]
+    cmds = [[hipcc()] + FLAGS + inc + ["-c", os.path.join(HERE, s), "-o", o] for s, o in zip(srcs, objs)]
+    jobs = jobs or min(len(cmds), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
+    tmp = LIB + ".tmp"
+    _run([hipcc()] + FLAGS + ["-shared"] + objs + ["-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -1329,8 +1329,9 @@ static aao_status run_solve_sweeps(aao_plan_t p, double* u, const double* alphas
   info->m0 = m;
   // alpha of sweep k and the error model after it (mm updated); the sequence
   // depends on gamma and m0 only, so the next sweep's alpha is known while
-  // the current one runs.  done: Alg. 2's loop condition ended the iteration.
-  auto alpha_at = [&](int k, double& mm, bool& done) {
+  // the current one runs.  done: Alg. 2's loop condition ended the iteration
+  // (only when allow_exit).
+  auto alpha_at = [&](int k, double& mm, bool allow_exit, bool& done) {
     done = false;
     if (alphas) return alphas[std::min(k, n_alphas - 1)];
     if (p->f32) {
@@ -1343,7 +1344,7 @@ static aao_status run_solve_sweeps(aao_plan_t p, double* u, const double* alphas
       mm = mm * (a + gr / a);
       return a;
     }
-    if (mm <= tol) {  // Alg. 2 loop condition: the error model is below tol
+    if (allow_exit && mm <= tol) {  // Alg. 2 loop condition: the error model is below tol
       done = true;
       return 0.0;
     }
@@ -1351,16 +1352,25 @@ static aao_status run_solve_sweeps(aao_plan_t p, double* u, const double* alphas
     mm = 2 * std::sqrt(mm * gamma);
     return a;
   };
+  // Sec. 3.3: the error model m_k overestimates the error and the difference
+  // of consecutive iterates alone can take stagnation for convergence.  The
+  // model's exit rests on gamma, which assumes every shifted system met tau,
+  // so it is honoured only after a sweep without inner failures; and the
+  // monitored quantity must keep contracting, else ESTAGNATE.
+  constexpr int kStallSweeps = 3;
+  constexpr double kStallRatio = 0.9;
+  int last_fail = 0, stall = 0;
+  double prev_mon = 0.0;
   for (int k = 0; k < max_iter; ++k) {
     bool done;
-    double alpha = alpha_at(k, m, done);
+    double alpha = alpha_at(k, m, last_fail == 0, done);
     if (done) {
       info->converged = 1;
       return AAO_OK;
     }
     double m_next = m, next_alpha = 0.0;
     if (k + 1 < max_iter) {
-      next_alpha = alpha_at(k + 1, m_next, done);
+      next_alpha = alpha_at(k + 1, m_next, true, done);
       if (done) next_alpha = 0.0;
     }
     SweepOut o;
@@ -1373,24 +1383,40 @@ static aao_status run_solve_sweeps(aao_plan_t p, double* u, const double* alphas
     }
     if (s != AAO_OK) return s;
     const double wn = std::sqrt(adj ? 1.0 : p->w2);
+    const double res_rel = std::sqrt(o.res2) / wn;
     if (k < AAO_MAX_HIST) {
       info->alpha[k] = alpha;
       info->m[k] = m;
-      info->res_rel[k] = std::sqrt(o.res2) / wn;
+      info->res_rel[k] = res_rel;
       info->dlast_inf[k] = stopped ? 0.0 : o.dmax;
-      info->inner_mean[k] = o.inner_mean;
-      info->inner_max[k] = o.inner_max;
+      info->inner_mean[k] = stopped ? 0.0 : o.inner_mean;
+      info->inner_max[k] = stopped ? 0 : o.inner_max;
+      info->inner_fail[k] = stopped ? 0 : o.inner_fail;
     }
     if (stopped) {
       info->iterations = k;
       info->converged = 1;
       return AAO_OK;
     }
+    info->inner_fail_total += o.inner_fail;
+    last_fail = o.inner_fail;
     info->iterations = k + 1;
     if (stop_rule == AAO_STOP_LASTSTEP && o.dmax <= tol) {
       info->converged = 1;
       return AAO_OK;
     }
+    // the residual rule monitors the residual before the sweep, the last-step
+    // rule the difference the sweep made
+    const double mon = stop_rule == AAO_STOP_RESIDUAL ? res_rel : o.dmax;
+    if (k > 0 && mon > tol && mon >= kStallRatio * prev_mon) {
+      if (++stall >= kStallSweeps)
+        return fail(AAO_ESTAGNATE, "stagnation: " + std::to_string(kStallSweeps) +
+                                       " sweeps in a row without contraction above tol (last " +
+                                       std::to_string(mon) + ")");
+    } else {
+      stall = 0;
+    }
+    prev_mon = mon;
   }
   return fail(AAO_ENOCONV, "no convergence within max_iter sweeps");
 }
@@ -1726,6 +1752,7 @@ aao_status aao_adjoint_solve(aao_plan_t p, const double* g_last, double* lam, co
   aao_status s = need_ready(p, false);
   if (s != AAO_OK) return s;
   if (!g_last || !lam) return fail(AAO_EINVAL, "null array");
+  if (!info) return fail(AAO_EINVAL, "null info");
   close_run(p);
   HIPCHK(aao::launch_norms_bn(g_last, p->B, p->N, p->npart(), kNormBlocks, p->stream));
   std::vector<double> h(2 * kNormBlocks);

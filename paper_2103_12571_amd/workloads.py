@@ -57,7 +57,7 @@ WORKLOADS = {
                           alpha=1e-3, stop="residual", tol=1e-12),
     # 2D heat nu=1e-2 on 256^2, L=64, dt=1e-3, 16 seeded Fourier modes, adaptive alpha, COCG.
     "heat2d_256": Workload("heat2d_256", "heat2d", 256, 256, 64, 3, 1e-3, nu=1e-2, init="modes",
-                           tol=1e-11, inner="cocg"),
+                           tol=1e-12, inner="cocg"),
     # 1D advection c=1, N=4096, 4th-order central, L=128, dt=1e-3, Gaussian + noise.
     "adv1d_4096": Workload("adv1d_4096", "adv1d_c4", 4096, 1, 128, 3, 1e-3, vel=(1.0, 0.0),
                            init="gauss", tol=1e-11, inner="bicgstab"),
@@ -80,6 +80,56 @@ WORKLOADS = {
                                   vel=(1.0, 0.5), batch=8, init="modes", tol=1e-10,
                                   inner="bicgstab", precision="mixed", inner_tol=1e-6),
 }
+
+
+# Sec. 5.1, Table 1: per problem and tolerance to reach, the points per
+# dimension N, the order of the differences, the nodes M, the steps L and the
+# sequential solver's tolerance tau.  Heat on [pi, pi + 0.1] (t0 = pi),
+# advection on [0, 1e-2].
+TABLE1 = {
+    ("heat", 1e-5): dict(N=450, order=2, M=1, L=32, tau=1e-6),
+    ("heat", 1e-9): dict(N=400, order=4, M=2, L=32, tau=1e-10),
+    ("heat", 1e-12): dict(N=300, order=6, M=3, L=16, tau=1e-13),
+    ("adv", 1e-5): dict(N=350, order=2, M=2, L=8, tau=1e-8),
+    ("adv", 1e-9): dict(N=350, order=4, M=2, L=16, tau=1e-11),
+    ("adv", 1e-12): dict(N=600, order=5, M=3, L=32, tau=1e-14),
+}
+TABLE1_T = {"heat": 0.1, "adv": 1e-2}
+
+# Sec. 5.2, Table 2: the parameter sets of the moving window over 64 steps of
+# dT = T64 / 64: N, order, M, T64, the sequential solver's tolerance tau and
+# the inner tolerance of the parallel method (the table's tilde-tau).
+TABLE2 = {
+    ("heat", 1e-5): dict(N=350, order=2, M=1, T64=0.32, tau=1e-6, tau_par=1e-6),
+    ("heat", 1e-9): dict(N=400, order=4, M=2, T64=0.16, tau=1e-10, tau_par=1e-10),
+    ("heat", 1e-12): dict(N=350, order=6, M=3, T64=0.16, tau=1e-14, tau_par=1e-13),
+    ("adv", 1e-5): dict(N=800, order=1, M=1, T64=0.00016, tau=1e-6, tau_par=1e-9),
+    ("adv", 1e-9): dict(N=800, order=3, M=2, T64=0.00064, tau=1e-11, tau_par=1e-13),
+    ("adv", 1e-12): dict(N=700, order=5, M=3, T64=0.0128, tau=1e-14, tau_par=1e-15),
+}
+
+
+def _problem_base(problem):
+    return WORKLOADS["heat2d_table1"] if problem == "heat" else WORKLOADS["adv2d_table1"]
+
+
+def table1_workload(problem, tol, **kw):
+    """The Sec. 5 problem at Table 1's parameters for tolerance tol (keyword
+    overrides, e.g. inner solver and tolerances, go to the Workload)."""
+    p = TABLE1[(problem, tol)]
+    w = _problem_base(problem).with_(name="%s_table1_%g" % (problem, tol), nx=p["N"], ny=p["N"], order=p["order"],
+                                     M=p["M"], L=p["L"], dt=TABLE1_T[problem] / p["L"])
+    return w.with_(**kw)
+
+
+def table2_workload(problem, tol, L=16, **kw):
+    """The Sec. 5 problem at Table 2's parameters for tolerance tol, as one
+    window of L steps of dT = T64 / 64 (64 / L windows cover T64); the inner
+    tolerance is the table's tilde-tau unless overridden."""
+    p = TABLE2[(problem, tol)]
+    w = _problem_base(problem).with_(name="%s_table2_%g" % (problem, tol), nx=p["N"], ny=p["N"], order=p["order"],
+                                     M=p["M"], L=L, dt=p["T64"] / 64, inner_tol=p["tau_par"])
+    return w.with_(**kw)
 
 
 def grid(w):

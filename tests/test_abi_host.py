@@ -44,6 +44,38 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def _c_layout(structs):
+    """sizeof and offsetof of the named structs' fields, as the C compiler lays
+    them out from include/aao.h (gcc, host ABI)."""
+    import subprocess
+    import tempfile
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "aao.h"', "int main(void) {"]
+    for name, cls in structs:
+        lines.append('printf("%s sizeof %%zu\\n", sizeof(%s));' % (name, name))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (name, f, name, f))
+    lines.append("return 0; }")
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "lay.c"), os.path.join(d, "lay")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    return {tuple(l.split()[:2]): int(l.split()[2]) for l in out.splitlines()}
+
+
+def test_binding_struct_layouts_match_header():
+    """Every struct the binding passes through the ABI has the C layout: same
+    size and the same offset for every field."""
+    structs = [("aao_stencil", bd.aao_stencil), ("aao_config", bd.aao_config),
+               ("aao_solve_info", bd.aao_solve_info), ("aao_gmres_info", bd.aao_gmres_info),
+               ("aao_kernel_stats", bd.aao_kernel_stats)]
+    lay = _c_layout(structs)
+    for name, cls in structs:
+        assert lay[(name, "sizeof")] == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert lay[(name, f)] == getattr(cls, f).offset, (name, f)
+
+
 def _setup(kind="heat1d", nx=16, ny=1, M=3, L=8, dt=0.01, inner=bd.AAO_INNER_COCG, batch=1, nodes=None,
            nu=0.1, vel=(1.0, 0.5), ntaps=None, prec=bd.AAO_FP64):
     dx, dy, c, d = taps_for(kind, nx, ny, nu=nu, vel=vel)

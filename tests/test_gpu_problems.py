@@ -1,7 +1,8 @@
 """The two test problems of Sec. 5 on the GPU: the heat equation with its
 source (eq. (heat), the source entering w through aao_set_forcing) and the
 advection equation with upwind differences (eq. (advection)), against the
-oracle and against the exact solutions at Table 1's parameters."""
+oracle; the moving window of Sec. 5.2 against sequential collocation.  Every
+parameter set of Tables 1 and 2 runs in test_gpu_tables.py."""
 import numpy as np
 import pytest
 
@@ -95,28 +96,6 @@ def test_upwind_advection_parity(name, w):
     assert e < 1e-10
 
 
-@pytest.mark.parametrize("w,tol", [(HEAT, 1e-9), (ADV, 1e-9),
-                                   (HEAT.with_(inner="fft", inner_tol=1e-15), 1e-9),
-                                   (ADV.with_(inner="fft", inner_tol=1e-15), 1e-9)],
-                         ids=["heat_cocg", "adv_bicgstab", "heat_fft", "adv_fft"])
-def test_table1_middle_column_reaches_tolerance(w, tol):
-    """Table 1 (tolerance 1e-9): the GPU solution at T is within 1e-9 of the
-    exact solution and matches the sequential oracle."""
-    need_gpu()
-    say("table 1", w.name)
-    u, info, u0, _ = _solve(w)
-    T = w.t0 + w.L * w.dt
-    err = np.max(np.abs(u[0, -1, -1] - wl.exact_solution(w, T)))
-    op, Q, tau = _oracle(w, u0, None)
-    b = _oracle_source(w, tau)[0] if w.source else None
-    ref = oracle.sequential_solve(op, Q, w.dt, u0[0], w.L, backend="spectral", forcing=b)
-    e = rel_l2(u[0], ref)
-    say("  sweeps", info["iterations"], "alphas", ["%.2e" % a for a in info["alpha"]],
-        "exact err %.2e" % err, "oracle err %.2e" % e)
-    assert err < tol
-    assert e < 1e-10
-
-
 def test_moving_window_equals_sequential():
     """Four windows of L = 4 steps reproduce steps 13-16 of the sequential
     collocation solution over 16 steps (Sec. 5.2's moving window)."""
@@ -133,23 +112,3 @@ def test_moving_window_equals_sequential():
     # the plan's own u0 is restored: a plain solve starts from it again
     u1, _ = p.solve(tol=w.tol, max_iter=40)
     assert rel_l2(host(u1)[0], ref[:w.L]) < 1e-10
-
-
-def test_moving_window_table2_heat():
-    """Table 2, heat, tolerance 1e-9: 400^2 points, 4th order, M = 2,
-    T_64 = 0.16 over 64 steps, solved as 4 windows of L = 16 with the source
-    of each window; the result at T is within 1e-9 of the exact solution."""
-    need_gpu()
-    W, L = 4, 16
-    w = HEAT.with_(L=L, dt=0.16 / 64, inner_tol=1e-12, tol=1e-11)
-    p = plan_for(w)
-    u0 = wl.initial_batch(w)
-    p.set_u0(dev(u0))
-    tau = np.asarray(p.collocation()[0])
-    src = np.stack([wl.source_values(w, w.t0 + (k * L + np.arange(L)[:, None] + tau[None, :]) * w.dt)
-                    for k in range(W)])
-    u, infos = p.solve_windows(W, sources=dev(src), tol=w.tol, max_iter=40)
-    T = w.t0 + W * L * w.dt
-    err = np.max(np.abs(host(u)[0, -1, -1] - wl.exact_solution(w, T)))
-    say("table 2 heat windows", [i["iterations"] for i in infos], "exact err %.2e" % err)
-    assert err < 1e-9
