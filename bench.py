@@ -22,6 +22,109 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
+# Algorithmic bytes per unit of work of each kernel class as the textbook
+# (unfused) form of each step counts them: per complex element and inner
+# iteration for the Krylov kernels, per real space-time DOF for the
+# transforms; cs = bytes of one complex element of the inner solves (16 or 8),
+# half-spectrum factor h = (L/2 + 1)/L on the complex terms.  The roofline's
+# `achieved` uses the bytes each kernel's own algorithm must move (the
+# library's statistics: e.g. 4 cs / 6 cs per element and pass for the fused
+# COCG pass, which never writes s or A r); `achieved_unfused_bytes` divides
+# these larger counts by the same time, a measure of the fusion, not of
+# bandwidth (it can exceed the peak).
+#   fwd_residual_dft_l: residual (read u 8, write r 8) + transform (read r 8,
+#                       write cs h)
+#   bwd_idft_l_update:  read cs h, read and write u 16
+#   cocg_pass:          10 cs per element and iteration (x, r, p, s, w traffic
+#                       of the two-kernel form); cocg_init 3 cs
+#   bicgstab_wg:        250 / 16 cs per element and iteration
+#   fft_inner:          6 cs per element in 2D (rows, columns, rows), 2 cs in 1D
+
+
+def survey_bytes(name, s, w, cs):
+    h = (w.L // 2 + 1) / w.L
+    per = {"fwd_residual_dft_l": 24.0 + cs * h, "bwd_idft_l_update": 16.0 + cs * h,
+           "cocg_pass": 10.0 * cs, "cocg_init": 3.0 * cs, "bicgstab_wg": 250.0 / 16.0 * cs}.get(name)
+    return s["bytes"] if per is None else per * s["elements"]
+
+
+def roofline_of(stats, w, cs):
+    """The dominant kernel class of a timed run against the 8 TB/s HBM peak:
+    achieved = the kernel's algorithmic bytes / its summed launch time (HIP
+    events on the plan's stream); also the unfused byte count over the same
+    time, and the counter traffic when a record for these sources exists."""
+    if not stats:
+        return None
+    name, s = max(stats.items(), key=lambda kv: kv[1]["ms"])
+    if s["ms"] <= 0:
+        return None
+    sec = s["ms"] * 1e-3
+    unf = survey_bytes(name, s, w, cs)
+    ach = s["bytes"] / sec / 1e9
+    out = {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(name, w.name),
+           "launches": s["launches"], "avg_launch_us": round(1e3 * s["ms"] / s["launches"], 2),
+           "bytes_per_launch": s["bytes"] / s["launches"],
+           "achieved_unfused_bytes": round(unf / sec / 1e9, 1), "unfused_bytes_per_launch": unf / s["launches"],
+           "share_of_kernel_time": round(s["ms"] / sum(v["ms"] for v in stats.values()), 3)}
+    tr = out["traffic"]
+    if tr:
+        out["achieved_traffic"] = round(tr * s["launches"] / sec / 1e9, 1)
+        out["frac_traffic"] = round(out["achieved_traffic"] / HBM_PEAK_GBS, 4)
+    return out
+
+
+def host_info():
+    """CPU model and the cores this process may use."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count() or 1, "usable_cores": usable}
+
+
+_BARRIER = None
+
+
+def _pool_init(barrier):
+    global _BARRIER
+    _BARRIER = barrier
+
+
+def _oracle_job(name):
+    """One oracle solve of workload `name` in a worker process (one thread);
+    returns its wall-clock start and end after all workers met at a barrier."""
+    from paper_2103_12571_amd import workloads as wl
+    w = wl.WORKLOADS[name]
+    u0 = wl.initial_batch(w)
+    _BARRIER.wait()
+    t0 = time.time()
+    oracle_solution(w, u0)
+    return t0, time.time()
+
+
+def oracle_all_cores(name, procs):
+    """The oracle as it stands (one thread per process: numpy's FFTs and
+    batched 3 x 3 solves do not thread) run as `procs` concurrent independent
+    solves of the same workload, one per core; returns the span from the first
+    start to the last end.  Spawned workers, started before this process
+    touches the GPU."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    bar = ctx.Barrier(procs)
+    with ctx.Pool(procs, initializer=_pool_init, initargs=(bar,)) as pool:
+        spans = pool.map(_oracle_job, [name] * procs, chunksize=1)
+    return max(b for _, b in spans) - min(a for a, _ in spans)
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -35,6 +138,7 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain device copy (counter scale)")
     ap.add_argument("--no-gmres", action="store_true", help="skip the outer-GMRES comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (row a7) timing")
+    ap.add_argument("--no-small", action="store_true", help="skip the 1D configurations (heat1d_64, adv1d_4096)")
     ap.add_argument("--all-configs", action="store_true",
                     help="also time every workload once against the oracle (adds about a minute)")
     return ap.parse_args()
@@ -63,6 +167,22 @@ def traffic_for(kernel, workload):
         if r.get("kernel") == kernel and r.get("workload") == workload and r.get("source_sha") == source_hash():
             return r.get("bytes_per_launch")
     return None
+
+
+def cpu_legs(w, u0):
+    """The oracle on the host before the GPU is touched: one thread (median of
+    three whole solves) and all usable cores (one concurrent solve per core,
+    at most 16)."""
+    ts = []
+    ref = None
+    for _ in range(3):
+        t0 = time.perf_counter()
+        ref = oracle_solution(w, u0)
+        ts.append(time.perf_counter() - t0)
+    host = host_info()
+    procs = max(1, min(16, host["usable_cores"]))
+    span = oracle_all_cores(w.name, procs)
+    return {"t1": sorted(ts)[1], "procs": procs, "span": span, "host": host, "ref": ref}
 
 
 def run_solves(plan, u, w, n, timing):
@@ -130,10 +250,13 @@ def speedup_block(np, torch, wl, plan_for, with_oracle):
             print("bench: %s %s path on %s" % (inner, name, w.name), file=sys.stderr, flush=True)
             run_solves(plan, u, w, 1, False)  # warm-up
             el, sw, infos, _ = run_solves(plan, u, w, 2, False)
+            _, _, _, st = run_solves(plan, u, w, 1, True)  # kernel timing in a run of its own
             r = {"time_to_solution_s": el / 2, "sweeps": sw / 2, "inner_tol": w.inner_tol,
                  "dof_sweeps_per_s": w.dof * sw / el,
                  "alphas": [float("%.3e" % a) for a in infos[-1]["alpha"]],
-                 "inner_iters_mean": [round(v, 1) for v in infos[-1]["inner_mean"]]}
+                 "inner_iters_mean": [round(v, 1) for v in infos[-1]["inner_mean"]],
+                 "inner_iters_max": infos[-1]["inner_max"],
+                 "roofline": roofline_of(st, w, 16 if name == "fp64" else 8)}
             if ref is not None:
                 r["rel_l2_vs_oracle"] = float(np.linalg.norm(u.cpu().numpy() - ref) / np.linalg.norm(ref))
             out[name] = r
@@ -217,6 +340,12 @@ def adjoint_block(np, torch, wl, plan_for, with_oracle):
 
         print("bench: adjoint on %s (%s inner)" % (wk.name, wk.inner), file=sys.stderr, flush=True)
         once()  # warm-up
+        plan.reset_stats()  # kernel timing in a run of its own
+        plan.set_timing(True)
+        once()
+        torch.cuda.synchronize()
+        plan.set_timing(False)
+        st = plan.stats()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         n = 2
@@ -227,7 +356,8 @@ def adjoint_block(np, torch, wl, plan_for, with_oracle):
         sw = info["iterations"] + ainfo["iterations"]
         res = {"workload": wk.name, "dof": wk.dof, "batch": wk.batch, "precision": wk.precision, "inner": wk.inner,
                "time_to_gradient_s": el, "forward_sweeps": info["iterations"], "adjoint_sweeps": ainfo["iterations"],
-               "dof_sweeps_per_s": wk.dof * sw / el}
+               "dof_sweeps_per_s": wk.dof * sw / el,
+               "roofline": roofline_of(st, wk, 16 if wk.precision == "fp64" else 8)}
         out = (u[0].cpu().numpy(), lam[0].cpu().numpy(), gu0[0].cpu().numpy(), float(gnu[0]))
         del plan
         torch.cuda.empty_cache()
@@ -250,6 +380,50 @@ def adjoint_block(np, torch, wl, plan_for, with_oracle):
                                                 "dJ_dnu": abs(gv - gn) / abs(gn)}
     res["fft_inner"] = res_fft
     return res
+
+
+def small_configs_block(np, torch, wl, plan_for, with_oracle):
+    """The 1D configurations beside the headline: heat1d_64 (768 DOF, fixed
+    alpha = 1e-3, relative residual 1e-12) is launch-latency bound, so it is
+    reported in microseconds per sweep; adv1d_4096 (1.6 M DOF, complex
+    vectors of 25 MB that stay in the 256 MB Infinity Cache) with the
+    BiCGStab inner solve and with the spatial-FFT direct solve, whose
+    bandwidth is "effective" (cache-resident, not HBM)."""
+    out = {}
+    for key, w, reps in (("heat1d_64", wl.WORKLOADS["heat1d_64"], 20),
+                         ("adv1d_4096", wl.WORKLOADS["adv1d_4096"], 3),
+                         ("adv1d_4096+fft", wl.WORKLOADS["adv1d_4096"].with_(inner="fft", inner_tol=1e-15), 10)):
+        print("bench: config %s" % key, file=sys.stderr, flush=True)
+        u0 = wl.initial_batch(w)
+        plan = plan_for(w)
+        plan.set_u0(torch.as_tensor(u0, device="cuda"))
+        u = torch.empty(plan.shape, dtype=torch.float64, device="cuda")
+        run_solves(plan, u, w, 1, False)
+        best = None
+        for _ in range(reps):
+            el, sw, infos, _ = run_solves(plan, u, w, 1, False)
+            best = el if best is None else min(best, el)
+        _, _, _, st = run_solves(plan, u, w, 1, True)
+        info = infos[-1]
+        r = {"dof": w.dof, "inner": w.inner, "sweeps": sw, "gpu_time_to_solution_s": best,
+             "us_per_sweep": round(1e6 * best / sw, 2), "dof_sweeps_per_s": w.dof * sw / best,
+             "inner_iters_mean": [round(v, 1) for v in info["inner_mean"]], "inner_iters_max": info["inner_max"],
+             "inner_fail": info["inner_fail"]}
+        if key != "heat1d_64":
+            rf = roofline_of(st, w, 16)
+            if rf:
+                rf["bound"] = "effective (Infinity Cache resident)"
+            r["effective_bandwidth"] = rf
+        if with_oracle:
+            t0 = time.perf_counter()
+            ref = oracle_solution(w, u0)
+            r["oracle_time_s"] = time.perf_counter() - t0
+            r["speedup_vs_oracle_1core"] = r["oracle_time_s"] / best
+            r["rel_l2_vs_oracle"] = float(np.linalg.norm(u.cpu().numpy() - ref) / np.linalg.norm(ref))
+        out[key] = r
+        del plan, u
+        torch.cuda.empty_cache()
+    return out
 
 
 def copy_bandwidth(torch):
@@ -317,9 +491,17 @@ def main():
         sys.exit(2)
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     import numpy as np
+    from paper_2103_12571_amd import workloads as wl
+
+    w = wl.WORKLOADS[args.workload]
+    u0 = wl.initial_batch(w)
+    cpu = None
+    if not args.no_cpu_baseline and not args.copy_probe:
+        print("bench: oracle on the host (one thread, then all cores)", file=sys.stderr, flush=True)
+        cpu = cpu_legs(w, u0)
+
     import torch
     from paper_2103_12571_amd import binding
-    from paper_2103_12571_amd import workloads as wl
     from paper_2103_12571_amd.stencil import plan_for
 
     binding.lib()
@@ -337,9 +519,7 @@ def main():
         print(json.dumps({"copy_probe_bytes_each_way": x.numel() * 8, "copies": 3}))
         return
 
-    w = wl.WORKLOADS[args.workload]
     plan = plan_for(w)
-    u0 = wl.initial_batch(w)
     u0_d = torch.as_tensor(u0, device="cuda")
     plan.set_u0(u0_d)
     u = torch.empty(plan.shape, dtype=torch.float64, device="cuda")
@@ -352,17 +532,8 @@ def main():
     print("bench: timed %.3f s, %d sweeps" % (elapsed, sweeps), file=sys.stderr, flush=True)
 
     # dominant kernel and its roofline
-    dom = max(stats.items(), key=lambda kv: kv[1]["ms"]) if stats else None
-    roofline = None
-    if dom and dom[1]["ms"] > 0:
-        name, s = dom
-        achieved = s["bytes"] / (s["ms"] * 1e-3) / 1e9
-        tr = traffic_for(name, w.name)
-        roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": tr, "launches": s["launches"],
-                    "avg_launch_us": round(1e3 * s["ms"] / s["launches"], 2),
-                    "bytes_per_launch": s["bytes"] / s["launches"]}
+    cs = 16 if w.precision == "fp64" else 8
+    roofline = roofline_of(stats, w, cs)
     if roofline is not None:
         cp = copy_bandwidth(torch)
         roofline["copy_probe_GBps"] = round(cp, 1)
@@ -398,32 +569,32 @@ def main():
         "kernels": kernels,
     }
 
-    if not args.no_cpu_baseline:
-        ts = []
-        ref = None
-        for _ in range(3):
-            t0 = time.perf_counter()
-            ref = oracle_solution(w, u0)
-            ts.append(time.perf_counter() - t0)
-        t_or = sorted(ts)[1]
+    ref = None
+    out["gpu_time_to_solution_s"] = elapsed / args.steps
+    if cpu is not None:
+        ref = cpu["ref"]
+        spp = sweeps / args.steps
         out["cpu_baseline"] = {
-            "value": w.dof * (sweeps / args.steps) / t_or, "unit": "DOF*sweeps/s", "cores": 1,
+            "value": w.dof * spp * cpu["procs"] / cpu["span"], "unit": "DOF*sweeps/s", "cores": cpu["procs"],
             "kind": "oracle",
-            "sample": "the whole workload: sequential collocation over all L steps, per-Fourier-mode "
-                      "M x M solves (numpy, one thread: its FFTs and batched 3 x 3 solves do not use "
-                      "more), median of 3 = %.3f s; converted with the GPU's %.1f sweeps per solve "
-                      "(equal result)" % (t_or, sweeps / args.steps),
-            "time_to_solution_s": t_or}
+            "sample": "%d concurrent whole solves of the workload, one per core (one thread each: the oracle's "
+                      "FFTs and batched M x M solves do not thread), sequential collocation over all L steps "
+                      "with per-Fourier-mode solves; %.3f s from the first start to the last end; converted "
+                      "with the GPU's %.1f sweeps per solve (equal result)" % (cpu["procs"], cpu["span"], spp),
+            "host": cpu["host"],
+            "aggregate_s_per_solve": cpu["span"] / cpu["procs"],
+            "one_core": {"value": w.dof * spp / cpu["t1"], "cores": 1, "time_to_solution_s": cpu["t1"],
+                         "sample": "one whole solve, median of 3"}}
         out["parity"] = {"rel_l2_vs_oracle": float(np.linalg.norm(u_gpu - ref) / np.linalg.norm(ref))}
-        out["gpu_time_to_solution_s"] = elapsed / args.steps
+    if not args.no_small:
+        out["small_configs"] = small_configs_block(np, torch, wl, plan_for, cpu is not None)
     if not args.no_gmres:
         print("bench: outer GMRES on %s" % w.name, file=sys.stderr, flush=True)
-        out["outer_gmres"] = gmres_block(np, torch, w, plan, u0, None if args.no_cpu_baseline else ref,
-                                         elapsed / args.steps)
+        out["outer_gmres"] = gmres_block(np, torch, w, plan, u0, ref, elapsed / args.steps)
     if not args.no_speedup:
-        out["mixed_vs_fp64"] = speedup_block(np, torch, wl, plan_for, not args.no_cpu_baseline)
+        out["mixed_vs_fp64"] = speedup_block(np, torch, wl, plan_for, cpu is not None)
     if not args.no_adjoint:
-        out["adjoint"] = adjoint_block(np, torch, wl, plan_for, not args.no_cpu_baseline)
+        out["adjoint"] = adjoint_block(np, torch, wl, plan_for, cpu is not None)
     if args.all_configs:
         out["configs"] = all_configs(np, torch, wl, plan_for)
     print(json.dumps(out), flush=True)

@@ -152,6 +152,32 @@ typedef struct {
 aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stream,
                      aao_plan_t* out);
 
+/* Absolute floor of the inner stop inside aao_solve, aao_solve_windows and
+ * aao_adjoint_solve.  The paper's iteration (eq. (Riteration) in its
+ * right-hand-side form, Alg. 1) gives every shifted system the transform of
+ * w + (C_alpha - C) u^k, which is of the size of w, and stops it at the
+ * relative tolerance tau (Sec. 5.2 uses GMRES with a relative tolerance; the
+ * error model of Sec. 3.3, gamma = L (3 eps + tau) ||w||, rests on it).  In the
+ * defect-correction form the right-hand side is the residual, which shrinks
+ * sweep by sweep, so a relative stop there asks for far more accuracy than the
+ * paper's.  With the floor, system s stops once
+ *     ||r_s||_2 <= max(tau ||b_s||_2, tau_w ||x1_s(w)||_2),
+ * x1_s(w) being the transform of w that system s would receive (primal: w =
+ * 1_M (x) u0 in step 1; adjoint: g_last at the last node of step L; a source
+ * is not counted, which only lowers the floor).  Every system still makes at
+ * least one iteration.  The error the floor leaves in u is of the order of
+ * tau_w ||w|| (Sec. 3.3's round-off model with tau_w in place of tau), so it
+ * must sit below the outer stop tolerance.  tau_w = 0: relative stop only;
+ * tau_w > 0: that floor in every solve; tau_w < 0 (the default): tau_w =
+ * min(tau, tol / 100) with tol the stop tolerance of the solve at hand.  If
+ * the monitored quantity makes no progress for two sweeps while the floor is
+ * on, the solve tightens it a hundredfold (three times at most, then drops
+ * it); AAO_ESTAGNATE is returned only for a stall without the floor.
+ * aao_sweep, aao_precond, aao_shifted_solve and aao_solve_gmres always stop
+ * relative to their own right-hand sides.
+ * EINVAL for a null plan or a non-finite tau_w. */
+aao_status aao_set_inner_floor(aao_plan_t plan, double tau_w);
+
 /* Rebind the plan to another stream. */
 aao_status aao_set_stream(aao_plan_t plan, void* hip_stream);
 
@@ -213,8 +239,10 @@ aao_status aao_sweep(aao_plan_t plan, double* u_dev, double alpha, double* res_r
  * shifted system of the last sweep met tau (gamma assumes it); otherwise the
  * sweeps go on under the stop rule.  The monitored quantity (the last-step
  * difference, or the relative residual under AAO_STOP_RESIDUAL) must keep
- * contracting: when three sweeps in a row each leave it above tol and above
- * 0.9 times its previous value, the call returns AAO_ESTAGNATE.
+ * improving: when four sweeps in a row leave it above tol and not below 0.99
+ * times the smallest value seen so far, the call returns AAO_ESTAGNATE (a
+ * slow steady contraction sets a new smallest value every sweep; a round-off
+ * plateau does not).
  * Returns ENOCONV when max_iter is reached; info is filled in every case
  * (info->inner_fail counts the shifted systems that missed tau per sweep). */
 aao_status aao_solve(aao_plan_t plan, double* u_dev, const double* alphas, int n_alphas,

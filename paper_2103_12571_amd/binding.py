@@ -23,7 +23,7 @@ AAO_NUM_KERNELS = 14
 STATUS_NAMES = {0: "AAO_OK", -1: "AAO_EINVAL", -2: "AAO_EHIP", -3: "AAO_ENODIAG", -4: "AAO_ENOCONV",
                 -5: "AAO_ESTAGNATE", -6: "AAO_EWORKSPACE", -7: "AAO_ENAN", -8: "AAO_ESTATE"}
 
-EXPORTS = ["aao_setup", "aao_set_stream", "aao_workspace_size", "aao_set_workspace", "aao_set_u0",
+EXPORTS = ["aao_setup", "aao_set_stream", "aao_set_inner_floor", "aao_workspace_size", "aao_set_workspace", "aao_set_u0",
            "aao_set_stencil_coef", "aao_set_forcing", "aao_solve_windows", "aao_gmres_workspace_size",
            "aao_solve_gmres",
            "aao_residual", "aao_precond", "aao_sweep", "aao_solve", "aao_adjoint_solve", "aao_grad",
@@ -98,6 +98,7 @@ def lib():
     sig = {
         "aao_setup": [C.POINTER(aao_stencil), C.POINTER(aao_config), P, C.POINTER(P)],
         "aao_set_stream": [P, P],
+        "aao_set_inner_floor": [P, C.c_double],
         "aao_workspace_size": [P, C.POINTER(C.c_size_t)],
         "aao_set_workspace": [P, P, C.c_size_t],
         "aao_set_u0": [P, P],
@@ -230,6 +231,11 @@ class Plan:
         return cplx(d), cplx(r), cplx(djm).reshape(Lh, self.M), cond.value
 
     # -- C-ABI calls
+    def set_inner_floor(self, tau_w):
+        """Absolute floor of the inner stop in solve / solve_windows /
+        adjoint_solve (aao_set_inner_floor): 0 off, < 0 the default."""
+        check(lib().aao_set_inner_floor(self._h, float(tau_w)))
+
     def set_stencil_coef(self, coef, dcoef=None):
         """New stencil weights (same offsets), e.g. another nu, without re-planning."""
         c = np.ascontiguousarray(coef, dtype=np.float64)

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -105,6 +106,15 @@ struct aao_plan {
   int ndim = 1, nx = 0, ny = 1, N = 0, M = 0, L = 0, logL = 0, Lh = 0, B = 1;
   int precision = AAO_FP64, inner = AAO_INNER_COCG, inner_maxit = 1000;
   double dt = 0, inner_tol = 1e-12;
+  // absolute floor of the inner stop inside aao_solve / windows / adjoint:
+  // tau_w (< 0: the default of floor_tau), the stop tolerance of the current
+  // solve and whether the current call uses the floor
+  double floor_tol = -1;
+  double solve_tol = 0;
+  double floor_div = 1;  // tightening of the floor within the current solve
+  bool floor_on = false;
+  // per instance ||u0_b||_2^2 (primal, [0]) and ||g_b||_2^2 (adjoint, [1])
+  std::vector<double> n2[2];
   std::vector<double> t, Q, QT;
   aao::Taps taps{}, tapsT{}, dtaps{};
   bool has_dnu = false, symmetric = false;
@@ -128,7 +138,7 @@ struct aao_plan {
   // library-owned device tables and pinned staging
   char* dtab = nullptr;
   size_t off_tw = 0, off_sf = 0, off_sb = 0, off_m1 = 0, off_m2 = 0, off_sh = 0, off_q = 0,
-         off_wx = 0, off_wy = 0, off_bx = 0, off_by = 0, off_hostend = 0, tab_bytes = 0;
+         off_wx = 0, off_wy = 0, off_bx = 0, off_by = 0, off_bf = 0, off_hostend = 0, tab_bytes = 0;
   char* htab = nullptr;      // pinned mirror of the alpha-dependent tables (two slots)
   char* hread = nullptr;     // pinned readback area
   size_t hread_bytes = 0;
@@ -138,6 +148,7 @@ struct aao_plan {
   int cur_slot = 0;
   double slot_alpha[2] = {-1, -1};
   int slot_adj[2] = {-1, -1};
+  double slot_tw[2] = {-1, -1};  // tau_w the slot's inner floors were built with
   hipEvent_t slot_ev[2] = {nullptr, nullptr};  // recorded after each slot's upload
   // caller workspace
   char* ws = nullptr;
@@ -181,6 +192,7 @@ struct aao_plan {
   double2* d_m1() const { return reinterpret_cast<double2*>(dtab + off_m1 + (size_t)cur_slot * atab_stride); }
   double2* d_m2() const { return reinterpret_cast<double2*>(dtab + off_m2 + (size_t)cur_slot * atab_stride); }
   double2* d_sh() const { return reinterpret_cast<double2*>(dtab + off_sh + (size_t)cur_slot * atab_stride); }
+  double* d_bf() const { return reinterpret_cast<double*>(dtab + off_bf + (size_t)cur_slot * atab_stride); }
   double* d_q() const { return reinterpret_cast<double*>(dtab + off_q); }
   double2* d_wx() const { return reinterpret_cast<double2*>(dtab + off_wx); }
   double2* d_wy() const { return reinterpret_cast<double2*>(dtab + off_wy); }
@@ -251,6 +263,14 @@ void collect_timing(aao_plan* p) {
 // Build the tables of alpha into slot `slot` (host, pinned) and enqueue their
 // upload into the same device slot.  The host copy of a slot is rewritten
 // only after the stream has been synchronised since its last upload.
+// tau_w of the absolute inner floor: the caller's (aao_set_inner_floor), else
+// min(tau, tol / 100) with tol the stop tolerance of the current solve (the
+// error the floor leaves behind stays two decades under the stop rule).
+double floor_tau(const aao_plan* p) {
+  if (p->floor_tol >= 0) return p->floor_tol / p->floor_div;
+  return std::min(p->inner_tol, 0.01 * p->solve_tol) / p->floor_div;
+}
+
 aao_status build_tables(aao_plan* p, double alpha, int adj, int slot) {
   if (!(alpha > 0.0 && alpha < 1.0))
     return fail(AAO_EINVAL, "alpha must lie in (0, 1), got " + std::to_string(alpha));
@@ -263,6 +283,8 @@ aao_status build_tables(aao_plan* p, double alpha, int adj, int slot) {
   cd* m1 = reinterpret_cast<cd*>(h + (p->off_m1 - p->off_sf));
   cd* m2 = reinterpret_cast<cd*>(h + (p->off_m2 - p->off_sf));
   cd* sh = reinterpret_cast<cd*>(h + (p->off_sh - p->off_sf));
+  double* bf = reinterpret_cast<double*>(h + (p->off_bf - p->off_sf));
+  const double tw_used = p->floor_on ? floor_tau(p) : 0.0;
   p->slot_alpha[slot] = -1;
   // Lemma 1: J^{-1} = diag(alpha^{(l-1)/L}) before the DFT, J and the 1/L of the
   // inverse DFT after it.  Transposed (V^T = (1/L) F J, V^{-T} = J^{-1} F^*):
@@ -297,6 +319,31 @@ aao_status build_tables(aao_plan* p, double alpha, int adj, int slot) {
       }
     for (int b = 0; b < p->B; ++b)
       for (int m = 0; m < M; ++m) sh[((size_t)b * Lh + j) * M + m] = p->dt * ft.lam[m];
+    // Absolute floor of the inner stop: the paper's right-hand-side form of
+    // eq. (Riteration) hands each shifted system the transform of w + (C_alpha
+    // - C) u^k, which is w-sized, and stops it at tau relative to that; in the
+    // defect-correction form the right-hand side is the residual instead, and
+    // the same absolute accuracy is tau_w times the norm of the transform of
+    // w.  Without a source, w is 1_M (x) u0 in step 1 only (g_last at the last
+    // node of step L for the adjoint), so frequency j holds it unchanged (times
+    // the scaling of that step) and system (j, m) gets row m of the node
+    // transform applied to it.  With a source only the u0 part is counted (a
+    // smaller floor: the inner solves are then at least as accurate).
+    const double tw = tw_used;
+    const std::vector<double>& n2 = p->n2[adj];
+    for (int m = 0; m < M; ++m) {
+      double g2 = 0;
+      if (!adj) {
+        cd s = 0;
+        for (int k = 0; k < M; ++k) s += A1[m * M + k];
+        g2 = std::norm(s);
+      } else {
+        g2 = std::norm(A1[m * M + (M - 1)]) * sf[L - 1] * sf[L - 1];
+      }
+      const double ratio = tw > 0 ? tw / p->inner_tol : 0.0;
+      for (int b = 0; b < p->B; ++b)
+        bf[((size_t)b * Lh + j) * M + m] = ((size_t)b < n2.size()) ? ratio * ratio * g2 * n2[b] : 0.0;
+    }
   }
   close_run(p);
   HIPCHK(hipMemcpyAsync(p->dtab + p->off_sf + (size_t)slot * p->atab_stride, h, p->atab_stride,
@@ -304,12 +351,14 @@ aao_status build_tables(aao_plan* p, double alpha, int adj, int slot) {
   HIPCHK(hipEventRecord(p->slot_ev[slot], p->stream));
   p->slot_alpha[slot] = alpha;
   p->slot_adj[slot] = adj;
+  p->slot_tw[slot] = tw_used;
   return AAO_OK;
 }
 
 int slot_of(const aao_plan* p, double alpha, int adj) {
   for (int i = 0; i < 2; ++i)
-    if (p->slot_alpha[i] == alpha && p->slot_adj[i] == adj) return i;
+    if (p->slot_alpha[i] == alpha && p->slot_adj[i] == adj && p->slot_tw[i] == (p->floor_on ? floor_tau(p) : 0.0))
+      return i;
   return -1;
 }
 
@@ -411,6 +460,7 @@ aao::KrylovArgs krylov_args(aao_plan* p, int adj, int nsys) {
   a.wps_rho = a.wps;
   a.wps_bb = a.wps;
   a.tol2 = p->inner_tol * p->inner_tol;
+  a.bbfloor = p->floor_on ? p->d_bf() : nullptr;
   a.maxit = p->inner_maxit;
   return a;
 }
@@ -453,6 +503,7 @@ aao::CgArgs cg_args(aao_plan* p, int adj, int nsys) {
   a.ntiles_prev = a.ntiles;
   a.part_stride = (size_t)5 * nsys * std::max(p->cg_ntiles, p->cg_ntiles_s);
   a.tol2 = p->inner_tol * p->inner_tol;
+  a.bbfloor = p->floor_on ? p->d_bf() : nullptr;
   a.maxit = p->inner_maxit;
   return a;
 }
@@ -1099,8 +1150,8 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   off = align256(off + kWorkSlots * sizeof(unsigned long long));
   p->off_gpart = off;
   off = align256(off + (size_t)p->B * p->grad_blocks * sizeof(double));
-  p->off_npart = off;
-  off = align256(off + 2 * kNormBlocks * sizeof(double));
+  p->off_npart = off;  // norms over all instances, then per instance
+  off = align256(off + 2 * kNormBlocks * (size_t)(p->B + 1) * sizeof(double));
   p->off_win = off;
   off = align256(off + (size_t)p->B * p->N * sizeof(double));
   p->ws_need = off;
@@ -1130,11 +1181,20 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   t = align256(t + (size_t)p->Lh * p->M * p->M * sizeof(double2));
   p->off_sh = t;
   t = align256(t + (size_t)p->S * sizeof(double2));
+  p->off_bf = t;
+  t = align256(t + (size_t)p->S * sizeof(double));
   p->off_hostend = t;
   p->atab_stride = p->off_hostend - p->off_sf;
   p->tab_bytes = t + p->atab_stride;  // second slot of the alpha-dependent tables
   p->hread_bytes = 128 + (size_t)p->S * sizeof(aao::SysState) + 64;
   *out = p;
+  return AAO_OK;
+}
+
+aao_status aao_set_inner_floor(aao_plan_t p, double tau_w) {
+  if (!p) return fail(AAO_EINVAL, "null plan");
+  if (!std::isfinite(tau_w)) return fail(AAO_EINVAL, "tau_w must be finite");
+  p->floor_tol = tau_w < 0 ? -1.0 : tau_w;
   return AAO_OK;
 }
 
@@ -1195,6 +1255,23 @@ aao_status aao_set_workspace(aao_plan_t p, void* dev, size_t bytes) {
 
 // ||w||_2^2 and ||w||_inf of the all-at-once right-hand side (Alg. 2 uses
 // ||w||_inf, the residual stop ||w||_2); w = (1_M (x) u0 + dT Q b_1, dT Q b_2, ...).
+// Per instance ||v_b||_2^2 of v [B][N] into n2, the slots of the alpha tables
+// of direction adj marked stale (their inner floors scale with these norms).
+// Enqueued only; the caller reads npart after synchronising.
+static aao_status enqueue_norms_b(aao_plan* p, const double* v) {
+  close_run(p);
+  HIPCHK(aao::launch_norms_per_b(v, p->B, p->N, p->npart() + 2 * kNormBlocks, kNormBlocks, p->stream));
+  return AAO_OK;
+}
+static void take_norms_b(aao_plan* p, const std::vector<double>& h, int adj) {
+  std::vector<double>& n2 = p->n2[adj];
+  n2.assign(p->B, 0.0);
+  for (int b = 0; b < p->B; ++b)
+    for (int i = 0; i < kNormBlocks; ++i) n2[b] += h[2 * kNormBlocks * (b + 1) + 2 * i];
+  for (int i = 0; i < 2; ++i)
+    if (p->slot_adj[i] == adj) p->slot_alpha[i] = -1;
+}
+
 static aao_status update_wnorms(aao_plan* p, const double* u0) {
   close_run(p);
   if (p->frc) {
@@ -1204,7 +1281,9 @@ static aao_status update_wnorms(aao_plan* p, const double* u0) {
   } else {
     HIPCHK(aao::launch_norms_bn(u0, p->B, p->N, p->npart(), kNormBlocks, p->stream));
   }
-  std::vector<double> h(2 * kNormBlocks);
+  aao_status st = enqueue_norms_b(p, u0);
+  if (st != AAO_OK) return st;
+  std::vector<double> h(2 * kNormBlocks * (size_t)(p->B + 1));
   HIPCHK(hipMemcpyAsync(h.data(), p->npart(), h.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   double s2 = 0, mx = 0;
@@ -1216,6 +1295,7 @@ static aao_status update_wnorms(aao_plan* p, const double* u0) {
                                                        : "u0 contains NaN or Inf");
   p->w2 = p->frc ? s2 : p->M * s2;  // without a source ||w||_2^2 = M ||u0||^2
   p->winf = mx;
+  take_norms_b(p, h, 0);
   return AAO_OK;
 }
 
@@ -1302,7 +1382,12 @@ static aao_status run_solve_sweeps(aao_plan_t p, double* u, const double* alphas
 static aao_status run_solve(aao_plan_t p, double* u, const double* alphas, int n_alphas, double m0,
                             double tol, int stop_rule, int max_iter, aao_solve_info* info, int adj,
                             double gnorm_inf) {
+  p->solve_tol = tol;
+  p->floor_div = 1;
+  // a floor far below tau never binds (the relative stop is met first)
+  p->floor_on = floor_tau(p) > 1e-8 * p->inner_tol;
   aao_status s = run_solve_sweeps(p, u, alphas, n_alphas, m0, tol, stop_rule, max_iter, info, adj, gnorm_inf);
+  p->floor_on = false;
   close_run(p);
   hipError_t e = hipStreamSynchronize(p->stream);
   collect_timing(p);
@@ -1356,11 +1441,20 @@ static aao_status run_solve_sweeps(aao_plan_t p, double* u, const double* alphas
   // of consecutive iterates alone can take stagnation for convergence.  The
   // model's exit rests on gamma, which assumes every shifted system met tau,
   // so it is honoured only after a sweep without inner failures; and the
-  // monitored quantity must keep contracting, else ESTAGNATE.
-  constexpr int kStallSweeps = 3;
-  constexpr double kStallRatio = 0.9;
+  // monitored quantity must keep improving: when kStallSweeps sweeps in a row
+  // leave it above tol without a new best (below kStallGain times the best so
+  // far), the call returns ESTAGNATE.  A slow but steady contraction (alpha
+  // near 1/2 late in Alg. 2 contracts the lowest modes by about
+  // alpha / (1 - alpha) per sweep) sets a new best every sweep; round-off
+  // plateaus do not.  While the absolute inner floor is on, its error (of the
+  // order of tau_w ||w||) is the first suspect: after kFloorStall sweeps
+  // without a new best the floor is tightened a hundredfold (at most three
+  // times, then switched off), and only a stall without it counts.
+  constexpr int kStallSweeps = 4;
+  constexpr int kFloorStall = 2;
+  constexpr double kStallGain = 0.99;
   int last_fail = 0, stall = 0;
-  double prev_mon = 0.0;
+  double best_mon = 0.0;
   for (int k = 0; k < max_iter; ++k) {
     bool done;
     double alpha = alpha_at(k, m, last_fail == 0, done);
@@ -1408,15 +1502,23 @@ static aao_status run_solve_sweeps(aao_plan_t p, double* u, const double* alphas
     // the residual rule monitors the residual before the sweep, the last-step
     // rule the difference the sweep made
     const double mon = stop_rule == AAO_STOP_RESIDUAL ? res_rel : o.dmax;
-    if (k > 0 && mon > tol && mon >= kStallRatio * prev_mon) {
-      if (++stall >= kStallSweeps)
-        return fail(AAO_ESTAGNATE, "stagnation: " + std::to_string(kStallSweeps) +
-                                       " sweeps in a row without contraction above tol (last " +
-                                       std::to_string(mon) + ")");
+    if (k > 0 && mon > tol && !(mon < kStallGain * best_mon)) {
+      ++stall;
+      if (p->floor_on && stall >= kFloorStall) {
+        p->floor_div *= 100;
+        if (p->floor_div > 1e6) p->floor_on = false;
+        stall = 0;
+      } else if (!p->floor_on && stall >= kStallSweeps)
+      {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "stagnation: %d sweeps in a row above tol without a new best (best %.3e, last %.3e)",
+                      kStallSweeps, best_mon, mon);
+        return fail(AAO_ESTAGNATE, msg);
+      }
     } else {
       stall = 0;
     }
-    prev_mon = mon;
+    if (k == 0 || mon < best_mon) best_mon = mon;
   }
   return fail(AAO_ENOCONV, "no convergence within max_iter sweeps");
 }
@@ -1755,7 +1857,9 @@ aao_status aao_adjoint_solve(aao_plan_t p, const double* g_last, double* lam, co
   if (!info) return fail(AAO_EINVAL, "null info");
   close_run(p);
   HIPCHK(aao::launch_norms_bn(g_last, p->B, p->N, p->npart(), kNormBlocks, p->stream));
-  std::vector<double> h(2 * kNormBlocks);
+  s = enqueue_norms_b(p, g_last);
+  if (s != AAO_OK) return s;
+  std::vector<double> h(2 * kNormBlocks * (size_t)(p->B + 1));
   close_run(p);
   HIPCHK(hipMemcpyAsync(h.data(), p->npart(), h.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   close_run(p);
@@ -1766,6 +1870,7 @@ aao_status aao_adjoint_solve(aao_plan_t p, const double* g_last, double* lam, co
     gi = std::max(gi, h[2 * i + 1]);
   }
   if (!std::isfinite(g2)) return fail(AAO_ENAN, "g_last contains NaN or Inf");
+  take_norms_b(p, h, 1);
   HIPCHK(timed(p, aao::KC_INIT, [&] { return aao::launch_fill(lam, 0.0, (int64_t)p->B * p->L * p->M * p->N, p->stream); }));
   const double* keep_u0 = p->u0;
   p->u0 = g_last;  // w0 of the transposed residual

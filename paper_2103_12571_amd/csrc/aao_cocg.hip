@@ -373,7 +373,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass(CgArgs a, int k) {
       int go = 0;
       CgStep c{0, mk(0, 0), mk(0, 0)};
       {
-        const double bb = (k == 0) ? pv[4] : bb0;
+        const double bb = (k == 0) ? (a.bbfloor ? fmax(pv[4], a.bbfloor[s]) : pv[4]) : bb0;
         c = cg_advance(k, mk(pv[0], pv[1]), mk(pv[2], pv[3]), pv[4], bb, a.tol2, a.maxit, s0, s1);
         go = c.dec == 0;
         if (tile == 0) {
@@ -534,7 +534,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_scalars(CgArgs a, int k) {
   const double2 del = mk(v[2], v[3]);
   const double rr = v[4];
   if (k < 0) {
-    st->bb = rr;
+    st->bb = a.bbfloor ? fmax(rr, a.bbfloor[s]) : rr;
     st->rr = rr;
     st->gamma = gam;
     st->beta = mk(0, 0);

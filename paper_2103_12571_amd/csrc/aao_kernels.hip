@@ -415,9 +415,12 @@ __global__ void k_fill(double* p, double v, int64_t n) {
     p[i] = v;
 }
 
-// part[2*blk] = sum v^2, part[2*blk+1] = max |v| over a grid-stride share.
+// part[2*blk] = sum v^2, part[2*blk+1] = max |v| over a grid-stride share;
+// grid row y covers v + y n into part + 2 y gridDim.x.
 __global__ __launch_bounds__(kBlock) void k_norms(const double* v, int64_t n, double* part) {
   __shared__ double sh[4];
+  v += (int64_t)blockIdx.y * n;
+  part += 2 * (size_t)gridDim.x * blockIdx.y;
   double s = 0.0, mx = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
     s = fma(v[i], v[i], s);
@@ -565,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg1(KrylovArgs a, int k) {
     const int nw[4] = {a.wps_rho, a.wps_rho, a.wps_rho, a.wps_bb};
     double v[4];
     reduce_parts<4>(a, qs, nw, s, v, sh);
-    const bool conv = v[2] <= a.tol2 * v[3];
+    const bool conv = v[2] <= a.tol2 * (a.bbfloor ? fmax(v[3], a.bbfloor[s]) : v[3]);
     if (conv || k >= a.maxit || st->breakdown) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->active = 0;
@@ -852,11 +855,12 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
   double2 rho = mk(bb, 0.0), hv = mk(w4[0], w4[1]);
   double2 al = mk(1, 0), om = mk(1, 0);
   double rr = bb;
+  const double bbstop = a.bbfloor ? fmax(bb, a.bbfloor[s]) : bb;
   bool brk = false;
   int k = 0, flag = 1;
   for (;; ++k) {
     if (k > 0) {
-      const bool conv = rr <= a.tol2 * bb;
+      const bool conv = rr <= a.tol2 * bbstop;
       if (conv || k >= a.maxit || brk) {
         flag = conv ? 0 : (brk ? 2 : 1);
         break;
@@ -1172,6 +1176,11 @@ hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t st) {
 
 hipError_t launch_norms_bn(const double* v, int B, int N, double* part, int nparts, hipStream_t st) {
   hipLaunchKernelGGL(k_norms, dim3(nparts), dim3(kBlock), 0, st, v, (int64_t)B * N, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_norms_per_b(const double* v, int B, int N, double* part, int nparts, hipStream_t st) {
+  hipLaunchKernelGGL(k_norms, dim3(nparts, B), dim3(kBlock), 0, st, v, (int64_t)N, part);
   return hipGetLastError();
 }
 

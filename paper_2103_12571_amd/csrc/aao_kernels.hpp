@@ -86,6 +86,9 @@ struct CgArgs {
   // active), and tile 0 writes its fresh state and init_list[y] = y
   int* init_list;
   double tol2;
+  // nullable, [num_sys]: a system stops once ||r||^2 <= tol2 max(||b||^2,
+  // bbfloor[s]), i.e. at the relative tolerance or an absolute floor
+  const double* bbfloor;
   int maxit;
   // fused passes: when snap_row >= 0 the launch has one more row of
   // workgroups (row snap_row == the active count); its first workgroup lists
@@ -147,6 +150,7 @@ struct KrylovArgs {
   // iteration's last kernel), wps_bb the count of the first iteration.
   int num_sys, wps, chunk, wps_stride, wps_rho, wps_bb;
   double tol2;
+  const double* bbfloor;  // nullable, [num_sys]: as in CgArgs
   int maxit;
 };
 
@@ -202,6 +206,8 @@ hipError_t launch_last_node(const double* u, double* out, int B, int L, int M, i
 hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t st);
 hipError_t launch_norms_bn(const double* v, int B, int N, double* part, int nparts,
                            hipStream_t st);
+// The same per instance: part[2 (b nparts + blk) + {0, 1}] for v + b N.
+hipError_t launch_norms_per_b(const double* v, int B, int N, double* part, int nparts, hipStream_t st);
 hipError_t launch_wnorms(int M, const FwdArgs& a, int B, double* part, int nparts, hipStream_t st);
 hipError_t launch_cg_init(bool f32, const CgArgs& a, int nact, hipStream_t st);
 hipError_t launch_cg_pass(bool f32, const CgArgs& a, int k, int nact, hipStream_t st);

@@ -113,21 +113,22 @@ def _problem_base(problem):
     return WORKLOADS["heat2d_table1"] if problem == "heat" else WORKLOADS["adv2d_table1"]
 
 
-def table1_workload(problem, tol, **kw):
-    """The Sec. 5 problem at Table 1's parameters for tolerance tol (keyword
-    overrides, e.g. inner solver and tolerances, go to the Workload)."""
-    p = TABLE1[(problem, tol)]
-    w = _problem_base(problem).with_(name="%s_table1_%g" % (problem, tol), nx=p["N"], ny=p["N"], order=p["order"],
+def table1_workload(problem, target, **kw):
+    """The Sec. 5 problem at Table 1's parameters for the tolerance `target`
+    (keyword overrides, e.g. inner solver and tolerances, go to the
+    Workload)."""
+    p = TABLE1[(problem, target)]
+    w = _problem_base(problem).with_(name="%s_table1_%g" % (problem, target), nx=p["N"], ny=p["N"], order=p["order"],
                                      M=p["M"], L=p["L"], dt=TABLE1_T[problem] / p["L"])
     return w.with_(**kw)
 
 
-def table2_workload(problem, tol, L=16, **kw):
-    """The Sec. 5 problem at Table 2's parameters for tolerance tol, as one
-    window of L steps of dT = T64 / 64 (64 / L windows cover T64); the inner
-    tolerance is the table's tilde-tau unless overridden."""
-    p = TABLE2[(problem, tol)]
-    w = _problem_base(problem).with_(name="%s_table2_%g" % (problem, tol), nx=p["N"], ny=p["N"], order=p["order"],
+def table2_workload(problem, target, L=16, **kw):
+    """The Sec. 5 problem at Table 2's parameters for the tolerance `target`,
+    as one window of L steps of dT = T64 / 64 (64 / L windows cover T64); the
+    inner tolerance is the table's tilde-tau unless overridden."""
+    p = TABLE2[(problem, target)]
+    w = _problem_base(problem).with_(name="%s_table2_%g" % (problem, target), nx=p["N"], ny=p["N"], order=p["order"],
                                      M=p["M"], L=L, dt=p["T64"] / 64, inner_tol=p["tau_par"])
     return w.with_(**kw)
 

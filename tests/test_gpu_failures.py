@@ -30,20 +30,31 @@ def _oracle(w, u0):
     return oracle.sequential_solve(op, Q, w.dt, u0[0], w.L, backend="spectral")
 
 
+@pytest.mark.parametrize("floor", ["off", "default"])
 @pytest.mark.parametrize("inner,cap", [("cocg", 2), ("bicgstab", 2)])
-def test_inner_iteration_cap_is_reported(inner, cap):
+def test_inner_iteration_cap_is_reported(inner, cap, floor):
+    """Every shifted system is capped at two iterations.  Without the inner
+    floor each sweep asks for tau relative to its residual, so some systems
+    fail in every sweep; with the default floor the later sweeps' systems may
+    meet it within the cap, but the first sweep's cannot."""
     need_gpu()
-    say("inner cap", inner, cap)
+    say("inner cap", inner, cap, "floor", floor)
     w = HEAT.with_(inner=inner)
     p = plan_for(w, inner_maxit=cap)
+    if floor == "off":
+        p.set_inner_floor(0.0)
     p.set_u0(dev(wl.initial_batch(w)))
     u, info = p.solve(tol=1e-10, max_iter=12, raise_on_noconv=False)
     say("  status", info["status"], "sweeps", info["iterations"], "fails", info["inner_fail"],
         "dlast", ["%.1e" % d for d in info["dlast_inf"]])
     S = w.batch * (w.L // 2 + 1) * w.M
-    assert all(0 < f <= S for f in info["inner_fail"])
+    assert all(0 <= f <= S for f in info["inner_fail"]) and info["inner_fail"][0] > 0
+    if floor == "off":
+        assert all(f > 0 for f in info["inner_fail"])
     assert info["inner_fail_total"] == sum(info["inner_fail"])
-    assert all(m == cap for m in info["inner_max"])
+    assert all(m <= cap for m in info["inner_max"]) and info["inner_max"][0] == cap
+    if floor == "off":
+        assert all(m == cap for m in info["inner_max"])
     if info["status"] == "AAO_OK":
         # never Alg. 2's model exit after a sweep with failed systems: the stop rule held
         assert info["converged"] and info["dlast_inf"][-1] <= 1e-10
@@ -66,7 +77,7 @@ def test_no_failures_reported_when_every_system_converges():
 @pytest.mark.parametrize("stop", ["laststep", "residual"])
 def test_unreachable_tolerance_stagnates(stop):
     """tol below FP64 round-off: the last-step differences (or residuals)
-    settle at the round-off level and stop contracting; the call returns
+    settle at the round-off level and stop improving; the call returns
     AAO_ESTAGNATE well before max_iter, with a result as accurate as ever."""
     need_gpu()
     w = HEAT.with_(inner="fft", inner_tol=1e-15)
@@ -78,8 +89,8 @@ def test_unreachable_tolerance_stagnates(stop):
     say("unreachable tol", stop, info["status"], "sweeps", info["iterations"], ["%.1e" % v for v in mon])
     assert info["status"] == "AAO_ESTAGNATE" and not info["converged"]
     assert info["iterations"] < 40
-    tail = mon[-4:]
-    assert all(b >= 0.9 * a for a, b in zip(tail[:-1], tail[1:]))
+    # the last four sweeps set no new best (none below 0.99 x the smallest before them)
+    assert min(mon[-4:]) >= 0.99 * min(mon[:-4])
     assert rel_l2(host(u)[0], _oracle(w, u0)) < 1e-12
     with pytest.raises(bd.AAOError) as e:
         p.solve(tol=1e-300, stop=stop, max_iter=40)
