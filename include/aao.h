@@ -212,6 +212,24 @@ aao_status aao_set_forcing(aao_plan_t plan, const double* b_dev);
  * (nullable host out) = ||r||_2 / ||w||_2. */
 aao_status aao_residual(aao_plan_t plan, const double* u_dev, double* r_dev, double* res_norm);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): aao_residual
+ * with no workspace and no allocation.  Its partial sums and norms live in a
+ * fixed 14 KiB device array inside the library (one per GPU, held until the
+ * process ends), looked up once per device; the plan needs only aao_setup
+ * (host-only), not aao_set_workspace or aao_set_u0.  u0_dev [B][N] defines w
+ * as in aao_set_u0 (plus the plan's source, if aao_set_forcing gave one).
+ * r_dev [B][L][M][N] receives w - C u; res_norm (nullable host out) =
+ * ||r||_2 / ||w||_2, computed by the same kernels in the same order as
+ * aao_residual, so both calls give the same bits.  Any problem size fits: at
+ * most 1024 partial sums are formed (EINVAL otherwise, never reached).  The
+ * plan's device must be current; the call synchronises the plan's stream.  Every call on one GPU shares the array: calls that overlap on one
+ * GPU (other threads, other streams) race and must be serialised by the
+ * caller.  Nothing in the array needs to start at zero (every slot read is
+ * written first by the same call).  EINVAL for null arguments, EHIP, ENAN. */
+aao_status aao_residual_noalloc(aao_plan_t plan, const double* u0_dev, const double* u_dev, double* r_dev,
+                                double* res_norm);
+
 /* Rows a2-a4: delta = C_alpha^{-1} r via Alg. 1's diagonalised steps
  * (Lemma 1; eqs. (s123), (innercoll), (innerdiag), (QGL)).  r_dev and
  * delta_dev are [B][L][M][N]; they may alias.  alpha in (0, 1).

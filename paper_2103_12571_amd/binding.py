@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "AAO_OK", -1: "AAO_EINVAL", -2: "AAO_EHIP", -3: "AAO_ENODIAG"
 EXPORTS = ["aao_setup", "aao_set_stream", "aao_set_inner_floor", "aao_workspace_size", "aao_set_workspace", "aao_set_u0",
            "aao_set_stencil_coef", "aao_set_forcing", "aao_solve_windows", "aao_gmres_workspace_size",
            "aao_solve_gmres",
-           "aao_residual", "aao_precond", "aao_sweep", "aao_solve", "aao_adjoint_solve", "aao_grad",
+           "aao_residual", "aao_residual_noalloc", "aao_precond", "aao_sweep", "aao_solve", "aao_adjoint_solve", "aao_grad",
            "aao_shifted_solve", "aao_set_timing", "aao_get_stats", "aao_reset_stats", "aao_kernel_name",
            "aao_tables", "aao_collocation", "aao_last_error", "aao_destroy"]
 
@@ -110,6 +110,7 @@ def lib():
         "aao_solve_gmres": [P, P, C.c_int, D, C.c_int, C.c_double, C.c_int, P, C.c_size_t,
                             C.POINTER(aao_gmres_info)],
         "aao_residual": [P, P, P, D],
+        "aao_residual_noalloc": [P, P, P, P, D],
         "aao_precond": [P, P, P, C.c_double],
         "aao_sweep": [P, P, C.c_double, D, D],
         "aao_solve": [P, P, D, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, C.POINTER(aao_solve_info)],
@@ -278,6 +279,17 @@ class Plan:
         nrm = C.c_double()
         self._sync_stream()
         check(lib().aao_residual(self._h, _ptr(u), _ptr(r), C.byref(nrm)))
+        return r, nrm.value
+
+    def residual_noalloc(self, u, u0=None):
+        """aao_residual_noalloc: the residual with the library's fixed device
+        scratch (no workspace); u0 defaults to the plan's own."""
+        u = self._f64(u, self.shape)
+        u0 = self._u0 if u0 is None else self._f64(u0, (self.B, self.N))
+        r = self.torch.empty_like(u)
+        nrm = C.c_double()
+        self._sync_stream()
+        check(lib().aao_residual_noalloc(self._h, _ptr(u0), _ptr(u), _ptr(r), C.byref(nrm)))
         return r, nrm.value
 
     def precond(self, r, alpha):

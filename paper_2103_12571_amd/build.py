@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libaao.so")
 OBJ = os.path.join(ROOT, "_build")
 SOURCES = ["csrc/aao_kernels.hip", "csrc/aao_cocg.hip", "csrc/aao_fftsolve.hip", "csrc/aao_gmres.hip",
-           "csrc/aao_api.cpp", "csrc/aao_host.cpp"]
+           "csrc/aao_noalloc.hip", "csrc/aao_api.cpp", "csrc/aao_host.cpp"]
 
 
 def hipcc():

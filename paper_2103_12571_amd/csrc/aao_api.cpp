@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "aao.h"
+#include "aao_noalloc.hpp"
 #include "aao_host.hpp"
 #include "aao_kernels.hpp"
 
@@ -1337,6 +1338,57 @@ aao_status aao_residual(aao_plan_t p, const double* u, double* r, double* res_no
   s = read_back(p, 0, true, o);
   if (s != AAO_OK) return s;
   if (res_norm) *res_norm = std::sqrt(o.res2) / std::sqrt(p->w2);
+  return AAO_OK;
+}
+
+// aao_residual with its partial sums in the library's fixed device scratch
+// (aao_noalloc.hip) instead of the plan's workspace: no workspace, no
+// aao_set_u0, no allocation.  The kernels and the order of every reduction are
+// those of aao_residual and aao_set_u0, so r and the norm come out the same
+// bit for bit.
+aao_status aao_residual_noalloc(aao_plan_t p, const double* u0, const double* u, double* r, double* res_norm) {
+  if (!p) return fail(AAO_EINVAL, "null plan");
+  if (!u0 || !u || !r) return fail(AAO_EINVAL, "null array");
+  const int nblk = std::min(1024, std::max(1, (int)(((int64_t)p->B * p->L * p->N + 255) / 256)));
+  if (nblk > aao::kScratchResParts || kNormBlocks != aao::kScratchWBlocks)
+    return fail(AAO_EINVAL, "residual partial sums exceed the fixed scratch (" +
+                                std::to_string(aao::kScratchResParts) + " blocks)");
+  double* sc = nullptr;
+  HIPCHK(aao::noalloc_scratch(&sc));
+  aao::FwdArgs fa{};
+  fa.u = u;
+  fa.w0 = u0;
+  fa.frc = p->frc;
+  fa.part = sc;
+  fa.g = {p->nx, p->ny, p->N};
+  fa.taps = p->taps;
+  for (int i = 0; i < p->M * p->M; ++i) fa.q[i] = p->Q[i];
+  fa.dt = p->dt;
+  fa.L = p->L;
+  fa.logL = p->logL;
+  fa.Lh = p->Lh;
+  fa.TN = p->TN;
+  fa.logTN = p->logTN;
+  // ||w||: the kernels of aao_set_u0 into the scratch's w-norm slots
+  if (p->frc) {
+    aao::FwdArgs fw = fa;
+    fw.part = nullptr;
+    HIPCHK(aao::launch_wnorms(p->M, fw, p->B, sc + aao::kScratchWParts, kNormBlocks, p->stream));
+  } else {
+    HIPCHK(aao::launch_norms_bn(u0, p->B, p->N, sc + aao::kScratchWParts, kNormBlocks, p->stream));
+  }
+  HIPCHK(aao::launch_residual(p->M, false, fa, r, p->B, p->stream));
+  HIPCHK(aao::launch_finalize(sc, nblk, sc, 0, sc + aao::kScratchOut, p->stream));
+  double hn[2];
+  double hw[2 * aao::kScratchWBlocks];
+  HIPCHK(hipMemcpyAsync(hn, sc + aao::kScratchOut, sizeof hn, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipMemcpyAsync(hw, sc + aao::kScratchWParts, sizeof hw, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  double s2 = 0;
+  for (int i = 0; i < kNormBlocks; ++i) s2 += hw[2 * i];
+  if (!std::isfinite(s2)) return fail(AAO_ENAN, "u0 or the source contains NaN or Inf");
+  const double w2 = p->frc ? s2 : p->M * s2;
+  if (res_norm) *res_norm = std::sqrt(hn[0]) / std::sqrt(w2);
   return AAO_OK;
 }
 
