@@ -85,10 +85,10 @@ int ilog2(int64_t v) {
 #define AAO_XFORM_LDS_KB 24
 #endif
 #ifndef AAO_FFT_ROW_LDS_KB
-#define AAO_FFT_ROW_LDS_KB 32
+#define AAO_FFT_ROW_LDS_KB 40
 #endif
 #ifndef AAO_FFT_COL_LDS_KB
-#define AAO_FFT_COL_LDS_KB 32
+#define AAO_FFT_COL_LDS_KB 144
 #endif
 
 constexpr int kWorkSlots = 32;     // [class] for k > 0, [16 + class] for k == 0
@@ -671,6 +671,11 @@ aao_status inner_solve_fft(aao_plan* p, int adj, int nsys) {
   f.N = p->N;
   f.lognx = ilog2(p->nx);
   f.logny = ilog2(p->ny);
+  f.px2 = is_pow2(p->nx) ? 1 : 0;
+  f.py2 = is_pow2(p->ny) ? 1 : 0;
+  f.diag = 0;
+  for (int t = 0; t < f.taps.n; ++t)
+    if (f.taps.dx[t] != 0 && f.taps.dy[t] != 0) f.diag = 1;
   f.rows = p->fft_rows;
   f.cols = p->fft_cols;
   f.norm = (double)p->N;
@@ -1065,9 +1070,10 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   if (p->inner == AAO_INNER_FFT && p->ny > 1) {
     // rows (columns) per workgroup: a divisor of ny (nx) within the LDS budget
     const int cs = (int)p->csize;
-    const int lx = (int)fft_line(p->nx), ly = (int)fft_line(p->ny);
+    const int lx = aao::fft_pad_line((int)fft_line(p->nx)), ly = aao::fft_pad_line((int)fft_line(p->ny));
     p->fft_rows = largest_divisor(p->ny, AAO_FFT_ROW_LDS_KB * 1024 / (lx * cs));
-    p->fft_cols = largest_divisor(p->nx, AAO_FFT_COL_LDS_KB * 1024 / (ly * cs));
+    // columns: a cache line (128 B) of consecutive elements per row, within the LDS budget
+    p->fft_cols = largest_divisor(p->nx, std::min(128 / cs, AAO_FFT_COL_LDS_KB * 1024 / (ly * cs)));
   }
   {
     const int target = 4096;

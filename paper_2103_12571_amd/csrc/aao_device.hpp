@@ -172,30 +172,66 @@ template <> struct LdsCplx<float2> {
   __device__ void st(int i, float2 v) const { p[i] = v; }
 };
 
+// K consecutive radix-2 DIT stages s .. s+K-1 on the group of 2^K rows
+// i0 + t 2^s (t < 2^K; bits s .. s+K-1 of i0 clear, pos = i0 mod 2^s) of one
+// column, in registers.  Stage s+q pairs rows t and t + 2^q (bit q of t
+// clear) with twiddle index (pos + (t mod 2^q) 2^s) L / 2^(s+q+1).
+template <int K, bool INV>
+__device__ __forceinline__ void fft_group(double* re, double* im, const double* twr, const double* twi, int L,
+                                          int s, int i0, int pos, int ncol, int col) {
+  constexpr int R = 1 << K;
+  const int span = 1 << s;
+  double2 v[R];
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int o = (i0 + t * span) * ncol + col;
+    v[t] = mk(re[o], im[o]);
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int half = 1 << q;
+    const int tstride = L >> (s + q + 1);
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      if (t & half) continue;
+      const int ti = (pos + (t & (half - 1)) * span) * tstride;
+      const double2 w = mk(twr[ti], INV ? -twi[ti] : twi[ti]);
+      const double2 x0 = v[t];
+      const double2 x1 = cmul(w, v[t + half]);
+      v[t] = mk(x0.x + x1.x, x0.y + x1.y);
+      v[t + half] = mk(x0.x - x1.x, x0.y - x1.y);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int o = (i0 + t * span) * ncol + col;
+    re[o] = v[t].x;
+    im[o] = v[t].y;
+  }
+}
+
 // In-place radix-2 DIT FFT over the row index of the complex array c[L][ncol]
 // held as planes (re, im): bit-reversed input order, natural output order.
-// (twr, twi) = e^{-2 pi i k / L}, k < L/2; INV uses the conjugates.
+// (twr, twi) = e^{-2 pi i k / L}, k < L/2; INV uses the conjugates.  The
+// stages are taken three at a time in registers (groups of eight rows, one
+// barrier per three stages); every element sees the butterflies of the
+// stage-by-stage form in the same order, so the result is the same bit for bit.
 template <bool INV>
 __device__ __forceinline__ void lds_fft(double* re, double* im, const double* twr, const double* twi, int L,
                                         int logL, int ncol) {
-  for (int s = 0; s < logL; ++s) {
-    const int half = 1 << s;
-    const int tstride = L >> (s + 1);
+  for (int s = 0; s < logL; s += 3) {
+    const int k = min(3, logL - s);
+    const int span = 1 << s;
+    const int ngroups = (L >> k) * ncol;
     __syncthreads();
-    const int total = (L >> 1) * ncol;
-    for (int idx = threadIdx.x; idx < total; idx += kBlock) {
+    for (int idx = threadIdx.x; idx < ngroups; idx += kBlock) {
       const int col = idx % ncol;
-      const int k = idx / ncol;
-      const int pos = k & (half - 1);
-      const int i0 = ((k >> s) << (s + 1)) + pos;
-      const int o0 = i0 * ncol + col, o1 = o0 + half * ncol;
-      const double2 w = mk(twr[pos * tstride], INV ? -twi[pos * tstride] : twi[pos * tstride]);
-      const double2 x0 = mk(re[o0], im[o0]);
-      const double2 x1 = cmul(w, mk(re[o1], im[o1]));
-      re[o0] = x0.x + x1.x;
-      im[o0] = x0.y + x1.y;
-      re[o1] = x0.x - x1.x;
-      im[o1] = x0.y - x1.y;
+      const int g = idx / ncol;
+      const int pos = g & (span - 1);
+      const int i0 = ((g >> s) << (s + k)) + pos;
+      if (k == 3) fft_group<3, INV>(re, im, twr, twi, L, s, i0, pos, ncol, col);
+      else if (k == 2) fft_group<2, INV>(re, im, twr, twi, L, s, i0, pos, ncol, col);
+      else fft_group<1, INV>(re, im, twr, twi, L, s, i0, pos, ncol, col);
     }
   }
   __syncthreads();

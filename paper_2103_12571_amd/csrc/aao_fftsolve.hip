@@ -30,107 +30,206 @@ template <typename V> struct scal;
 template <> struct scal<double2> { using type = double; };
 template <> struct scal<float2> { using type = float; };
 
-// Element (b, i) of a batch of transforms lives at c[b * sb + i * se] (an LDS
-// complex array).  The table W holds e^{+2 pi i k / n}, k < n.
-template <typename V, bool INV, bool FASTB>
-__device__ __forceinline__ void fft_dit(const LdsCplx<V>& c, const double2* W, int n, int logn, int nb, int sb,
-                                        int se) {
+// LDS index of transform element i: one pad slot after every eight elements,
+// so that the eight-element groups of the first and last FFT passes (and
+// lines that sit a power of two apart) fall into different banks.
+__device__ __forceinline__ int padi(int i) { return i + (i >> 3); }
+
+// Radix-2 stages on a group of 2^K elements held in registers: element t is
+// transform element i0 + t 2^slo (bits slo .. slo+K-1 of i0 clear, pos0 =
+// i0 mod 2^slo).  DIT: stages slo .. slo+K-1 with butterflies (a, b) -> (a +
+// w b, a - w b); DIF: stages slo+K-1 down to slo with (a, d) -> (a + d,
+// (a - d) w).  Stage slo+q pairs t and t + 2^q (bit q of t clear) with
+// twiddle W[pos tstride], pos = pos0 + (t mod 2^q) 2^slo, tstride = n /
+// 2^(slo+q+1); the forward transform uses the conjugates of W = e^{+2 pi i k / n}.
+template <typename V, bool DIT, bool INV, int K>
+__device__ __forceinline__ void group_stages(V (&v)[1 << K], const double2* W, int n, int slo, int pos0) {
   using T = typename scal<V>::type;
-  const int half_n = n >> 1;
-  for (int s = 0; s < logn; ++s) {
-    const int half = 1 << s;
-    const int tstride = n >> (s + 1);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < nb * half_n; idx += kBlock) {
-      const int b = FASTB ? idx % nb : idx / half_n;
-      const int k = FASTB ? idx / nb : idx % half_n;
-      const int pos = k & (half - 1);
-      const int i0 = ((k >> s) << (s + 1)) + pos;
-      const double2 wd = W[pos * tstride];
+  constexpr int R = 1 << K;
+  const int span = 1 << slo;
+#pragma unroll
+  for (int qq = 0; qq < K; ++qq) {
+    const int q = DIT ? qq : K - 1 - qq;
+    const int half = 1 << q;
+    const int tstride = n >> (slo + q + 1);
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      if (t & half) continue;
+      const double2 wd = W[(pos0 + (t & (half - 1)) * span) * tstride];
       V w;
       w.x = (T)wd.x;
       w.y = INV ? (T)wd.y : (T)-wd.y;
-      const int o0 = b * sb + i0 * se, o1 = o0 + half * se;
-      const V a = c.ld(o0);
-      const V t = vmul(w, c.ld(o1));
-      c.st(o0, vadd(a, t));
-      c.st(o1, vsub(a, t));
+      const V a = v[t];
+      if (DIT) {
+        const V b = vmul(w, v[t + half]);
+        v[t] = vadd(a, b);
+        v[t + half] = vsub(a, b);
+      } else {
+        const V d = v[t + half];
+        v[t] = vadd(a, d);
+        v[t + half] = vmul(vsub(a, d), w);
+      }
+    }
+  }
+}
+
+// One pass of K stages over nb transforms of length n in LDS (element (b, i)
+// at b sb + padi(i) se), one group of 2^K elements per thread and trip.
+// MID: the group is also multiplied element-wise by mul(b, i) and taken back
+// through the same stages as DIF (the last forward pass, the divide and the
+// first inverse pass of a forward-divide-inverse solve in one trip).
+// FASTB: consecutive threads take consecutive transforms (b).
+template <typename V, bool DIT, bool INV, bool FASTB, int K, bool MID = false, typename Mul = int>
+__device__ __forceinline__ void fft_pass(const LdsCplx<V>& c, const double2* W, int n, int logn, int slo, int nb,
+                                         int sb, int se, int nth, const Mul& mul = 0) {
+  constexpr int R = 1 << K;
+  const int lng = logn - K;  // 2^lng groups per transform
+  const int span = 1 << slo;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < (nb << lng); idx += nth) {
+    const int b = FASTB ? idx % nb : idx >> lng;
+    const int g = FASTB ? idx / nb : idx & ((1 << lng) - 1);
+    const int pos0 = g & (span - 1);
+    const int i0 = ((g >> slo) << (slo + K)) + pos0;
+    const int base = b * sb;
+    V v[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) v[t] = c.ld(base + padi(i0 + t * span) * se);
+    if constexpr (MID) {
+      group_stages<V, true, false, K>(v, W, n, slo, pos0);
+#pragma unroll
+      for (int t = 0; t < R; ++t) v[t] = vmul(v[t], mul(b, i0 + t * span));
+      group_stages<V, false, true, K>(v, W, n, slo, pos0);
+    } else {
+      group_stages<V, DIT, INV, K>(v, W, n, slo, pos0);
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) c.st(base + padi(i0 + t * span) * se, v[t]);
+  }
+}
+
+template <typename V, bool DIT, bool INV, bool FASTB>
+__device__ __forceinline__ void fft_pass_k(const LdsCplx<V>& c, const double2* W, int n, int logn, int slo, int k,
+                                           int nb, int sb, int se, int nth) {
+  if (k == 3) fft_pass<V, DIT, INV, FASTB, 3>(c, W, n, logn, slo, nb, sb, se, nth);
+  else if (k == 2) fft_pass<V, DIT, INV, FASTB, 2>(c, W, n, logn, slo, nb, sb, se, nth);
+  else fft_pass<V, DIT, INV, FASTB, 1>(c, W, n, logn, slo, nb, sb, se, nth);
+}
+
+// Stage grouping: the forward (DIT) transform takes its partial pass first,
+// the inverse (DIF) last, so that the last forward pass and the first inverse
+// pass act on the same groups (stages logn-3 .. logn-1).
+__device__ __forceinline__ int dit_first_k(int logn) { return logn - 3 * ((logn - 1) / 3); }
+
+// nb radix-2 transforms of length n in LDS: DIT = decimation in time
+// (bit-reversed input, natural output), else decimation in frequency
+// (natural input, bit-reversed output).  The stages are taken up to three at
+// a time in registers: one barrier per pass.
+template <typename V, bool DIT, bool INV, bool FASTB>
+__device__ __forceinline__ void fft_lds(const LdsCplx<V>& c, const double2* W, int n, int logn, int nb, int sb,
+                                        int se, int nth) {
+  if (DIT) {
+    for (int slo = 0, k = dit_first_k(logn); slo < logn; slo += k, k = 3)
+      fft_pass_k<V, DIT, INV, FASTB>(c, W, n, logn, slo, k, nb, sb, se, nth);
+  } else {
+    for (int done = 0; done < logn;) {
+      const int k = min(3, logn - done);
+      fft_pass_k<V, DIT, INV, FASTB>(c, W, n, logn, logn - done - k, k, nb, sb, se, nth);
+      done += k;
     }
   }
   __syncthreads();
 }
 
-template <typename V, bool INV, bool FASTB>
-__device__ __forceinline__ void fft_dif(const LdsCplx<V>& c, const double2* W, int n, int logn, int nb, int sb,
-                                        int se) {
-  using T = typename scal<V>::type;
-  const int half_n = n >> 1;
-  for (int s = logn - 1; s >= 0; --s) {
-    const int half = 1 << s;
-    const int tstride = n >> (s + 1);
+// Forward transform (DIT, bit-reversed input), element-wise multiply by
+// mul(b, k) at frequency k, inverse transform (DIF, bit-reversed output), with
+// the last forward pass, the multiply and the first inverse pass in one trip.
+template <typename V, bool FASTB, typename Mul>
+__device__ __forceinline__ void fft_mul_ifft(const LdsCplx<V>& c, const double2* W, int n, int logn, int nb, int sb,
+                                             int se, int nth, const Mul& mul) {
+  const int km = min(3, logn);
+  const int sm = logn - km;  // the shared pass: stages sm .. logn-1
+  for (int slo = 0, k = dit_first_k(logn); slo < sm; slo += k, k = 3)
+    fft_pass_k<V, true, false, FASTB>(c, W, n, logn, slo, k, nb, sb, se, nth);
+  if (km == 3) fft_pass<V, true, false, FASTB, 3, true>(c, W, n, logn, sm, nb, sb, se, nth, mul);
+  else if (km == 2) fft_pass<V, true, false, FASTB, 2, true>(c, W, n, logn, sm, nb, sb, se, nth, mul);
+  else if (km == 1) fft_pass<V, true, false, FASTB, 1, true>(c, W, n, logn, sm, nb, sb, se, nth, mul);
+  else {  // n = 1: the transforms are the identity
     __syncthreads();
-    for (int idx = threadIdx.x; idx < nb * half_n; idx += kBlock) {
-      const int b = FASTB ? idx % nb : idx / half_n;
-      const int k = FASTB ? idx / nb : idx % half_n;
-      const int pos = k & (half - 1);
-      const int i0 = ((k >> s) << (s + 1)) + pos;
-      const double2 wd = W[pos * tstride];
-      V w;
-      w.x = (T)wd.x;
-      w.y = INV ? (T)wd.y : (T)-wd.y;
-      const int o0 = b * sb + i0 * se, o1 = o0 + half * se;
-      const V a = c.ld(o0);
-      const V d = c.ld(o1);
-      c.st(o0, vadd(a, d));
-      c.st(o1, vmul(vsub(a, d), w));
-    }
+    for (int b = threadIdx.x; b < nb; b += nth) c.st(b * sb, vmul(c.ld(b * sb), mul(b, 0)));
+  }
+  for (int done = km; done < logn;) {
+    const int k = min(3, logn - done);
+    fft_pass_k<V, false, true, FASTB>(c, W, n, logn, logn - done - k, k, nb, sb, se, nth);
+    done += k;
   }
   __syncthreads();
 }
 
-// 1 / ((1 - c lambda(kx, ky)) * nx * ny): the inverse transforms are unnormalised
-__device__ __forceinline__ double2 inv_symbol(const FftArgs& a, double2 c, int kx, int ky) {
+// (k d) mod n for a tap offset d in [-4, 4]
+__device__ __forceinline__ int tap_mod(int v, int n, int pow2) { return pow2 ? (v & (n - 1)) : ((v % n) + n) % n; }
+
+// The symbol lambda(kx, ky) = sum_t c_t e^{2 pi i (kx dx_t / nx + ky dy_t / ny)}
+// in three parts: taps along x (dy = 0), taps along y (dx = 0, dy != 0) and
+// the rest (both offsets nonzero; a.diag says whether there are any), so that
+// a column's x part is summed once.
+__device__ __forceinline__ double2 sym_x(const FftArgs& a, int kx) {
   double2 lam = mk(0, 0);
   for (int t = 0; t < a.taps.n; ++t) {
-    const int ix = ((kx * a.taps.dx[t]) % a.nx + a.nx) % a.nx;
-    const int iy = ((ky * a.taps.dy[t]) % a.ny + a.ny) % a.ny;
-    const double2 e = cmul(a.Wx[ix], a.Wy[iy]);
+    if (a.taps.dy[t] != 0) continue;
+    const double2 e = a.Wx[tap_mod(kx * a.taps.dx[t], a.nx, a.px2)];
     lam.x += a.taps.c[t] * e.x;
     lam.y += a.taps.c[t] * e.y;
   }
+  return lam;
+}
+__device__ __forceinline__ double2 sym_rest(const FftArgs& a, int kx, int ky) {
+  double2 lam = mk(0, 0);
+  for (int t = 0; t < a.taps.n; ++t) {
+    const int dx = a.taps.dx[t], dy = a.taps.dy[t];
+    if (dy == 0 || (dx != 0 && !a.diag)) continue;
+    double2 e = a.Wy[tap_mod(ky * dy, a.ny, a.py2)];
+    if (dx != 0) e = cmul(a.Wx[tap_mod(kx * dx, a.nx, a.px2)], e);
+    lam.x += a.taps.c[t] * e.x;
+    lam.y += a.taps.c[t] * e.y;
+  }
+  return lam;
+}
+// 1 / ((1 - c lambda) * nx * ny): the inverse transforms are unnormalised.
+__device__ __forceinline__ double2 inv_den(const FftArgs& a, double2 c, double2 lam) {
   const double2 den = mk((1.0 - (c.x * lam.x - c.y * lam.y)) * a.norm, (-(c.x * lam.y + c.y * lam.x)) * a.norm);
   return cdiv(mk(1, 0), den);
 }
+__device__ __forceinline__ double2 inv_symbol(const FftArgs& a, double2 c, int kx, int ky) {
+  return inv_den(a, c, cadd(sym_x(a, kx), sym_rest(a, kx, ky)));
+}
 
 // Bluestein convolution of nb sequences of length P held in c (element (b, i)
-// at b * sb + i * se) at bit-reversed positions: forward radix-2 transform,
-// multiply by the filter's transform F, inverse radix-2 transform.  Leaves P
-// times the cyclic convolution, again at bit-reversed positions.
+// at b * sb + padi(i) * se) at bit-reversed positions: forward radix-2
+// transform, multiply by the filter's transform F, inverse radix-2 transform.
+// Leaves P times the cyclic convolution, again at bit-reversed positions.
 template <typename V, bool FASTB>
 __device__ __forceinline__ void blue_conv(const LdsCplx<V>& c, const BlueDim& d, const double2* F, int nb, int sb,
-                                          int se) {
-  fft_dit<V, false, FASTB>(c, d.W, d.P, d.logP, nb, sb, se);
-  for (int idx = threadIdx.x; idx < nb * d.P; idx += kBlock) {
-    const int b = FASTB ? idx % nb : idx >> d.logP;
-    const int k = FASTB ? idx / nb : idx & (d.P - 1);
-    const int o = b * sb + k * se;
-    c.st(o, vmul(c.ld(o), from_d2<V>(F[k])));
-  }
-  fft_dif<V, true, FASTB>(c, d.W, d.P, d.logP, nb, sb, se);
+                                          int se, int nth) {
+  fft_mul_ifft<V, FASTB>(c, d.W, d.P, d.logP, nb, sb, se, nth, [&](int, int k) { return from_d2<V>(F[k]); });
 }
 
 __device__ __forceinline__ double2 cscale(double2 v, double s) { return mk(v.x * s, v.y * s); }
-__device__ __forceinline__ double2 cconj(double2 v) { return mk(v.x, -v.y); }
+
+// Threads of the column kernel: one per group of eight elements of the
+// tile (cols x line), at least 64 and at most 1024 (launch_fft_solve).
 
 // Rows: MODE 0 forward (in place), MODE 1 inverse (R -> X), MODE 2 forward,
-// divide and inverse (1D, R -> X).  grid (ny / rows, nsys).  BLUE: nx is
-// transformed through length-P convolutions (LDS rows of P).
+// divide and inverse (1D, R -> X).  grid (ny / rows, nsys).  Row r of the
+// tile starts at r * padi(line) in LDS.  BLUE: nx is transformed through
+// length-P convolutions.
 template <typename V, int MODE, bool BLUE>
 __global__ __launch_bounds__(kBlock) void k_fft_rows(FftArgs a) {
   extern __shared__ char smem[];
   const int s = blockIdx.y;
   const int nx = a.nx, rows = a.rows;
-  const LdsCplx<V> c(smem, rows * (BLUE ? a.bx.P : nx));
+  const int ls = padi(BLUE ? a.bx.P : nx);
+  const LdsCplx<V> c(smem, rows * ls);
   int grp = blockIdx.x;
   if ((gridDim.x & 7) == 0) grp = (grp & 7) * (gridDim.x >> 3) + (grp >> 3);
   const int y0 = grp * rows;
@@ -145,59 +244,54 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(FftArgs a) {
       const int r = i >> logP, j = i & (P - 1);
       V v = vzero<V>();
       if (j < nx) v = vmul(in[r * nx + j], from_d2<V>(MODE == 1 ? cconj(d.ch[j]) : d.ch[j]));
-      c.st(r * P + dev::bitrev(j, logP), v);
+      c.st(r * ls + padi(dev::bitrev(j, logP)), v);
     }
-    blue_conv<V, false>(c, d, MODE == 1 ? d.Bi : d.Bf, rows, P, 1);
+    blue_conv<V, false>(c, d, MODE == 1 ? d.Bi : d.Bf, rows, ls, 1, kBlock);
     if (MODE == 2) {
       const double2 sh = a.shift[s];
       for (int k = threadIdx.x; k < P; k += kBlock) {
-        const int o = dev::bitrev(k, logP);
+        const int o = padi(dev::bitrev(k, logP));
         c.st(o, k < nx ? vmul(c.ld(o), from_d2<V>(cscale(inv_symbol(a, sh, k, 0), invP))) : vzero<V>());
       }
-      blue_conv<V, false>(c, d, d.Bi, 1, P, 1);
+      blue_conv<V, false>(c, d, d.Bi, 1, ls, 1, kBlock);
     }
     for (int i = threadIdx.x; i < tot; i += kBlock) {
       const int r = i / nx, k = i - r * nx;
       const double2 chk = cscale(MODE == 0 ? d.ch[k] : cconj(d.ch[k]), invP);
-      out[i] = vmul(c.ld(r * P + dev::bitrev(k, logP)), from_d2<V>(chk));
+      out[i] = vmul(c.ld(r * ls + padi(dev::bitrev(k, logP))), from_d2<V>(chk));
     }
     return;
   }
   for (int i = threadIdx.x; i < tot; i += kBlock) {
     const int r = i / nx, x = i - r * nx;
-    const int dst = (MODE == 1) ? i : r * nx + dev::bitrev(x, a.lognx);
-    c.st(dst, in[i]);
+    c.st(r * ls + padi(MODE == 1 ? x : dev::bitrev(x, a.lognx)), in[i]);
   }
   if (MODE == 1) {
-    fft_dif<V, true, false>(c, a.Wx, nx, a.lognx, rows, nx, 1);
+    fft_lds<V, false, true, false>(c, a.Wx, nx, a.lognx, rows, ls, 1, kBlock);
+  } else if (MODE == 0) {
+    fft_lds<V, true, false, false>(c, a.Wx, nx, a.lognx, rows, ls, 1, kBlock);
   } else {
-    fft_dit<V, false, false>(c, a.Wx, nx, a.lognx, rows, nx, 1);
-  }
-  if (MODE == 2) {
     const double2 sh = a.shift[s];
-    for (int i = threadIdx.x; i < nx; i += kBlock) {
-      const double2 f = inv_symbol(a, sh, i, 0);
-      const V fv = from_d2<V>(f);
-      c.st(i, vmul(c.ld(i), fv));
-    }
-    fft_dif<V, true, false>(c, a.Wx, nx, a.lognx, 1, nx, 1);
+    fft_mul_ifft<V, false>(c, a.Wx, nx, a.lognx, rows, ls, 1, kBlock,
+                           [&](int, int k) { return from_d2<V>(inv_symbol(a, sh, k, 0)); });
   }
   for (int i = threadIdx.x; i < tot; i += kBlock) {
     const int r = i / nx, x = i - r * nx;
-    const int src = (MODE == 0) ? i : r * nx + dev::bitrev(x, a.lognx);
-    out[i] = c.ld(src);
+    out[i] = c.ld(r * ls + padi(MODE == 0 ? x : dev::bitrev(x, a.lognx)));
   }
 }
 
 // Columns: forward along y, divide, inverse along y, in place on R.
-// grid (nx / cols, nsys); LDS c[y][col].  BLUE: ny through length-P
-// convolutions (LDS c[P][col]).
+// grid (nx / cols, nsys); column col, row y at col + padi(y) cols in LDS (a
+// cache line of cols consecutive elements per row).  BLUE: ny through
+// length-P convolutions.
 template <typename V, bool BLUE>
-__global__ __launch_bounds__(kBlock) void k_fft_cols(FftArgs a) {
+__global__ __launch_bounds__(1024) void k_fft_cols(FftArgs a) {
+  const int CB = blockDim.x;
   extern __shared__ char smem[];
   const int s = blockIdx.y;
   const int nx = a.nx, ny = a.ny, cols = a.cols;
-  const LdsCplx<V> c(smem, (BLUE ? a.by.P : ny) * cols);
+  const LdsCplx<V> c(smem, padi(BLUE ? a.by.P : ny) * cols);
   int grp = blockIdx.x;  // XCD-banded: neighbouring column groups share cache lines
   if ((gridDim.x & 7) == 0) grp = (grp & 7) * (gridDim.x >> 3) + (grp >> 3);
   const int x0 = grp * cols;
@@ -207,41 +301,48 @@ __global__ __launch_bounds__(kBlock) void k_fft_cols(FftArgs a) {
     const BlueDim& d = a.by;
     const int P = d.P, logP = d.logP;
     const double invP = 1.0 / P;
-    for (int i = threadIdx.x; i < P * cols; i += kBlock) {
+    for (int i = threadIdx.x; i < P * cols; i += CB) {
       const int j = i / cols, col = i - j * cols;
-      c.st(dev::bitrev(j, logP) * cols + col,
+      c.st(padi(dev::bitrev(j, logP)) * cols + col,
            j < ny ? vmul(base[(size_t)j * nx + col], from_d2<V>(d.ch[j])) : vzero<V>());
     }
-    blue_conv<V, true>(c, d, d.Bf, cols, 1, cols);
+    blue_conv<V, true>(c, d, d.Bf, cols, 1, cols, CB);
     const double2 sh = a.shift[s];
-    for (int i = threadIdx.x; i < P * cols; i += kBlock) {
+    for (int i = threadIdx.x; i < P * cols; i += CB) {
       const int k = i / cols, col = i - k * cols;
-      const int o = dev::bitrev(k, logP) * cols + col;
+      const int o = padi(dev::bitrev(k, logP)) * cols + col;
       c.st(o, k < ny ? vmul(c.ld(o), from_d2<V>(cscale(inv_symbol(a, sh, x0 + col, k), invP))) : vzero<V>());
     }
-    blue_conv<V, true>(c, d, d.Bi, cols, 1, cols);
-    for (int i = threadIdx.x; i < tot; i += kBlock) {
+    blue_conv<V, true>(c, d, d.Bi, cols, 1, cols, CB);
+    for (int i = threadIdx.x; i < tot; i += CB) {
       const int k = i / cols, col = i - k * cols;
       base[(size_t)k * nx + col] =
-          vmul(c.ld(dev::bitrev(k, logP) * cols + col), from_d2<V>(cscale(cconj(d.ch[k]), invP)));
+          vmul(c.ld(padi(dev::bitrev(k, logP)) * cols + col), from_d2<V>(cscale(cconj(d.ch[k]), invP)));
     }
     return;
   }
-  for (int i = threadIdx.x; i < tot; i += kBlock) {
+  for (int i = threadIdx.x; i < tot; i += CB) {
     const int y = i / cols, col = i - y * cols;
-    c.st(dev::bitrev(y, a.logny) * cols + col, base[(size_t)y * nx + col]);
+    c.st(padi(dev::bitrev(y, a.logny)) * cols + col, base[(size_t)y * nx + col]);
   }
-  fft_dit<V, false, true>(c, a.Wy, ny, a.logny, cols, 1, cols);
   const double2 sh = a.shift[s];
-  for (int i = threadIdx.x; i < tot; i += kBlock) {
+  // forward, divide, inverse; the divide in a pass of its own (in the last
+  // forward pass it would hold the group's registers through the symbol
+  // evaluation).  When the block size is a multiple of cols every trip of a
+  // thread is on the same column: its x part is summed once.
+  fft_lds<V, true, false, true>(c, a.Wy, ny, a.logny, cols, 1, cols, CB);
+  const bool same_col = (CB % cols) == 0;
+  const double2 lx = sym_x(a, x0 + threadIdx.x % cols);
+  for (int i = threadIdx.x; i < tot; i += CB) {
     const int y = i / cols, col = i - y * cols;
-    const V fv = from_d2<V>(inv_symbol(a, sh, x0 + col, y));
-    c.st(i, vmul(c.ld(i), fv));
+    const int o = padi(y) * cols + col;
+    const double2 f = inv_den(a, sh, cadd(same_col ? lx : sym_x(a, x0 + col), sym_rest(a, x0 + col, y)));
+    c.st(o, vmul(c.ld(o), from_d2<V>(f)));
   }
-  fft_dif<V, true, true>(c, a.Wy, ny, a.logny, cols, 1, cols);
-  for (int i = threadIdx.x; i < tot; i += kBlock) {
+  fft_lds<V, false, true, true>(c, a.Wy, ny, a.logny, cols, 1, cols, CB);
+  for (int i = threadIdx.x; i < tot; i += CB) {
     const int y = i / cols, col = i - y * cols;
-    base[(size_t)y * nx + col] = c.ld(dev::bitrev(y, a.logny) * cols + col);
+    base[(size_t)y * nx + col] = c.ld(padi(dev::bitrev(y, a.logny)) * cols + col);
   }
 }
 
@@ -250,16 +351,17 @@ __global__ __launch_bounds__(kBlock) void k_fft_cols(FftArgs a) {
 hipError_t launch_fft_solve(bool f32, const FftArgs& a, int nsys, hipStream_t st) {
   auto lbytes = [&](int n) { return f32 ? LdsCplx<float2>::bytes(n) : LdsCplx<double2>::bytes(n); };
   const bool bx = a.bx.P > 0, by = a.by.P > 0;
-  const int lx = bx ? a.bx.P : a.nx, ly = by ? a.by.P : a.ny;
+  // padded line lengths (padi of the line)
+  const int lx = fft_pad_line(bx ? a.bx.P : a.nx), ly = fft_pad_line(by ? a.by.P : a.ny);
 #define AAO_ROWS(V, MODE, grid, lds)                                                          \
   do {                                                                                         \
     if (bx) hipLaunchKernelGGL((k_fft_rows<V, MODE, true>), grid, dim3(kBlock), lds, st, a);   \
     else hipLaunchKernelGGL((k_fft_rows<V, MODE, false>), grid, dim3(kBlock), lds, st, a);     \
   } while (0)
-#define AAO_COLS(V, grid, lds)                                                           \
-  do {                                                                                    \
-    if (by) hipLaunchKernelGGL((k_fft_cols<V, true>), grid, dim3(kBlock), lds, st, a);    \
-    else hipLaunchKernelGGL((k_fft_cols<V, false>), grid, dim3(kBlock), lds, st, a);      \
+#define AAO_COLS(V, grid, lds)                                                              \
+  do {                                                                                       \
+    if (by) hipLaunchKernelGGL((k_fft_cols<V, true>), grid, dim3(cthreads), lds, st, a);    \
+    else hipLaunchKernelGGL((k_fft_cols<V, false>), grid, dim3(cthreads), lds, st, a);      \
   } while (0)
   if (a.ny == 1) {
     dim3 grid(1, nsys);
@@ -271,6 +373,8 @@ hipError_t launch_fft_solve(bool f32, const FftArgs& a, int nsys, hipStream_t st
   if (a.rows < 1 || a.cols < 1 || a.ny % a.rows != 0 || a.nx % a.cols != 0) return hipErrorInvalidValue;
   dim3 grow(a.ny / a.rows, nsys), gcol(a.nx / a.cols, nsys);
   const size_t lrow = lbytes(a.rows * lx), lcol = lbytes(a.cols * ly);
+  int cthreads = 64;  // one thread per group of eight tile elements, a multiple of 64
+  while (cthreads < 1024 && cthreads * 8 < a.cols * (by ? a.by.P : a.ny)) cthreads *= 2;
   if (f32) {
     AAO_ROWS(float2, 0, grow, lrow);
     AAO_COLS(float2, gcol, lcol);

@@ -173,6 +173,8 @@ struct FftArgs {
   const double2* Wy;      // e^{+2 pi i k / ny}, k < ny
   Taps taps;
   int nx, ny, N, lognx, logny;
+  int px2, py2;           // nx / ny is a power of two
+  int diag;               // some tap has both offsets nonzero
   int rows, cols;         // rows / columns per workgroup in the 2D passes (divide ny / nx)
   double norm;            // nx * ny
   BlueDim bx, by;         // Bluestein data of x / y (P = 0 where n is a power of two)
@@ -237,6 +239,8 @@ hipError_t launch_krylov_init(const KrylovArgs& a, hipStream_t st, int* list = n
 bool bicg_wg_fits(int N);
 hipError_t launch_bicg_wg(bool f32, const KrylovArgs& a, int nsys, hipStream_t st);
 hipError_t launch_fft_solve(bool f32, const FftArgs& a, int nsys, hipStream_t st);
+// LDS slots of one transform line of n elements (one pad slot per eight).
+inline int fft_pad_line(int n) { return n + (n >> 3); }
 hipError_t launch_compact_active(const SysState* st, int n, int* list, int* count_tag, int tag, hipStream_t s);
 hipError_t launch_copy_c128_in(void* dst, bool f32, const double* src, int64_t n, hipStream_t st);
 hipError_t launch_copy_c128_out(double* dst, const void* src, bool f32, int64_t n,
