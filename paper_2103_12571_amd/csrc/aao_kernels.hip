@@ -717,14 +717,20 @@ __global__ __launch_bounds__(kBlock) void k_bicg3(KrylovArgs a, int k) {
 // block-wide sums in place of the chunk partial sums.  One launch runs every
 // iteration of every system, one workgroup each; nothing is shared between
 // workgroups, and each loop ends at the iteration cap at the latest.
-// complex128 takes 1024 threads (four points each), accumulates x in memory
+// complex128 takes 512 threads (eight points each), accumulates x in memory
 // (read and written once per iteration by its owner thread) and keeps v in a
-// second LDS array (each thread touches only its own points there): its
-// registers still spill (31 VGPRs; 85 with x and v in registers, more with
-// 512 x 8).  complex64 takes 512 threads (eight points, x and v in
-// registers, no spills).
+// second LDS array (each thread touches only its own points there); with
+// half the waves of a 1024 x 4 shape the block sums cost half the
+// instructions per point (the kernel is bound by instruction issue).
+// complex64 takes 512 threads too (x and v in registers, no spills).
 constexpr int kWgCap = 4096;
-template <typename T> struct WgShape { static constexpr int BLK = 1024; };
+#ifndef AAO_BICG_WG_F64_BLK
+#define AAO_BICG_WG_F64_BLK 512
+#endif
+#ifndef AAO_BICG_WG_F64_XMEM
+#define AAO_BICG_WG_F64_XMEM 1
+#endif
+template <typename T> struct WgShape { static constexpr int BLK = AAO_BICG_WG_F64_BLK; };
 template <> struct WgShape<float> { static constexpr int BLK = 512; };
 
 // Sum of K values over the BLK threads in a fixed order; every thread gets
@@ -745,11 +751,23 @@ __device__ __forceinline__ void wg_sum(double (&v)[K], double* sh) {
     for (int i = 0; i < K; ++i) sh[wid * K + i] = v[i];
   }
   __syncthreads();
+  if constexpr (NW <= 8) {  // few wave sums: every lane adds them in order (broadcast reads)
 #pragma unroll
-  for (int i = 0; i < K; ++i) v[i] = wave_sum(lane < NW ? sh[lane * K + i] : 0.0);
+    for (int i = 0; i < K; ++i) {
+      double acc = sh[i];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) acc += sh[w * K + i];
+      v[i] = acc;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < K; ++i) v[i] = wave_sum(lane < NW ? sh[lane * K + i] : 0.0);
+  }
 }
 
-template <typename T>
+// FAST: a 1D system of exactly kWgCap points (every owned point exists and a
+// neighbour index is one add and one mask).
+template <typename T, bool FAST>
 __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
   using V = typename cvec<T>::type;
   constexpr int kWgBlock = WgShape<T>::BLK;
@@ -784,7 +802,7 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
 #pragma unroll
     for (int j = 0; j < kWgPts; ++j) {
       const int n = t0 + j * kWgBlock;
-      if (n < N) W.st(n, in[j]);
+      if (FAST || n < N) W.st(n, in[j]);
     }
     __syncthreads();
 #pragma unroll
@@ -796,7 +814,8 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
 #pragma unroll
       for (int j = 0; j < kWgPts; ++j) {
         const int n = t0 + j * kWgBlock;
-        if (n < N) out[j] = vadd(out[j], vscale(W.ld(wrap_index(xy[j] & 0xffff, xy[j] >> 16, dx, dy, a.g)), c));
+        const int nb = FAST ? ((n + dx) & (kWgCap - 1)) : wrap_index(xy[j] & 0xffff, xy[j] >> 16, dx, dy, a.g);
+        if (FAST || n < N) out[j] = vadd(out[j], vscale(W.ld(nb), c));
       }
     }
 #pragma unroll
@@ -808,15 +827,15 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
   };
   auto rhat = [&](int j) {
     const int n = t0 + j * kWgBlock;
-    return (n < N) ? B[n] : vzero<V>();
+    return (FAST || n < N) ? B[n] : vzero<V>();
   };
-  constexpr bool kXMem = sizeof(T) == sizeof(double);
+  constexpr bool kXMem = sizeof(T) == sizeof(double) && AAO_BICG_WG_F64_XMEM;
   V r[kWgPts], p[kWgPts], v[kXMem ? 1 : kWgPts], x[kXMem ? 1 : kWgPts];
   const LdsCplx<V> Vl(reinterpret_cast<char*>(wg_lds) + LdsCplx<V>::bytes(N), N);  // v (complex128)
   auto vget = [&](int j) -> V {
     if constexpr (kXMem) {
       const int n = t0 + j * kWgBlock;
-      return (n < N) ? Vl.ld(n) : vzero<V>();
+      return (FAST || n < N) ? Vl.ld(n) : vzero<V>();
     } else {
       return v[j];
     }
@@ -826,7 +845,7 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
     for (int j = 0; j < kWgPts; ++j) {
       if constexpr (kXMem) {
         const int n = t0 + j * kWgBlock;
-        if (n < N) Vl.st(n, o[j]);
+        if (FAST || n < N) Vl.st(n, o[j]);
       } else {
         v[j] = o[j];
       }
@@ -910,7 +929,7 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
       const V inc = vadd(vmul(av, p[j]), vmul(ov, r[j]));
       if (kXMem) {
         const int n = t0 + j * kWgBlock;
-        if (n < N) X[n] = (k == 0) ? inc : vadd(X[n], inc);
+        if (FAST || n < N) X[n] = (k == 0) ? inc : vadd(X[n], inc);
       } else {
         x[j] = (k == 0) ? inc : vadd(x[j], inc);
       }
@@ -924,7 +943,7 @@ __global__ __launch_bounds__(WgShape<T>::BLK) void k_bicg_wg(KrylovArgs a) {
 #pragma unroll
   for (int j = 0; j < kWgPts; ++j) {
     const int n = t0 + j * kWgBlock;
-    if (n < N) {
+    if (FAST || n < N) {
       if (!kXMem) X[n] = x[j];
       Rout[n] = r[j];
     }
@@ -1230,11 +1249,15 @@ bool bicg_wg_fits(int N) { return N >= 1 && N <= kWgCap; }
 
 hipError_t launch_bicg_wg(bool f32, const KrylovArgs& a, int nsys, hipStream_t st) {
   if (!bicg_wg_fits(a.g.N) || nsys < 1) return hipErrorInvalidValue;
-  if (f32)
-    hipLaunchKernelGGL(k_bicg_wg<float>, dim3(nsys), dim3(WgShape<float>::BLK), LdsCplx<float2>::bytes(a.g.N), st, a);
-  else
-    hipLaunchKernelGGL(k_bicg_wg<double>, dim3(nsys), dim3(WgShape<double>::BLK), 2 * LdsCplx<double2>::bytes(a.g.N),
-                       st, a);  // the stencil's input and v
+  const bool fast = a.g.ny == 1 && a.g.N == kWgCap;
+  const size_t l32 = LdsCplx<float2>::bytes(a.g.N), l64 = 2 * LdsCplx<double2>::bytes(a.g.N);  // f64: input, v
+  if (f32) {
+    if (fast) hipLaunchKernelGGL((k_bicg_wg<float, true>), dim3(nsys), dim3(WgShape<float>::BLK), l32, st, a);
+    else hipLaunchKernelGGL((k_bicg_wg<float, false>), dim3(nsys), dim3(WgShape<float>::BLK), l32, st, a);
+  } else {
+    if (fast) hipLaunchKernelGGL((k_bicg_wg<double, true>), dim3(nsys), dim3(WgShape<double>::BLK), l64, st, a);
+    else hipLaunchKernelGGL((k_bicg_wg<double, false>), dim3(nsys), dim3(WgShape<double>::BLK), l64, st, a);
+  }
   return hipGetLastError();
 }
 
