@@ -213,8 +213,12 @@ def initial_batch(w):
     return np.stack([initial_condition(w, b) for b in range(w.batch)])
 
 
-def target_batch(w):
-    """u_target for the adjoint loss: a seeded Fourier-mode field per instance."""
+def target_initial_batch(w):
+    """u0* per instance (seeded Fourier modes, seed target_seed + b).  The
+    adjoint loss's u_target is the final value of the same collocation
+    problem started from u0* at the workload's nu (synthetic observations of
+    the model); each side computes it with its own solver, and it is held
+    fixed when nu varies."""
     return np.stack([fourier_modes(w.nx, w.ny, w.target_seed + b) for b in range(w.batch)])
 
 

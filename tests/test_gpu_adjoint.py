@@ -59,15 +59,20 @@ def test_gradients_vs_oracle_and_fd(prec, tol):
                                                  tol=1e-12 if prec == "fp64" else 1e-9)
     say("gradients", prec)
     u0 = wl.initial_batch(w)
-    ut = wl.target_batch(w)
+    us = wl.target_initial_batch(w)
+    # u_target: the model's final value from u0* at the workload's nu, each side with its own solver
+    pt = plan_for(w)
+    pt.set_u0(dev(us))
+    ut_gpu = pt.solve(tol=w.tol, max_iter=50)[0][:, -1, -1, :].clone()
+    op, Q = _setup(w)
+    ut = np.stack([oracle.sequential_solve(op, Q, w.dt, us[b], w.L)[-1, -1] for b in range(w.batch)])
     u0_t = dev(u0).requires_grad_(True)
     nu_t = torch.tensor(w.nu, dtype=torch.float64, device="cuda", requires_grad=True)
     uT = solve_uT(u0_t, nu_t, w, tol=w.tol, adj_tol=w.tol)
-    loss = 0.5 * ((uT - dev(ut)) ** 2).sum()
+    loss = 0.5 * ((uT - ut_gpu) ** 2).sum()
     loss.backward()
     gu0 = host(u0_t.grad)
     gnu = float(nu_t.grad)
-    op, Q = _setup(w)
     gnu_o = 0.0
     for b in range(w.batch):
         U = oracle.sequential_solve(op, Q, w.dt, u0[b], w.L)
