@@ -88,7 +88,10 @@ int ilog2(int64_t v) {
 #define AAO_FFT_ROW_LDS_KB 40
 #endif
 #ifndef AAO_FFT_COL_LDS_KB
-#define AAO_FFT_COL_LDS_KB 144
+#define AAO_FFT_COL_LDS_KB 72
+#endif
+#ifndef AAO_FFT_COL_SEG_BYTES
+#define AAO_FFT_COL_SEG_BYTES 128
 #endif
 
 constexpr int kWorkSlots = 32;     // [class] for k > 0, [16 + class] for k == 0
@@ -1072,8 +1075,8 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
     const int cs = (int)p->csize;
     const int lx = aao::fft_pad_line((int)fft_line(p->nx)), ly = aao::fft_pad_line((int)fft_line(p->ny));
     p->fft_rows = largest_divisor(p->ny, AAO_FFT_ROW_LDS_KB * 1024 / (lx * cs));
-    // columns: a cache line (128 B) of consecutive elements per row, within the LDS budget
-    p->fft_cols = largest_divisor(p->nx, std::min(128 / cs, AAO_FFT_COL_LDS_KB * 1024 / (ly * cs)));
+    // columns: up to AAO_FFT_COL_SEG_BYTES of consecutive elements per row, within the LDS budget
+    p->fft_cols = largest_divisor(p->nx, std::min(AAO_FFT_COL_SEG_BYTES / cs, AAO_FFT_COL_LDS_KB * 1024 / (ly * cs)));
   }
   {
     const int target = 4096;

@@ -216,6 +216,16 @@ __device__ __forceinline__ void blue_conv(const LdsCplx<V>& c, const BlueDim& d,
 
 __device__ __forceinline__ double2 cscale(double2 v, double s) { return mk(v.x * s, v.y * s); }
 
+// The first n/2 twiddles e^{+2 pi i k / n} (all a transform of length n
+// reads) copied to LDS after the data (byte offset `off`, 16-byte aligned);
+// the passes read them from there.  The copy is ordered before the first
+// read by the barrier that opens every pass.
+__device__ __forceinline__ const double2* lds_twiddles(char* smem, size_t off, const double2* W, int n, int nth) {
+  double2* tw = reinterpret_cast<double2*>(smem + off);
+  for (int k = threadIdx.x; k < (n >> 1); k += nth) tw[k] = W[k];
+  return tw;
+}
+
 // Threads of the column kernel: one per group of eight elements of the
 // tile (cols x line), at least 64 and at most 1024 (launch_fft_solve).
 
@@ -266,10 +276,11 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(FftArgs a) {
     const int r = i / nx, x = i - r * nx;
     c.st(r * ls + padi(MODE == 1 ? x : dev::bitrev(x, a.lognx)), in[i]);
   }
+  const double2* twx = lds_twiddles(smem, fft_tw_offset(sizeof(V), rows * ls), a.Wx, nx, kBlock);
   if (MODE == 1) {
-    fft_lds<V, false, true, false>(c, a.Wx, nx, a.lognx, rows, ls, 1, kBlock);
+    fft_lds<V, false, true, false>(c, twx, nx, a.lognx, rows, ls, 1, kBlock);
   } else if (MODE == 0) {
-    fft_lds<V, true, false, false>(c, a.Wx, nx, a.lognx, rows, ls, 1, kBlock);
+    fft_lds<V, true, false, false>(c, twx, nx, a.lognx, rows, ls, 1, kBlock);
   } else {
     const double2 sh = a.shift[s];
     fft_mul_ifft<V, false>(c, a.Wx, nx, a.lognx, rows, ls, 1, kBlock,
@@ -325,12 +336,13 @@ __global__ __launch_bounds__(1024) void k_fft_cols(FftArgs a) {
     const int y = i / cols, col = i - y * cols;
     c.st(padi(dev::bitrev(y, a.logny)) * cols + col, base[(size_t)y * nx + col]);
   }
+  const double2* twy = lds_twiddles(smem, fft_tw_offset(sizeof(V), padi(ny) * cols), a.Wy, ny, CB);
   const double2 sh = a.shift[s];
   // forward, divide, inverse; the divide in a pass of its own (in the last
   // forward pass it would hold the group's registers through the symbol
   // evaluation).  When the block size is a multiple of cols every trip of a
   // thread is on the same column: its x part is summed once.
-  fft_lds<V, true, false, true>(c, a.Wy, ny, a.logny, cols, 1, cols, CB);
+  fft_lds<V, true, false, true>(c, twy, ny, a.logny, cols, 1, cols, CB);
   const bool same_col = (CB % cols) == 0;
   const double2 lx = sym_x(a, x0 + threadIdx.x % cols);
   for (int i = threadIdx.x; i < tot; i += CB) {
@@ -339,7 +351,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(FftArgs a) {
     const double2 f = inv_den(a, sh, cadd(same_col ? lx : sym_x(a, x0 + col), sym_rest(a, x0 + col, y)));
     c.st(o, vmul(c.ld(o), from_d2<V>(f)));
   }
-  fft_lds<V, false, true, true>(c, a.Wy, ny, a.logny, cols, 1, cols, CB);
+  fft_lds<V, false, true, true>(c, twy, ny, a.logny, cols, 1, cols, CB);
   for (int i = threadIdx.x; i < tot; i += CB) {
     const int y = i / cols, col = i - y * cols;
     base[(size_t)y * nx + col] = c.ld(padi(dev::bitrev(y, a.logny)) * cols + col);
@@ -372,7 +384,9 @@ hipError_t launch_fft_solve(bool f32, const FftArgs& a, int nsys, hipStream_t st
   }
   if (a.rows < 1 || a.cols < 1 || a.ny % a.rows != 0 || a.nx % a.cols != 0) return hipErrorInvalidValue;
   dim3 grow(a.ny / a.rows, nsys), gcol(a.nx / a.cols, nsys);
-  const size_t lrow = lbytes(a.rows * lx), lcol = lbytes(a.cols * ly);
+  // non-Bluestein lines also hold their twiddle table in LDS
+  const size_t lrow = bx ? lbytes(a.rows * lx) : fft_tw_offset(f32 ? 8 : 16, a.rows * lx) + (size_t)(a.nx / 2) * 16;
+  const size_t lcol = by ? lbytes(a.cols * ly) : fft_tw_offset(f32 ? 8 : 16, a.cols * ly) + (size_t)(a.ny / 2) * 16;
   int cthreads = 64;  // one thread per group of eight tile elements, a multiple of 64
   while (cthreads < 1024 && cthreads * 8 < a.cols * (by ? a.by.P : a.ny)) cthreads *= 2;
   if (f32) {
