@@ -60,7 +60,10 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
   double* dst = ((nl & 1) ? cim : cre) + (nl >> 1);
 
   double res2 = 0.0;
-#pragma unroll 2
+#ifndef AAO_FWD_ROW_UNROLL
+#define AAO_FWD_ROW_UNROLL 2
+#endif
+#pragma unroll AAO_FWD_ROW_UNROLL
   for (int l = threadIdx.x >> a.logTN; l < L; l += (kBlock >> a.logTN)) {
     double rv[M];
 #pragma unroll
@@ -132,9 +135,9 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
 
   OutV* out = reinterpret_cast<OutV*>(a.out);
   const int logP = a.logTN - 1;
-  for (int idx = threadIdx.x; idx < a.Lh * P; idx += kBlock) {
-    const int j = idx >> logP;
-    const int p = idx & (P - 1);
+  // frequencies 0 and L/2 (both self-conjugate) share an item, so that the
+  // (L/2) P items fill the block once (L TN = 1024 within the LDS budget)
+  auto emit = [&](int j, int p) {
     const int jm = (L - j) & (L - 1);
     double2 A[M], Bv[M];
 #pragma unroll
@@ -164,6 +167,12 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
       if (n < N) out[o] = from_d2<OutV>(xa);
       if (n + 1 < N) out[o + 1] = from_d2<OutV>(xb);
     }
+  };
+  for (int idx = threadIdx.x; idx < max(L >> 1, 1) * P; idx += kBlock) {
+    const int j = idx >> logP;
+    const int p = idx & (P - 1);
+    emit(j, p);
+    if (j == 0 && L > 1) emit(L >> 1, p);
   }
   if (MODE == 0) {
     double v[1] = {res2};
@@ -257,9 +266,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd(BwdArgs a) {
   const InV* in = reinterpret_cast<const InV*>(a.in);
 
   const int logP = a.logTN - 1;
-  for (int idx = threadIdx.x; idx < a.Lh * P; idx += kBlock) {
-    const int j = idx >> logP;
-    const int p = idx & (P - 1);
+  // as in k_fwd, frequencies 0 and L/2 share an item
+  auto take = [&](int j, int p) {
     const int n = n0 + 2 * p;
     const InV* ij = in + ((size_t)b * a.Lh + j) * M * N + n;
     double2 xa[M], xb[M];
@@ -298,6 +306,12 @@ __global__ __launch_bounds__(kBlock) void k_bwd(BwdArgs a) {
         cim[oc] = yb.x - ya.y;
       }
     }
+  };
+  for (int idx = threadIdx.x; idx < max(L >> 1, 1) * P; idx += kBlock) {
+    const int j = idx >> logP;
+    const int p = idx & (P - 1);
+    take(j, p);
+    if (j == 0 && L > 1) take(L >> 1, p);
   }
   lds_fft<true>(cre, cim, twr, twi, L, a.logL, ncol);
 
