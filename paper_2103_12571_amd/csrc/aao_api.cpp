@@ -833,7 +833,12 @@ aao_status alloc_tables(aao_plan* p) {
   HIPCHK(hipHostMalloc(&p->htab, 2 * p->atab_stride, hipHostMallocDefault));
   HIPCHK(hipHostMalloc(&p->hread, p->hread_bytes, hipHostMallocDefault));
   HIPCHK(hipHostMalloc(&p->hlist, 256, hipHostMallocDefault));
-  std::memset(p->hlist, 0, 64);  // tags start at 1
+  // Pinned memory may come back from an earlier allocation with its old
+  // contents: a snapshot or report tag left there by a destroyed plan would
+  // match this plan's first tags (both count from 1), so every byte starts at 0.
+  std::memset(p->hlist, 0, 256);
+  std::memset(p->htab, 0, 2 * p->atab_stride);
+  std::memset(p->hread, 0, p->hread_bytes);
   std::vector<double2> tw(p->L / 2 + 1);
   for (int k = 0; k < (int)tw.size(); ++k) {
     const double ang = -2.0 * M_PI * (double)k / (double)p->L;

@@ -444,3 +444,26 @@ def test_solve_fft_inner_parity(name, w, tol):
     say("solve", name)
     info, _ = _solve_and_compare(w, tol, tol=w.tol, max_iter=40)
     assert info["converged"]
+
+
+def test_sweep_reports_of_consecutive_plans():
+    """A sweep's reported residual is its own: each plan's report comes
+    through pinned host memory with a tag that counts from 1, and a fresh plan
+    may get pinned memory that a destroyed plan used (regression: the first
+    sweep of such a plan read the old plan's report)."""
+    need_gpu()
+    H = wl.WORKLOADS["heat2d_256"]
+    shapes = [H.with_(nx=128, ny=64, L=8, M=4), H.with_(nx=128, ny=64, L=32), H.with_(nx=48, ny=40, L=8, M=4),
+              H.with_(nx=64, ny=64, L=2, M=4)]
+    for rep in range(2):
+        for w in shapes:
+            for inner in ("cocg", "fft"):
+                p = plan_for(w.with_(inner=inner))
+                rng = np.random.default_rng(11 + rep)
+                p.set_u0(dev(rng.standard_normal((w.batch, w.N))))
+                u = dev(rng.standard_normal((w.batch, w.L, w.M, w.N)))
+                _, nrm = p.residual(u)
+                res, _ = p.sweep(u, 1e-3)
+                say("  %dx%d L%d M%d %s: sweep %.12e residual %.12e" % (w.nx, w.ny, w.L, w.M, inner, res, nrm))
+                assert abs(res - nrm) <= 1e-13 * nrm
+                del p
