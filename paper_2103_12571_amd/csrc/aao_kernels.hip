@@ -9,6 +9,9 @@
 // real columns (n, n+1) are packed into one complex column, transformed by an
 // in-place radix-2 FFT (bit-reversed load, natural-order result) and separated
 // again; the M x M node transform of each frequency is applied on the way out.
+#include <algorithm>
+#include <cstdlib>
+
 #include "aao_kernels.hpp"
 #include "aao_device.hpp"
 
@@ -19,13 +22,175 @@ namespace {
 using namespace dev;
 
 // ----------------------------------------------------------------------------
+// Staged all-at-once residual of one tile (TN points of one grid row, N a
+// multiple of TN) for k_fwd: r_{l,m} = w - C u at every (l, m) of the tile,
+// scaled and left in the LDS planes (bit-reversed rows, the layout of the DFT
+// over l).  Phase 1 copies u of the tile into the planes and the hx points on
+// either side of the tile (periodic) into hal [lr][M][2 hx]; phase 2 forms the
+// residual rows of this thread in registers (stencil taps with dy = 0, the
+// node's own value and the coupling u_{l-1,M} (lambda_{l+1,.} for C^T) from
+// LDS, other taps and the source from global memory); phase 3 overwrites the
+// planes with the scaled rows.  The arithmetic is that of the unstaged loop,
+// operation for operation.
+constexpr int kStageRows = 4;  // rows l per thread: L TN <= kStageRows kBlock
+
+template <int M, bool ADJ, int NT>
+__device__ __forceinline__ void stage_residual(const FwdArgs& a, int b, int n0, int nl, int x, int y,
+                                               const int* nbs, int cim_off, int hal_off, double& res2) {
+  extern __shared__ double lds[];  // the transform's dynamic LDS (planes, twiddles, halo)
+  const int TN = a.TN, P = TN >> 1, L = a.L, N = a.g.N, nx = a.g.nx, hx = a.hx;
+  const int n = n0 + nl;
+  const int x0 = n0 % nx, row0 = n0 - x0;
+  const int step = kBlock >> a.logTN;
+  const int l0 = threadIdx.x >> a.logTN;
+  // every LDS access is lds[offset]: the planes start at 0 and cim_off, the
+  // halo at hal_off; own = this thread's point in its plane
+  const int own = ((nl & 1) ? cim_off : 0) + (nl >> 1);
+  const double* ub = a.u + (size_t)b * L * M * N;
+
+  // phase 1: the tile and its halo
+#pragma unroll
+  for (int i = 0; i < kStageRows; ++i) {
+    const int l = l0 + i * step;
+    if (l < L) {
+      const int lr = bitrev(l, a.logL);
+      const double* ul = ub + (size_t)l * M * N + n;
+#pragma unroll
+      for (int m = 0; m < M; ++m) lds[own + (lr * M + m) * P] = ul[(size_t)m * N];
+    }
+  }
+  const int hw = 2 * hx;
+  for (int i = threadIdx.x; i < L * M * hw; i += kBlock) {
+    const int k = i % hw, lm = i / hw;
+    const int l = lm / M, m = lm - l * M;
+    int xx = (k < hx) ? x0 - hx + k : x0 + TN + (k - hx);
+    xx += (xx < 0) ? nx : 0;
+    xx -= (xx >= nx) ? nx : 0;
+    lds[hal_off + (bitrev(l, a.logL) * M + m) * hw + k] = ub[((size_t)l * M + m) * N + row0 + xx];
+  }
+  __syncthreads();
+
+  // a tap along the row reads plane (q & 1) at q / 2 for a tile point q, or a
+  // halo slot: offset and row stride (P in the planes, 2 hx in the halo);
+  // stride 0 marks a tap read from global memory
+  auto row_src = [&](int dx, int& off, int& stride) {
+    int q = nl + dx;
+    if (TN == nx) {  // the tile is the whole row: the periodic wrap stays inside
+      q += (q < 0) ? TN : 0;
+      q -= (q >= TN) ? TN : 0;
+    }
+    if (q >= 0 && q < TN) {
+      off = ((q & 1) ? cim_off : 0) + (q >> 1);
+      stride = P;
+    } else {
+      off = hal_off + ((q < 0) ? q + hx : hx + (q - TN));
+      stride = hw;
+    }
+  };
+  int toff[NT > 0 ? NT : 1];
+  int tstr[NT > 0 ? NT : 1];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    toff[t] = 0;
+    tstr[t] = 0;
+    if (a.taps.dy[t] == 0) row_src(a.taps.dx[t], toff[t], tstr[t]);
+  }
+
+  // phase 2: residual rows in registers
+  double rr[kStageRows][M];
+#pragma unroll
+  for (int i = 0; i < kStageRows; ++i) {
+    const int l = l0 + i * step;
+#pragma unroll
+    for (int m = 0; m < M; ++m) rr[i][m] = 0.0;
+    if (l < L) {
+      const int lr = bitrev(l, a.logL);
+      const size_t base = ((size_t)b * L + l) * M * (size_t)N;
+      const double* ul = a.u + base;
+      double v[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) v[m] = 0.0;
+      auto tap = [&](double ct, int off, int str, int nb) {
+        if (str) {
+#pragma unroll
+          for (int m = 0; m < M; ++m) v[m] = fma(ct, lds[off + (lr * M + m) * str], v[m]);
+        } else {
+#pragma unroll
+          for (int m = 0; m < M; ++m) v[m] = fma(ct, ul[(size_t)m * N + nb], v[m]);
+        }
+      };
+      if (NT > 0) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) tap(a.taps.c[t], toff[t], tstr[t], nbs[t]);
+      } else {
+        for (int t = 0; t < a.taps.n; ++t) {
+          int off = 0, str = 0, nb = 0;
+          if (a.taps.dy[t] == 0) row_src(a.taps.dx[t], off, str);
+          else nb = wrap_index(x, y, a.taps.dx[t], a.taps.dy[t], a.g);
+          tap(a.taps.c[t], off, str, nb);
+        }
+      }
+      double f[M];  // source at the collocation times (eq. (collocation): dT Q b_l)
+#pragma unroll
+      for (int m = 0; m < M; ++m) f[m] = (!ADJ && a.frc) ? a.frc[base + (size_t)m * N + n] : 0.0;
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) s = fma(a.q[m * M + k], v[k] + f[k], s);
+        rr[i][m] = fma(a.dt, s, -lds[own + (lr * M + m) * P]);
+      }
+      if (!ADJ) {
+        const double add = (l == 0) ? a.w0[(size_t)b * N + n]
+                                    : lds[own + (bitrev(l - 1, a.logL) * M + (M - 1)) * P];  // u_{l-1, M}
+#pragma unroll
+        for (int m = 0; m < M; ++m) rr[i][m] += add;
+      } else {
+        if (l == L - 1) {
+          rr[i][M - 1] += a.w0[(size_t)b * N + n];
+        } else {
+          const int ln = bitrev(l + 1, a.logL) * M;  // lambda_{l+1, .}
+          double s = 0.0;
+#pragma unroll
+          for (int m = 0; m < M; ++m) s += lds[own + (ln + m) * P];
+          rr[i][M - 1] += s;
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m) res2 = fma(rr[i][m], rr[i][m], res2);
+    }
+  }
+  __syncthreads();
+
+  // phase 3: the scaled residual replaces u in the planes
+#pragma unroll
+  for (int i = 0; i < kStageRows; ++i) {
+    const int l = l0 + i * step;
+    if (l < L) {
+      const double sc = a.scale[l];
+      const int lr = bitrev(l, a.logL);
+#pragma unroll
+      for (int m = 0; m < M; ++m) lds[own + (lr * M + m) * P] = rr[i][m] * sc;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
 // Forward transform with the fused all-at-once residual.
 // MODE 0: r = w - C u computed on the fly; MODE 1: r read from memory.
 // ADJ: residual of C^T (coupling from step l+1 into the last node, Q^T, A^T).
 // NT > 0: the stencil has NT taps (unrolled, so all neighbour loads of a
 // point are in flight together).
-template <int M, bool ADJ, int MODE, typename OutV, int NT>
-__global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
+// STG (MODE 0, tiles inside one grid row): the tile's u for every (l, m) is
+// staged in the LDS planes, with a halo of a.hx points on each side of the
+// tile; taps along the row and the coupling between steps read LDS, taps into
+// other rows read global memory (L2: the neighbouring rows' tiles run on the
+// same XCD just before and after).
+template <int M, bool ADJ, int MODE, typename OutV, int NT, bool STG>
+// The staged form asks for five waves per SIMD (at most 96 VGPRs; the
+// unstaged form is left to the compiler, which takes about 100).
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(STG ? 5 : 1)))
+void k_fwd(FwdArgs a) {
   extern __shared__ double lds[];
   const int TN = a.TN, P = TN >> 1, L = a.L, N = a.g.N;
   const int b = blockIdx.y;
@@ -60,6 +225,9 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
   double* dst = ((nl & 1) ? cim : cre) + (nl >> 1);
 
   double res2 = 0.0;
+  if constexpr (MODE == 0 && STG) {
+    stage_residual<M, ADJ, NT>(a, b, n0, nl, x, y, nbs, plane, 2 * plane + L, res2);
+  } else {
 #ifndef AAO_FWD_ROW_UNROLL
 #define AAO_FWD_ROW_UNROLL 2
 #endif
@@ -128,6 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd(FwdArgs a) {
     const int lr = bitrev(l, a.logL);
 #pragma unroll
     for (int m = 0; m < M; ++m) dst[((size_t)lr * M + m) * P] = rv[m] * sc;
+  }
   }
 
   const int ncol = M * P;
@@ -1093,26 +1262,60 @@ size_t xform_lds_bytes(int M, int L, int TN) {
   return (2 * ((size_t)L * M * (TN / 2) + kPlanePad) + (size_t)L) * sizeof(double);
 }
 
+// Halo width of the staged residual (the largest |dx| of the taps with dy = 0;
+// none when a tile is a whole row), or -1 where it is not used: a tile must
+// lie inside one grid row, a thread hold at most kStageRows rows l, and the
+// halo take at most a quarter of the tile's LDS.  Staging also waits for a
+// grid of at least kStageMinGrid workgroups (64 per CU): measured on 1024^2
+// (L = 32) and 512^2 x 8 (L = 64) grids it saves 9-11 % of the kernel, on
+// 256^2 (L = 64, 4096 workgroups) it costs 8 %.
+constexpr int64_t kStageMinGrid = 16384;
+
+int stage_halo(const FwdArgs& a, int B) {
+  if ((int64_t)((a.g.N + a.TN - 1) / a.TN) * B < kStageMinGrid) return -1;
+  if (a.g.nx % a.TN != 0 || (int64_t)a.L * a.TN > (int64_t)kStageRows * kBlock) return -1;
+  if (a.TN == a.g.nx) return 0;
+  int hx = 0;
+  for (int t = 0; t < a.taps.n; ++t)
+    if (a.taps.dy[t] == 0) hx = std::max(hx, std::abs(a.taps.dx[t]));
+  return 8 * hx <= a.TN ? hx : -1;
+}
+
 template <int M>
-hipError_t fwd_m(bool adj, bool from_r, bool out_f32, const FwdArgs& a, int B, hipStream_t st) {
-  dim3 grid((a.g.N + a.TN - 1) / a.TN, B);
-  size_t lds = xform_lds_bytes(M, a.L, a.TN);
+hipError_t fwd_m(bool adj, bool from_r, bool out_f32, const FwdArgs& a0, int B, hipStream_t st) {
+  dim3 grid((a0.g.N + a0.TN - 1) / a0.TN, B);
+  FwdArgs a = a0;
+  const int hx = (from_r || M > 4) ? -1 : stage_halo(a0, B);
+  a.hx = hx > 0 ? hx : 0;
+  const size_t lds = xform_lds_bytes(M, a.L, a.TN) + (size_t)a.L * M * 2 * a.hx * sizeof(double);
   const int nt = (a.taps.n == 3 || a.taps.n == 5) ? a.taps.n : 0;
-#define AAO_FWD(ADJ, MODE, OV, NT) hipLaunchKernelGGL((k_fwd<M, ADJ, MODE, OV, NT>), grid, dim3(kBlock), lds, st, a)
-#define AAO_FWD0(ADJ, OV)                \
-  do {                                   \
-    if (nt == 5) AAO_FWD(ADJ, 0, OV, 5); \
-    else if (nt == 3) AAO_FWD(ADJ, 0, OV, 3); \
-    else AAO_FWD(ADJ, 0, OV, 0);         \
+#define AAO_FWD(ADJ, MODE, OV, NT, STG) \
+  hipLaunchKernelGGL((k_fwd<M, ADJ, MODE, OV, NT, STG>), grid, dim3(kBlock), lds, st, a)
+  // residual forms with 5, 3 or any number of taps: staged (M <= 4) or not
+#define AAO_FWDT(ADJ, OV, STG)                      \
+  do {                                              \
+    if (nt == 5) AAO_FWD(ADJ, 0, OV, 5, STG);       \
+    else if (nt == 3) AAO_FWD(ADJ, 0, OV, 3, STG);  \
+    else AAO_FWD(ADJ, 0, OV, 0, STG);               \
+  } while (0)
+#define AAO_FWD0(ADJ, OV)                                    \
+  do {                                                       \
+    if constexpr (M <= 4) {                                  \
+      if (hx < 0) AAO_FWDT(ADJ, OV, false);                  \
+      else AAO_FWDT(ADJ, OV, true);                          \
+    } else {                                                 \
+      AAO_FWDT(ADJ, OV, false);                              \
+    }                                                        \
   } while (0)
   if (!adj) {
     if (!from_r) { if (out_f32) AAO_FWD0(false, float2); else AAO_FWD0(false, double2); }
-    else { if (out_f32) AAO_FWD(false, 1, float2, 0); else AAO_FWD(false, 1, double2, 0); }
+    else { if (out_f32) AAO_FWD(false, 1, float2, 0, false); else AAO_FWD(false, 1, double2, 0, false); }
   } else {
     if (!from_r) { if (out_f32) AAO_FWD0(true, float2); else AAO_FWD0(true, double2); }
-    else { if (out_f32) AAO_FWD(true, 1, float2, 0); else AAO_FWD(true, 1, double2, 0); }
+    else { if (out_f32) AAO_FWD(true, 1, float2, 0, false); else AAO_FWD(true, 1, double2, 0, false); }
   }
 #undef AAO_FWD0
+#undef AAO_FWDT
 #undef AAO_FWD
   return hipGetLastError();
 }

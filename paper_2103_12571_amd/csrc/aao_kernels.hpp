@@ -114,6 +114,7 @@ struct FwdArgs {
   double q[kMaxM * kMaxM];  // Q (primal) or Q^T (adjoint), row-major
   double dt;
   int L, logL, Lh, TN, logTN;
+  int hx;               // halo width of the staged residual (set by the launcher)
 };
 
 // Inverse transform + update (row a4).
