@@ -62,7 +62,7 @@ def roofline_of(stats, w, cs):
     unf = survey_bytes(name, s, w, cs)
     ach = s["bytes"] / sec / 1e9
     out = {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(name, w.name),
+           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(name, w.name, w.precision),
            "launches": s["launches"], "avg_launch_us": round(1e3 * s["ms"] / s["launches"], 2),
            "bytes_per_launch": s["bytes"] / s["launches"],
            "achieved_unfused_bytes": round(unf / sec / 1e9, 1), "unfused_bytes_per_launch": unf / s["launches"],
@@ -141,6 +141,8 @@ def parse():
     ap.add_argument("--no-small", action="store_true", help="skip the 1D configurations (heat1d_64, adv1d_4096)")
     ap.add_argument("--all-configs", action="store_true",
                     help="also time every workload once against the oracle (adds about a minute)")
+    ap.add_argument("--only", choices=["small", "speedup", "adjoint"],
+                    help="run one block alone, without the oracle, and print its JSON (for profiling)")
     return ap.parse_args()
 
 
@@ -153,7 +155,7 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel, workload):
+def traffic_for(kernel, workload, precision):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
     was taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -164,7 +166,8 @@ def traffic_for(kernel, workload):
     except ValueError:
         return None
     for r in rec.get("records", []):
-        if r.get("kernel") == kernel and r.get("workload") == workload and r.get("source_sha") == source_hash():
+        if (r.get("kernel") == kernel and r.get("workload") == workload and r.get("precision") == precision
+                and r.get("source_sha") == source_hash()):
             return r.get("bytes_per_launch")
     return None
 
@@ -507,7 +510,7 @@ def main():
     w = wl.WORKLOADS[args.workload]
     u0 = wl.initial_batch(w)
     cpu = None
-    if not args.no_cpu_baseline and not args.copy_probe:
+    if not args.no_cpu_baseline and not args.copy_probe and not args.only:
         print("bench: oracle on the host (one thread, then all cores)", file=sys.stderr, flush=True)
         cpu = cpu_legs(w, u0)
 
@@ -528,6 +531,10 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_each_way": x.numel() * 8, "copies": 3}))
+        return
+    if args.only:
+        block = {"small": small_configs_block, "speedup": speedup_block, "adjoint": adjoint_block}[args.only]
+        print(json.dumps({args.only: block(np, torch, wl, plan_for, False)}), flush=True)
         return
 
     plan = plan_for(w)
