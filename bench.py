@@ -426,7 +426,9 @@ def small_configs_block(np, torch, wl, plan_for, with_oracle):
         if key != "heat1d_64":
             rf = roofline_of(st, w, 16)
             if rf:
-                rf["bound"] = "effective (Infinity Cache resident)"
+                rf["bound"] = ("instruction issue (one workgroup per system, vectors in registers and LDS; "
+                               "HBM bytes are b read and x, r written once per solve)"
+                               if rf["kernel"] == "bicgstab_wg" else "effective (Infinity Cache resident)")
             r["effective_bandwidth"] = rf
         if with_oracle:
             t0 = time.perf_counter()
