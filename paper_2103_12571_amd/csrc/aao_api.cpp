@@ -132,6 +132,7 @@ struct aao_plan {
   int cgTX = 1, cgTY = 1, cg_ntx = 1, cg_nty = 1, cg_ntiles = 1, Rx = 0, Ry = 0;
   int cgTXs = 0, cgTYs = 0, cg_ntxs = 0, cg_ntiles_s = 0;  // small tiling (cg_ntiles_s = 0: none)
   int fft_rows = 1, fft_cols = 1;
+  bool bicg_tiled = false;  // BiCGStab phases 1 and 2 on the COCG tiles
   int Px = 0, Py = 0;  // Bluestein lengths of x / y for the FFT inner solve (0: power of two)
   int* hlist = nullptr;      // pinned: (count, tag) of the active-system snapshots, per slot; from
                              // byte 64 the end-of-sweep report (k_sweep_report)
@@ -709,6 +710,20 @@ aao_status inner_solve(aao_plan* p, int adj, int nsys) {
     HIPCHK(timed(p, aao::KC_BICG_WG, [&] { return aao::launch_bicg_wg(p->f32, a, nsys, p->stream); }));
     return AAO_OK;
   }
+  // tiled: phases 1 and 2 on the COCG tiles, one chunk per tile throughout
+  const bool tiled = p->bicg_tiled;
+  aao::CgArgs g{};
+  if (tiled) {
+    g = cg_args(p, adj, nsys);
+    a.wps = g.ntiles;
+    a.chunk = (p->N + g.ntiles - 1) / g.ntiles;
+    a.wps_rho = a.wps;
+    a.wps_bb = a.wps;
+  }
+  auto phase = [&](int ph, int k, int nact) {
+    return (tiled && ph < 3) ? aao::launch_bicg_tiled(ph, p->f32, g, a, k, nact, p->stream)
+                             : aao::launch_bicg(ph, p->f32, a, k, nact, p->stream);
+  };
   close_run(p);
   HIPCHK(aao::launch_krylov_init(a, p->stream, p->dlist(2)));  // all active: the list is 0 .. nsys - 1
   int nact = nsys;
@@ -717,10 +732,10 @@ aao_status inner_solve(aao_plan* p, int adj, int nsys) {
   if (ls != AAO_OK) return ls;
   int next_check = 4;
   for (int k = 0; k <= p->inner_maxit; ++k) {
-    HIPCHK(timed(p, aao::KC_BICG_1, [&] { return aao::launch_bicg(1, p->f32, a, k, nact, p->stream); }));
+    HIPCHK(timed(p, aao::KC_BICG_1, [&] { return phase(1, k, nact); }));
     if (k < p->inner_maxit) {
-      HIPCHK(timed(p, aao::KC_BICG_2, [&] { return aao::launch_bicg(2, p->f32, a, k, nact, p->stream); }));
-      HIPCHK(timed(p, aao::KC_BICG_3, [&] { return aao::launch_bicg(3, p->f32, a, k, nact, p->stream); }));
+      HIPCHK(timed(p, aao::KC_BICG_2, [&] { return phase(2, k, nact); }));
+      HIPCHK(timed(p, aao::KC_BICG_3, [&] { return phase(3, k, nact); }));
       a.wps_rho = a.wps;  // rho_{k+1} and ||r_{k+1}||^2 were written by a.wps chunks
     }
     if (k + 1 == next_check) {
@@ -729,7 +744,7 @@ aao_status inner_solve(aao_plan* p, int adj, int nsys) {
       aao_status s = lag_check(c, nact, a.sys_list, n, false);
       if (s != AAO_OK) return s;
       if (n == 0) break;
-      krylov_chunks(p, nact, a);  // wider launches once fewer systems remain
+      if (!tiled) krylov_chunks(p, nact, a);  // wider launches once fewer systems remain
     }
   }
   if (c.pending >= 0) {
@@ -1140,6 +1155,20 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
   if (p->inner == AAO_INNER_COCG && p->cg_ntiles >= (1 << 16)) {  // tile indices use 16-bit exact division
     delete p;
     return fail(AAO_EINVAL, "grid too large for the COCG tiling (at most 65535 tiles per system)");
+  }
+  // BiCGStab on the COCG tiles: 2D grids beyond the one-workgroup size with
+  // at most 256 tiles per system (the update phase then uses one flat chunk
+  // of ceil(N / tiles) points per tile)
+  if (p->inner == AAO_INNER_BICGSTAB && p->ny > 1 && !aao::bicg_wg_fits(p->N)) {
+    aao::CgArgs g{};
+    g.TX = p->cgTX;
+    g.TY = p->cgTY;
+    g.Rx = p->Rx;
+    g.Ry = p->Ry;
+    g.ntiles = p->cg_ntiles;
+    const int64_t nt = p->cg_ntiles;
+    p->bicg_tiled = aao::bicg_tiled_fits(g) && nt * (nt - 1) < p->N;
+    if (p->bicg_tiled) p->wps_max = std::max(p->wps_max, p->cg_ntiles);
   }
   p->fb_slots = std::max(p->ntiles * p->B, 1024);
   p->grad_blocks = std::max(1, std::min(256, (p->N + aao::kBlock - 1) / aao::kBlock));

@@ -588,6 +588,195 @@ __global__ __launch_bounds__(kBlock) void k_cg_xfix(CgArgs a) {
     X[n] = vadd(k > 0 ? X[n] : vzero<V>(), vmul(al, Pk[n]));
 }
 
+
+// ----------------------------------------------------------------------------
+// Batched BiCGStab on the COCG tiles (2D grids, at most 256 tiles per
+// system): the two phases with a matrix-vector product form their vector on
+// the tile and its one-hop ring in LDS (read once per point, the ring's
+// points recomputed from their own inputs) and apply the stencil from there,
+// instead of rebuilding the vector at every neighbour from global memory.
+// Grid (tiles, active systems); tile t writes chunk t of the partial sums.
+// Scalars, stopping test and breakdown flags are those of the chunked
+// kernels (aao_kernels.hip, k_bicg1 and k_bicg2); the update phase (k_bicg3)
+// is shared, with as many chunks as there are tiles.
+
+// Phase 1: convergence test, beta, p = r + beta (p_old - omega v_old),
+// v = (I - cA) p, partial <r_hat, v> (k = 0: p = r_hat = r, <r, r>).
+template <typename T, int NI, int NH, int NT>
+__global__ __launch_bounds__(kBlock) void k_bicg_t1(CgArgs g, KrylovArgs a, int k) {
+  using V = typename cvec<T>::type;
+  extern __shared__ char smem[];
+  __shared__ double sh[4 * 8];
+  __shared__ int act;
+  const int t = threadIdx.x;
+  const int s = a.sys_list[blockIdx.y];
+  SysState* st = a.st + s;
+  const int tile = tile_of_block(g);
+  // one read of the flag per workgroup (tile 0 may clear it concurrently)
+  if (t == 0) act = st->active;
+  __syncthreads();
+  if (!act) return;
+  const int cur = k & 1;
+  const size_t off = (size_t)s * a.g.N;
+  const V* R = reinterpret_cast<const V*>(a.R) + off;
+  V* Rh = reinterpret_cast<V*>(a.Rh) + off;
+  V* Pn = reinterpret_cast<V*>(a.P[k & 1]) + off;
+  const V* Po = reinterpret_cast<const V*>(a.P[(k + 1) & 1]) + off;
+  V* Vn = reinterpret_cast<V*>(a.V[k & 1]) + off;
+  const V* Vo = reinterpret_cast<const V*>(a.V[(k + 1) & 1]) + off;
+  const V sft = from_d2<V>(a.shift[s]);
+  V bt = vzero<V>(), om = vzero<V>();
+  if (k > 0) {
+    const int qs[4] = {QP_RHO0_RE + 2 * cur, QP_RHO0_IM + 2 * cur, QP_RR0 + cur, QP_BB};
+    const int nw[4] = {a.wps_rho, a.wps_rho, a.wps_rho, a.wps_bb};
+    double v[4];
+    reduce_parts<4>(a, qs, nw, s, v, sh);
+    const bool conv = v[2] <= a.tol2 * (a.bbfloor ? fmax(v[3], a.bbfloor[s]) : v[3]);
+    if (conv || k >= a.maxit || st->breakdown) {
+      if (tile == 0 && t == 0) {
+        st->active = 0;
+        st->iters = k;
+        st->flag = conv ? 0 : (st->breakdown ? 2 : 1);
+      }
+      return;
+    }
+    const double2 rho = mk(v[0], v[1]);
+    bt = from_d2<V>(cmul(cdiv(rho, st->rho), cdiv(st->alpha, st->omega)));
+    om = from_d2<V>(st->omega);
+  }
+  // p at a point (k = 0: r)
+  auto pval = [&](int i) { return k == 0 ? R[i] : vadd(R[i], vmul(bt, vsub(Po[i], vmul(om, Vo[i])))); };
+  const TileGeo G = tile_geo(g, tile);
+  const LdsCplx<V> Pt(smem, G.PW * G.PH);
+  V pv[NI];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    int gi, l, q;
+    bool own;
+    tile_slot(g, G, t, j, gi, l, q, own);
+    pv[j] = pval(gi);
+    if (l >= 0) Pt.st(l, pv[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < NH; ++j) {
+    int gi, l, q;
+    ring_slot(g, G, t, j, gi, l, q);
+    if (q >= 0) Pt.st(l, pval(gi));  // one stencil: the one-hop ring is enough
+  }
+  __syncthreads();
+  double hv_re = 0, hv_im = 0, bb = 0;
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    int gi, l, q;
+    bool own;
+    tile_slot(g, G, t, j, gi, l, q, own);
+    if (own) {
+      const V p = pv[j];
+      const V v = vsub(p, vmul(sft, tile_stencil<NT, T>(g, Pt, l, G.PW)));
+      Pn[gi] = p;
+      Vn[gi] = v;
+      if (k == 0) {
+        Rh[gi] = p;
+        hv_re += (double)p.x * v.x + (double)p.y * v.y;
+        hv_im += (double)p.x * v.y - (double)p.y * v.x;
+        bb += (double)p.x * p.x + (double)p.y * p.y;
+      } else {
+        const V rh = Rh[gi];
+        hv_re += (double)rh.x * v.x + (double)rh.y * v.y;
+        hv_im += (double)rh.x * v.y - (double)rh.y * v.x;
+      }
+    }
+  }
+  if (k == 0) {
+    // rho_0 = <r_hat, r> = ||b||^2 (real)
+    double w[4] = {hv_re, hv_im, bb, bb};
+    const int qs[4] = {QP_A_RE, QP_A_IM, QP_BB, QP_RHO0_RE};
+    write_parts<4>(a, qs, s, tile, w, sh);
+    if (t == 0) qpart(a, QP_RHO0_IM, s)[tile] = 0.0;
+  } else {
+    double w[2] = {hv_re, hv_im};
+    const int qw[2] = {QP_A_RE, QP_A_IM};
+    write_parts<2>(a, qw, s, tile, w, sh);
+  }
+}
+
+// Phase 2: alpha = rho_k / <r_hat, v>; s = r - alpha v; t = (I - cA) s;
+// partials <t, s>, <t, t>.  Tile 0 records rho_k and alpha_k.
+template <typename T, int NI, int NH, int NT>
+__global__ __launch_bounds__(kBlock) void k_bicg_t2(CgArgs g, KrylovArgs a, int k) {
+  using V = typename cvec<T>::type;
+  extern __shared__ char smem[];
+  __shared__ double sh[4 * 8];
+  __shared__ int act;
+  const int t = threadIdx.x;
+  const int s = a.sys_list[blockIdx.y];
+  SysState* st = a.st + s;
+  const int tile = tile_of_block(g);
+  if (t == 0) act = st->active;
+  __syncthreads();
+  if (!act) return;
+  const int cur = k & 1;
+  double v[4];
+  {
+    const int qs[4] = {QP_RHO0_RE + 2 * cur, QP_RHO0_IM + 2 * cur, QP_A_RE, QP_A_IM};
+    const int nw[4] = {a.wps_rho, a.wps_rho, a.wps, a.wps};  // rho: the previous iteration (k = 0: this one)
+    reduce_parts<4>(a, qs, nw, s, v, sh);
+  }
+  const double2 rho = mk(v[0], v[1]);
+  const double2 hv = mk(v[2], v[3]);
+  double2 al = mk(0, 0);
+  if (hv.x * hv.x + hv.y * hv.y > 0.0) al = cdiv(rho, hv);
+  else if (tile == 0 && t == 0 && (rho.x != 0.0 || rho.y != 0.0)) st->breakdown = 1;
+  if (tile == 0 && t == 0) {
+    st->rho = rho;
+    st->alpha = al;
+  }
+  const size_t off = (size_t)s * a.g.N;
+  const V* R = reinterpret_cast<const V*>(a.R) + off;
+  const V* Vc = reinterpret_cast<const V*>(a.V[k & 1]) + off;
+  V* Sv = reinterpret_cast<V*>(a.S) + off;
+  V* Tv = reinterpret_cast<V*>(a.T) + off;
+  const V sft = from_d2<V>(a.shift[s]);
+  const V av = from_d2<V>(al);
+  auto sval = [&](int i) { return vsub(R[i], vmul(av, Vc[i])); };
+  const TileGeo G = tile_geo(g, tile);
+  const LdsCplx<V> St(smem, G.PW * G.PH);
+  V sv[NI];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    int gi, l, q;
+    bool own;
+    tile_slot(g, G, t, j, gi, l, q, own);
+    sv[j] = sval(gi);
+    if (l >= 0) St.st(l, sv[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < NH; ++j) {
+    int gi, l, q;
+    ring_slot(g, G, t, j, gi, l, q);
+    if (q >= 0) St.st(l, sval(gi));
+  }
+  __syncthreads();
+  double ts_re = 0, ts_im = 0, tt = 0;
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    int gi, l, q;
+    bool own;
+    tile_slot(g, G, t, j, gi, l, q, own);
+    if (own) {
+      const V x = sv[j];
+      const V tv = vsub(x, vmul(sft, tile_stencil<NT, T>(g, St, l, G.PW)));
+      Sv[gi] = x;
+      Tv[gi] = tv;
+      ts_re += (double)tv.x * x.x + (double)tv.y * x.y;
+      ts_im += (double)tv.x * x.y - (double)tv.y * x.x;
+      tt += (double)tv.x * tv.x + (double)tv.y * tv.y;
+    }
+  }
+  double w[3] = {ts_re, ts_im, tt};
+  const int qs[3] = {QP_B_RE, QP_B_IM, QP_TT};
+  write_parts<3>(a, qs, s, tile, w, sh);
+}
 }  // namespace
 
 size_t cg_lds_bytes(bool f32, const CgArgs& a) {
@@ -689,6 +878,53 @@ hipError_t launch_cg_xfix(bool f32, const CgArgs& a, int nsys, hipStream_t st) {
   dim3 grid(blocks, nsys);
   if (f32) hipLaunchKernelGGL(k_cg_xfix<float>, grid, dim3(kBlock), 0, st, a);
   else hipLaunchKernelGGL(k_cg_xfix<double>, grid, dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+
+bool bicg_tiled_fits(const CgArgs& g) {
+  return g.TX * g.TY <= kInside * kBlock && g.ntiles <= kBlock && cg_ring_slots(g) <= 8;
+}
+
+hipError_t launch_bicg_tiled(int phase, bool f32, const CgArgs& g, const KrylovArgs& a, int k, int nact,
+                             hipStream_t st) {
+  if (!bicg_tiled_fits(g) || a.wps != g.ntiles || a.wps > a.wps_stride || a.wps_rho < 1 ||
+      a.wps_rho > a.wps_stride || a.wps_bb < 1 || a.wps_bb > a.wps_stride || (phase != 1 && phase != 2))
+    return hipErrorInvalidValue;
+  dim3 grid(g.ntiles, nact);
+  const size_t lds = cg_lds_bytes(f32, g);
+  const int nh = cg_ring_slots(g);
+  const int nt = (g.taps.n == 3 || g.taps.n == 5) ? g.taps.n : 0;
+  const bool one = g.TX * g.TY <= kBlock;
+#define AAO_BT4(T, NI, NH, NT)                                                                          \
+  do {                                                                                                  \
+    if (phase == 1) hipLaunchKernelGGL((k_bicg_t1<T, NI, NH, NT>), grid, dim3(kBlock), lds, st, g, a, k); \
+    else hipLaunchKernelGGL((k_bicg_t2<T, NI, NH, NT>), grid, dim3(kBlock), lds, st, g, a, k);           \
+  } while (0)
+#define AAO_BT3(NI, NH, NT)                 \
+  do {                                      \
+    if (f32) AAO_BT4(float, NI, NH, NT);    \
+    else AAO_BT4(double, NI, NH, NT);       \
+  } while (0)
+#define AAO_BT2(NH, NT)                 \
+  do {                                  \
+    if (one) AAO_BT3(1, NH, NT);        \
+    else AAO_BT3(kInside, NH, NT);      \
+  } while (0)
+#define AAO_BT(NH)                      \
+  do {                                  \
+    if (nt == 3) AAO_BT2(NH, 3);        \
+    else if (nt == 5) AAO_BT2(NH, 5);   \
+    else AAO_BT2(NH, 0);                \
+  } while (0)
+  if (nh <= 1) AAO_BT(1);
+  else if (nh <= 2) AAO_BT(2);
+  else if (nh <= 4) AAO_BT(4);
+  else AAO_BT(8);
+#undef AAO_BT4
+#undef AAO_BT3
+#undef AAO_BT2
+#undef AAO_BT
   return hipGetLastError();
 }
 

@@ -237,5 +237,38 @@ __device__ __forceinline__ void lds_fft(double* re, double* im, const double* tw
   __syncthreads();
 }
 
+// Per-chunk partial sums of the batched BiCGStab ([quantity][system][chunk],
+// chunk < wps_stride).  Every workgroup reduces them in the same fixed order,
+// so the scalars are bitwise identical across workgroups and no grid-wide
+// synchronisation is needed.
+__device__ __forceinline__ double* qpart(const KrylovArgs& a, int q, int s) {
+  return a.part + ((size_t)q * a.num_sys + s) * a.wps_stride;
+}
+
+// Sum quantity qs[i] over the nw[i] chunks that wrote it (fixed order).
+template <int K>
+__device__ __forceinline__ void reduce_parts(const KrylovArgs& a, const int (&qs)[K], const int (&nw)[K], int s,
+                                             double (&v)[K], double* sh) {
+#pragma unroll
+  for (int i = 0; i < K; ++i) v[i] = 0.0;
+  for (int c = threadIdx.x; c < a.wps_stride; c += kBlock) {
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+      if (c < nw[i]) v[i] += qpart(a, qs[i], s)[c];
+  }
+  block_sum<K>(v, sh);
+}
+
+// This workgroup's sums of quantities qs, as chunk `chunk` of system s.
+template <int K>
+__device__ __forceinline__ void write_parts(const KrylovArgs& a, const int (&qs)[K], int s, int chunk,
+                                            double (&v)[K], double* sh) {
+  block_sum<K>(v, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) qpart(a, qs[i], s)[chunk] = v[i];
+  }
+}
+
 }  // namespace dev
 }  // namespace aao

@@ -661,33 +661,7 @@ __global__ __launch_bounds__(kBlock) void k_wnorms(FwdArgs a, int B, double* par
 // workgroup owns one chunk of one system.  Scalars are reduced from per-chunk
 // partial sums by every workgroup in the same fixed order (bitwise identical),
 // so no grid-wide synchronisation and no host round trip is needed.
-__device__ __forceinline__ double* qpart(const KrylovArgs& a, int q, int s) {
-  return a.part + ((size_t)q * a.num_sys + s) * a.wps_stride;
-}
-
-// Sum quantity qs[i] over the nw[i] chunks that wrote it (fixed order).
-template <int K>
-__device__ __forceinline__ void reduce_parts(const KrylovArgs& a, const int (&qs)[K], const int (&nw)[K], int s,
-                                             double (&v)[K], double* sh) {
-#pragma unroll
-  for (int i = 0; i < K; ++i) v[i] = 0.0;
-  for (int c = threadIdx.x; c < a.wps_stride; c += kBlock) {
-#pragma unroll
-    for (int i = 0; i < K; ++i)
-      if (c < nw[i]) v[i] += qpart(a, qs[i], s)[c];
-  }
-  block_sum<K>(v, sh);
-}
-
-template <int K>
-__device__ __forceinline__ void write_parts(const KrylovArgs& a, const int (&qs)[K], int s,
-                                            double (&v)[K], double* sh) {
-  block_sum<K>(v, sh);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < K; ++i) qpart(a, qs[i], s)[blockIdx.x] = v[i];
-  }
-}
+// (qpart, reduce_parts and write_parts: aao_device.hpp)
 
 
 // Shifted operator at point n on a vector given through an accessor.
@@ -744,7 +718,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg1(KrylovArgs a, int k) {
     // rho_0 = <r_hat, r> = ||b||^2 (real)
     double w[4] = {hv_re, hv_im, bb, bb};
     const int qs[4] = {QP_A_RE, QP_A_IM, QP_BB, QP_RHO0_RE};
-    write_parts<4>(a, qs, s, w, sh);
+    write_parts<4>(a, qs, s, blockIdx.x, w, sh);
     if (threadIdx.x == 0) qpart(a, QP_RHO0_IM, s)[blockIdx.x] = 0.0;
   } else {
     const int qs[4] = {QP_RHO0_RE + 2 * cur, QP_RHO0_IM + 2 * cur, QP_RR0 + cur, QP_BB};
@@ -776,7 +750,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg1(KrylovArgs a, int k) {
     }
     double w[2] = {hv_re, hv_im};
     const int qw[2] = {QP_A_RE, QP_A_IM};
-    write_parts<2>(a, qw, s, w, sh);
+    write_parts<2>(a, qw, s, blockIdx.x, w, sh);
   }
 }
 
@@ -832,7 +806,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg2(KrylovArgs a, int k) {
   }
   double w[3] = {ts_re, ts_im, tt};
   const int qs[3] = {QP_B_RE, QP_B_IM, QP_TT};
-  write_parts<3>(a, qs, s, w, sh);
+  write_parts<3>(a, qs, s, blockIdx.x, w, sh);
 }
 
 // Phase 3: omega = <t, s> / <t, t>; x += alpha p + omega s; r = s - omega t;
@@ -888,7 +862,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg3(KrylovArgs a, int k) {
   }
   double w[3] = {hr_re, hr_im, rr};
   const int qs[3] = {QP_RHO0_RE + 2 * nxt, QP_RHO0_IM + 2 * nxt, QP_RR0 + nxt};
-  write_parts<3>(a, qs, s, w, sh);
+  write_parts<3>(a, qs, s, blockIdx.x, w, sh);
 }
 
 // BiCGStab for a whole system in one workgroup, for systems of at most

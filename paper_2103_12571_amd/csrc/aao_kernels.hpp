@@ -232,6 +232,11 @@ hipError_t launch_cg_xfix(bool f32, const CgArgs& a, int nsys, hipStream_t st);
 size_t cg_lds_bytes(bool f32, const CgArgs& a);
 int cg_ring_slots(const CgArgs& a);
 hipError_t launch_bicg(int phase, bool f32, const KrylovArgs& a, int k, int nact, hipStream_t st);
+// Phases 1 and 2 of the batched BiCGStab on the COCG tiles of g (2D; every
+// tile one chunk: a.wps == g.ntiles); bicg_tiled_fits says whether g allows it.
+bool bicg_tiled_fits(const CgArgs& g);
+hipError_t launch_bicg_tiled(int phase, bool f32, const CgArgs& g, const KrylovArgs& a, int k, int nact,
+                             hipStream_t st);
 // Fresh state for systems 0 .. num_sys - 1, and list[i] = i when list is given
 // (every system starts active).
 hipError_t launch_krylov_init(const KrylovArgs& a, hipStream_t st, int* list = nullptr);
