@@ -22,6 +22,12 @@ def _setup(w):
                                                                            tol=1e-13), 1e-10),
     ("advdiff_32_L16_B2_mixed", wl.WORKLOADS["advdiff2d_512_adj"].with_(nx=32, ny=32, L=16, batch=2), 1e-8),
     ("heat2d_20x16_L4_M2_cocg", wl.WORKLOADS["heat2d_256"].with_(nx=20, ny=16, L=4, M=2, tol=1e-13), 1e-10),
+    # BiCGStab beyond 4096 points: the matrix-vector phases on ragged 64 x 16 tiles with A^T
+    ("advdiff_130x70_L8_fp64_tiled", wl.WORKLOADS["advdiff2d_512_adj"].with_(nx=130, ny=70, L=8, batch=1,
+                                                                               precision="fp64", inner_tol=1e-13,
+                                                                               tol=1e-13), 1e-10),
+    ("advdiff_130x70_L8_B2_mixed_tiled", wl.WORKLOADS["advdiff2d_512_adj"].with_(nx=130, ny=70, L=8, batch=2),
+     1e-8),
     # the spatial-FFT inner solve with the transposed stencil's symbol; it is
     # exact, so tau (which sets Alg. 2's gamma) is the FP64 round-off level
     ("advdiff_16x12_L8_B2_fp64_fft", wl.WORKLOADS["advdiff2d_512_adj"].with_(nx=16, ny=12, L=8, batch=2,

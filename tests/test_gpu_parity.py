@@ -21,7 +21,7 @@ Q3 = None
 
 
 def _oracle_op(w):
-    return oracle.stencil_for(w.kind, w.nx, w.ny, nu=w.nu, c=w.vel)
+    return oracle.stencil_for(w.kind, w.nx, w.ny, nu=w.nu, c=w.vel, order=w.order)
 
 
 def _Q(M):
@@ -105,19 +105,23 @@ def test_shifted_solve_parity(inner, kind, prec):
     assert np.all(its > 0)
 
 
-@pytest.mark.parametrize("kind,nx,ny", [("advdiff2d", 64, 64), ("advdiff2d", 65, 64),
-                                        ("adv1d_c4", 4096, 1), ("adv1d_c4", 4100, 1)])
+@pytest.mark.parametrize("kind,nx,ny,order", [("advdiff2d", 64, 64, 2), ("advdiff2d", 65, 64, 2),
+                                              ("advdiff2d", 130, 70, 2), ("adv2d_upwind", 96, 80, 4),
+                                              ("adv1d_c4", 4096, 1, 2), ("adv1d_c4", 4100, 1, 2)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_shifted_solve_bicgstab_both_paths(kind, nx, ny, prec):
+def test_shifted_solve_bicgstab_both_paths(kind, nx, ny, order, prec):
     """Row a3 with BiCGStab on both sides of the 4096-point limit: smaller
     systems run every iteration in one workgroup per system (one launch),
-    larger ones in the chunked three-kernel form.  Shifts of |c| up to 10 /
-    (Gershgorin bound of A), against a sparse direct solve."""
+    larger ones in the three-kernel form (2D grids: the matrix-vector phases
+    on 64 x 16 tiles, here ragged in x, in y, and with a two-point reach;
+    1D: flat chunks).  Shifts of |c| up to 10 / (Gershgorin bound of A),
+    against a sparse direct solve."""
     import scipy.sparse as sp
     import scipy.sparse.linalg as spla
     need_gpu()
-    say("bicgstab paths", kind, nx, ny, prec)
-    w = wl.Workload("t", kind, nx, ny, 8, 3, 1e-3, nu=1e-2, vel=(1.0, 0.5), inner="bicgstab", precision=prec)
+    say("bicgstab paths", kind, nx, ny, order, prec)
+    w = wl.Workload("t", kind, nx, ny, 8, 3, 1e-3, nu=1e-2, vel=(1.0, 0.5), inner="bicgstab", precision=prec,
+                    order=order)
     p = plan_for(w, inner_tol=1e-13 if prec == "fp64" else 1e-6)
     A = _oracle_op(w).matrix()
     rho = abs(A).sum(axis=1).max()
