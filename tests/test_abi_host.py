@@ -135,6 +135,20 @@ def test_null_arguments():
     assert lib.aao_workspace_size(None, None) == bd.AAO_EINVAL
 
 
+def test_inner_floor_setter_checks_arguments():
+    """aao_set_inner_floor is host-only: a null plan or a non-finite tau_w is
+    EINVAL, any finite value (negative: the default) is taken."""
+    lib = bd.lib()
+    assert lib.aao_set_inner_floor(None, 1e-14) == bd.AAO_EINVAL
+    s, h = _setup()
+    assert s == 0
+    for v in (float("nan"), float("inf"), -float("inf")):
+        assert lib.aao_set_inner_floor(h, v) == bd.AAO_EINVAL
+    for v in (-1.0, 0.0, 1e-14, 0.3):
+        assert lib.aao_set_inner_floor(h, v) == 0
+    lib.aao_destroy(h)
+
+
 def test_calls_before_workspace_report_state():
     s, h = _setup()
     lib = bd.lib()
