@@ -84,14 +84,17 @@ int ilog2(int64_t v) {
 #ifndef AAO_XFORM_LDS_KB
 #define AAO_XFORM_LDS_KB 24
 #endif
+// LDS budgets of the FFT inner solve's tiles (row lines; column tiles: a
+// full 128-byte segment per row within the smaller budget, else at least 64
+// bytes within the larger one)
 #ifndef AAO_FFT_ROW_LDS_KB
-#define AAO_FFT_ROW_LDS_KB 40
+#define AAO_FFT_ROW_LDS_KB 20
+#endif
+#ifndef AAO_FFT_COL_LDS_SMALL_KB
+#define AAO_FFT_COL_LDS_SMALL_KB 40
 #endif
 #ifndef AAO_FFT_COL_LDS_KB
 #define AAO_FFT_COL_LDS_KB 72
-#endif
-#ifndef AAO_FFT_COL_SEG_BYTES
-#define AAO_FFT_COL_SEG_BYTES 128
 #endif
 
 constexpr int kWorkSlots = 32;     // [class] for k > 0, [16 + class] for k == 0
@@ -1095,8 +1098,12 @@ aao_status aao_setup(const aao_stencil* A, const aao_config* cfg, void* hip_stre
     const int cs = (int)p->csize;
     const int lx = aao::fft_pad_line((int)fft_line(p->nx)), ly = aao::fft_pad_line((int)fft_line(p->ny));
     p->fft_rows = largest_divisor(p->ny, AAO_FFT_ROW_LDS_KB * 1024 / (lx * cs));
-    // columns: up to AAO_FFT_COL_SEG_BYTES of consecutive elements per row, within the LDS budget
-    p->fft_cols = largest_divisor(p->nx, std::min(AAO_FFT_COL_SEG_BYTES / cs, AAO_FFT_COL_LDS_KB * 1024 / (ly * cs)));
+    // columns: 128 bytes of consecutive elements per row where such a tile
+    // fits the smaller budget (more workgroups per CU), else 64 bytes within
+    // the larger one
+    int ccap = std::min(128 / cs, AAO_FFT_COL_LDS_SMALL_KB * 1024 / (ly * cs));
+    if (ccap * cs < 64) ccap = std::min(64 / cs, AAO_FFT_COL_LDS_KB * 1024 / (ly * cs));
+    p->fft_cols = largest_divisor(p->nx, ccap);
   }
   {
     const int target = 4096;
