@@ -506,12 +506,38 @@ __global__ __launch_bounds__(kBlock) void k_bwd(BwdArgs a) {
 }
 
 // ----------------------------------------------------------------------------
+// This thread's share (indices threadIdx.x + kBlock j) of the sum / max of
+// x[0 .. n): eight independent accumulators, so eight loads are in flight per
+// step instead of one chain of dependent adds (tens of thousands of
+// per-workgroup partials otherwise take 0.1-0.4 ms to add up); the order is
+// fixed by n.
+__device__ __forceinline__ double strided_sum(const double* x, int n) {
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int i = threadIdx.x;
+  for (; i + 7 * kBlock < n; i += 8 * kBlock) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] += x[i + q * kBlock];
+  }
+  for (; i < n; i += kBlock) a[0] += x[i];
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+__device__ __forceinline__ double strided_max(const double* x, int n) {
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int i = threadIdx.x;
+  for (; i + 7 * kBlock < n; i += 8 * kBlock) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = fmax(a[q], x[i + q * kBlock]);
+  }
+  for (; i < n; i += kBlock) a[0] = fmax(a[0], x[i]);
+  return fmax(fmax(fmax(a[0], a[1]), fmax(a[2], a[3])), fmax(fmax(a[4], a[5]), fmax(a[6], a[7])));
+}
+
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* ps, int ns, const double* pm,
                                                      int nm, double* out) {
   __shared__ double sh[4];
-  double s = 0.0, mx = 0.0;
-  for (int i = threadIdx.x; i < ns; i += kBlock) s += ps[i];
-  for (int i = threadIdx.x; i < nm; i += kBlock) mx = fmax(mx, pm[i]);
+  const double s = strided_sum(ps, ns);
+  double mx = strided_max(pm, nm);
   double v[1] = {s};
   block_sum<1>(v, sh);
   mx = block_max(mx, sh);
@@ -541,9 +567,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_report(const double* ps, int n
                                                          double* out, const SysState* st, int nsys, int cocg,
                                                          double* rep, int tag) {
   __shared__ double sh[4 * 8];
-  double s = 0.0, mx = 0.0;
-  for (int i = threadIdx.x; i < ns; i += kBlock) s += ps[i];
-  for (int i = threadIdx.x; i < nm; i += kBlock) mx = fmax(mx, pm[i]);
+  const double s = strided_sum(ps, ns);
+  double mx = strided_max(pm, nm);
   double v[5] = {s, 0.0, 0.0, 0.0, 0.0};
   double imax = 0.0;
   for (int i = threadIdx.x; i < nsys; i += kBlock) {
