@@ -4,11 +4,14 @@
 // A periodic stencil is diagonalised by the DFT: for the mode e^{2 pi i k.n/N}
 // it acts as lambda(k) = sum_t c_t e^{2 pi i (kx dx_t / nx + ky dy_t / ny)}, so
 // x = F^{-1}[ F b / (1 - c_s lambda(k)) ] exactly.  Transforms run in LDS with
-// radix-2 butterflies: decimation in time (bit-reversed input, natural output)
-// forward, decimation in frequency (natural input, bit-reversed output) for the
-// inverse, so no reordering pass is needed.  1D: one workgroup per system does
-// forward, divide and inverse.  2D: rows forward (in place), then columns
-// forward + divide + inverse (in place), then rows inverse into x.
+// radix-2 butterflies: decimation in frequency (natural input, bit-reversed
+// output) forward, decimation in time (bit-reversed input, natural output) for
+// the inverse, so spectra stay in bit-reversed order between the two and no
+// reordering pass is needed; the divide takes the frequency of a position as
+// its bit reversal.  1D: one workgroup per system does forward, divide and
+// inverse.  2D: rows forward (in place; a row's spectrum is left in
+// bit-reversed kx order), then columns forward + divide + inverse (in place),
+// then rows inverse into x.
 //
 // A length n that is not a power of two goes through Bluestein's chirp-z form
 // of the DFT: with jk = (j^2 + k^2 - (k - j)^2) / 2, X_k = ch_k (a * b)_k for
@@ -35,49 +38,70 @@ template <> struct scal<float2> { using type = float; };
 // lines that sit a power of two apart) fall into different banks.
 __device__ __forceinline__ int padi(int i) { return i + (i >> 3); }
 
+// v e^{2 pi i e / 8} for e in 0 .. 3 (the roots of unity that separate the
+// twiddles of one group).
+__device__ __forceinline__ double2 root8_mul(double2 v, int e) {
+  constexpr double h = 0.70710678118654752440;  // cos(pi / 4)
+  if (e == 0) return v;
+  if (e == 1) return mk((v.x - v.y) * h, (v.x + v.y) * h);
+  if (e == 2) return mk(-v.y, v.x);
+  return mk(-(v.x + v.y) * h, (v.x - v.y) * h);
+}
+
 // Radix-2 stages on a group of 2^K elements held in registers: element t is
 // transform element i0 + t 2^slo (bits slo .. slo+K-1 of i0 clear, pos0 =
 // i0 mod 2^slo).  DIT: stages slo .. slo+K-1 with butterflies (a, b) -> (a +
 // w b, a - w b); DIF: stages slo+K-1 down to slo with (a, d) -> (a + d,
-// (a - d) w).  Stage slo+q pairs t and t + 2^q (bit q of t clear) with
-// twiddle W[pos tstride], pos = pos0 + (t mod 2^q) 2^slo, tstride = n /
-// 2^(slo+q+1); the forward transform uses the conjugates of W = e^{+2 pi i k / n}.
+// (a - d) w).  Stage slo+q pairs t and t + 2^q (bit q of t clear) with the
+// twiddle e^{2 pi i (pos0 + j 2^slo) / 2^(slo+q+1)}, j = t mod 2^q, which is
+// w^(2^(K-1-q)) e^{2 pi i j / 2^(q+1)} for the group's base twiddle w =
+// e^{2 pi i pos0 / 2^(slo+K)}: one table read per group, the rest by complex
+// squaring and eighth roots of unity.  The forward transform takes the
+// conjugates.
 template <typename V, bool DIT, bool INV, int K>
-__device__ __forceinline__ void group_stages(V (&v)[1 << K], const double2* W, int n, int slo, int pos0) {
+__device__ __forceinline__ void group_stages(V (&v)[1 << K], double2 w) {
   using T = typename scal<V>::type;
   constexpr int R = 1 << K;
-  const int span = 1 << slo;
+  double2 wq[K];
+  wq[K - 1] = w;
+#pragma unroll
+  for (int q = K - 2; q >= 0; --q) wq[q] = cmul(wq[q + 1], wq[q + 1]);
 #pragma unroll
   for (int qq = 0; qq < K; ++qq) {
     const int q = DIT ? qq : K - 1 - qq;
     const int half = 1 << q;
-    const int tstride = n >> (slo + q + 1);
+    V tw[R / 2];
+#pragma unroll
+    for (int j = 0; j < half; ++j) {
+      const double2 wd = root8_mul(wq[q], j << (2 - q));
+      tw[j].x = (T)wd.x;
+      tw[j].y = INV ? (T)wd.y : (T)-wd.y;
+    }
 #pragma unroll
     for (int t = 0; t < R; ++t) {
       if (t & half) continue;
-      const double2 wd = W[(pos0 + (t & (half - 1)) * span) * tstride];
-      V w;
-      w.x = (T)wd.x;
-      w.y = INV ? (T)wd.y : (T)-wd.y;
+      const V wt = tw[t & (half - 1)];
       const V a = v[t];
       if (DIT) {
-        const V b = vmul(w, v[t + half]);
+        const V b = vmul(wt, v[t + half]);
         v[t] = vadd(a, b);
         v[t + half] = vsub(a, b);
       } else {
         const V d = v[t + half];
         v[t] = vadd(a, d);
-        v[t + half] = vmul(vsub(a, d), w);
+        v[t + half] = vmul(vsub(a, d), wt);
       }
     }
   }
 }
 
 // One pass of K stages over nb transforms of length n in LDS (element (b, i)
-// at b sb + padi(i) se), one group of 2^K elements per thread and trip.
-// MID: the group is also multiplied element-wise by mul(b, i) and taken back
-// through the same stages as DIF (the last forward pass, the divide and the
-// first inverse pass of a forward-divide-inverse solve in one trip).
+// at b sb + padi(i) se), one group of 2^K elements per thread and trip.  W:
+// e^{+2 pi i k / n} (k < n / 2 is read), in global memory.
+// MID (the lowest stages, slo = 0): DIF forward stages, the element-wise
+// multiply by mul(b, k) at frequency k (element i holds frequency bitrev(i)),
+// then the same stages as DIT inverse (the last forward pass, the divide and
+// the first inverse pass of a forward-divide-inverse solve in one trip).
 // FASTB: consecutive threads take consecutive transforms (b).
 template <typename V, bool DIT, bool INV, bool FASTB, int K, bool MID = false, typename Mul = int>
 __device__ __forceinline__ void fft_pass(const LdsCplx<V>& c, const double2* W, int n, int logn, int slo, int nb,
@@ -85,6 +109,7 @@ __device__ __forceinline__ void fft_pass(const LdsCplx<V>& c, const double2* W, 
   constexpr int R = 1 << K;
   const int lng = logn - K;  // 2^lng groups per transform
   const int span = 1 << slo;
+  const int wstride = n >> (slo + K);
   __syncthreads();
   for (int idx = threadIdx.x; idx < (nb << lng); idx += nth) {
     const int b = FASTB ? idx % nb : idx >> lng;
@@ -92,16 +117,17 @@ __device__ __forceinline__ void fft_pass(const LdsCplx<V>& c, const double2* W, 
     const int pos0 = g & (span - 1);
     const int i0 = ((g >> slo) << (slo + K)) + pos0;
     const int base = b * sb;
+    const double2 w = W[pos0 * wstride];
     V v[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) v[t] = c.ld(base + padi(i0 + t * span) * se);
     if constexpr (MID) {
-      group_stages<V, true, false, K>(v, W, n, slo, pos0);
+      group_stages<V, false, false, K>(v, w);
 #pragma unroll
-      for (int t = 0; t < R; ++t) v[t] = vmul(v[t], mul(b, i0 + t * span));
-      group_stages<V, false, true, K>(v, W, n, slo, pos0);
+      for (int t = 0; t < R; ++t) v[t] = vmul(v[t], mul(b, bitrev(i0 + t * span, logn)));
+      group_stages<V, true, true, K>(v, w);
     } else {
-      group_stages<V, DIT, INV, K>(v, W, n, slo, pos0);
+      group_stages<V, DIT, INV, K>(v, w);
     }
 #pragma unroll
     for (int t = 0; t < R; ++t) c.st(base + padi(i0 + t * span) * se, v[t]);
@@ -116,53 +142,40 @@ __device__ __forceinline__ void fft_pass_k(const LdsCplx<V>& c, const double2* W
   else fft_pass<V, DIT, INV, FASTB, 1>(c, W, n, logn, slo, nb, sb, se, nth);
 }
 
-// Stage grouping: the forward (DIT) transform takes its partial pass first,
-// the inverse (DIF) last, so that the last forward pass and the first inverse
-// pass act on the same groups (stages logn-3 .. logn-1).
-__device__ __forceinline__ int dit_first_k(int logn) { return logn - 3 * ((logn - 1) / 3); }
-
-// nb radix-2 transforms of length n in LDS: DIT = decimation in time
-// (bit-reversed input, natural output), else decimation in frequency
-// (natural input, bit-reversed output).  The stages are taken up to three at
-// a time in registers: one barrier per pass.
-template <typename V, bool DIT, bool INV, bool FASTB>
-__device__ __forceinline__ void fft_lds(const LdsCplx<V>& c, const double2* W, int n, int logn, int nb, int sb,
-                                        int se, int nth) {
-  if (DIT) {
-    for (int slo = 0, k = dit_first_k(logn); slo < logn; slo += k, k = 3)
-      fft_pass_k<V, DIT, INV, FASTB>(c, W, n, logn, slo, k, nb, sb, se, nth);
-  } else {
-    for (int done = 0; done < logn;) {
-      const int k = min(3, logn - done);
-      fft_pass_k<V, DIT, INV, FASTB>(c, W, n, logn, logn - done - k, k, nb, sb, se, nth);
-      done += k;
-    }
+// DIT passes over stages lo .. logn-1 (upwards, three at a time, the last
+// pass partial) and DIF passes over stages logn-1 down to lo.
+template <typename V, bool INV, bool FASTB>
+__device__ __forceinline__ void dit_passes(const LdsCplx<V>& c, const double2* W, int n, int logn, int lo, int nb,
+                                           int sb, int se, int nth) {
+  for (int slo = lo; slo < logn; slo += 3)
+    fft_pass_k<V, true, INV, FASTB>(c, W, n, logn, slo, min(3, logn - slo), nb, sb, se, nth);
+}
+template <typename V, bool INV, bool FASTB>
+__device__ __forceinline__ void dif_passes(const LdsCplx<V>& c, const double2* W, int n, int logn, int lo, int nb,
+                                           int sb, int se, int nth) {
+  for (int hi = logn; hi > lo; hi -= 3) {
+    const int k = min(3, hi - lo);
+    fft_pass_k<V, false, INV, FASTB>(c, W, n, logn, hi - k, k, nb, sb, se, nth);
   }
-  __syncthreads();
 }
 
-// Forward transform (DIT, bit-reversed input), element-wise multiply by
-// mul(b, k) at frequency k, inverse transform (DIF, bit-reversed output), with
-// the last forward pass, the multiply and the first inverse pass in one trip.
+// Forward transform (DIF: natural input, bit-reversed output), element-wise
+// multiply by mul(b, k) at frequency k, inverse transform (DIT: bit-reversed
+// input, natural output), with the last forward pass, the multiply and the
+// first inverse pass (stages 0 .. 2) in one trip.
 template <typename V, bool FASTB, typename Mul>
 __device__ __forceinline__ void fft_mul_ifft(const LdsCplx<V>& c, const double2* W, int n, int logn, int nb, int sb,
                                              int se, int nth, const Mul& mul) {
   const int km = min(3, logn);
-  const int sm = logn - km;  // the shared pass: stages sm .. logn-1
-  for (int slo = 0, k = dit_first_k(logn); slo < sm; slo += k, k = 3)
-    fft_pass_k<V, true, false, FASTB>(c, W, n, logn, slo, k, nb, sb, se, nth);
-  if (km == 3) fft_pass<V, true, false, FASTB, 3, true>(c, W, n, logn, sm, nb, sb, se, nth, mul);
-  else if (km == 2) fft_pass<V, true, false, FASTB, 2, true>(c, W, n, logn, sm, nb, sb, se, nth, mul);
-  else if (km == 1) fft_pass<V, true, false, FASTB, 1, true>(c, W, n, logn, sm, nb, sb, se, nth, mul);
+  dif_passes<V, false, FASTB>(c, W, n, logn, km, nb, sb, se, nth);
+  if (km == 3) fft_pass<V, true, false, FASTB, 3, true>(c, W, n, logn, 0, nb, sb, se, nth, mul);
+  else if (km == 2) fft_pass<V, true, false, FASTB, 2, true>(c, W, n, logn, 0, nb, sb, se, nth, mul);
+  else if (km == 1) fft_pass<V, true, false, FASTB, 1, true>(c, W, n, logn, 0, nb, sb, se, nth, mul);
   else {  // n = 1: the transforms are the identity
     __syncthreads();
     for (int b = threadIdx.x; b < nb; b += nth) c.st(b * sb, vmul(c.ld(b * sb), mul(b, 0)));
   }
-  for (int done = km; done < logn;) {
-    const int k = min(3, logn - done);
-    fft_pass_k<V, false, true, FASTB>(c, W, n, logn, logn - done - k, k, nb, sb, se, nth);
-    done += k;
-  }
+  dit_passes<V, true, FASTB>(c, W, n, logn, km, nb, sb, se, nth);
   __syncthreads();
 }
 
@@ -205,9 +218,9 @@ __device__ __forceinline__ double2 inv_symbol(const FftArgs& a, double2 c, int k
 }
 
 // Bluestein convolution of nb sequences of length P held in c (element (b, i)
-// at b * sb + padi(i) * se) at bit-reversed positions: forward radix-2
-// transform, multiply by the filter's transform F, inverse radix-2 transform.
-// Leaves P times the cyclic convolution, again at bit-reversed positions.
+// at b * sb + padi(i) * se) in natural order: forward radix-2 transform,
+// multiply by the filter's transform F, inverse radix-2 transform.  Leaves P
+// times the cyclic convolution, again in natural order.
 template <typename V, bool FASTB>
 __device__ __forceinline__ void blue_conv(const LdsCplx<V>& c, const BlueDim& d, const double2* F, int nb, int sb,
                                           int se, int nth) {
@@ -216,15 +229,9 @@ __device__ __forceinline__ void blue_conv(const LdsCplx<V>& c, const BlueDim& d,
 
 __device__ __forceinline__ double2 cscale(double2 v, double s) { return mk(v.x * s, v.y * s); }
 
-// The first n/2 twiddles e^{+2 pi i k / n} (all a transform of length n
-// reads) copied to LDS after the data (byte offset `off`, 16-byte aligned);
-// the passes read them from there.  The copy is ordered before the first
-// read by the barrier that opens every pass.
-__device__ __forceinline__ const double2* lds_twiddles(char* smem, size_t off, const double2* W, int n, int nth) {
-  double2* tw = reinterpret_cast<double2*>(smem + off);
-  for (int k = threadIdx.x; k < (n >> 1); k += nth) tw[k] = W[k];
-  return tw;
-}
+// Frequency kx of column x of a row spectrum: radix-2 rows leave their
+// spectra in bit-reversed order, Bluestein rows in natural order.
+__device__ __forceinline__ int kx_of(const FftArgs& a, int x) { return a.bx.P > 0 ? x : bitrev(x, a.lognx); }
 
 // Threads of the column kernel: one per group of eight elements of the
 // tile (cols x line), at least 64 and at most 1024 (launch_fft_solve).
@@ -254,13 +261,13 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(FftArgs a) {
       const int r = i >> logP, j = i & (P - 1);
       V v = vzero<V>();
       if (j < nx) v = vmul(in[r * nx + j], from_d2<V>(MODE == 1 ? cconj(d.ch[j]) : d.ch[j]));
-      c.st(r * ls + padi(dev::bitrev(j, logP)), v);
+      c.st(r * ls + padi(j), v);
     }
     blue_conv<V, false>(c, d, MODE == 1 ? d.Bi : d.Bf, rows, ls, 1, kBlock);
     if (MODE == 2) {
       const double2 sh = a.shift[s];
       for (int k = threadIdx.x; k < P; k += kBlock) {
-        const int o = padi(dev::bitrev(k, logP));
+        const int o = padi(k);
         c.st(o, k < nx ? vmul(c.ld(o), from_d2<V>(cscale(inv_symbol(a, sh, k, 0), invP))) : vzero<V>());
       }
       blue_conv<V, false>(c, d, d.Bi, 1, ls, 1, kBlock);
@@ -268,19 +275,22 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(FftArgs a) {
     for (int i = threadIdx.x; i < tot; i += kBlock) {
       const int r = i / nx, k = i - r * nx;
       const double2 chk = cscale(MODE == 0 ? d.ch[k] : cconj(d.ch[k]), invP);
-      out[i] = vmul(c.ld(r * ls + padi(dev::bitrev(k, logP))), from_d2<V>(chk));
+      out[i] = vmul(c.ld(r * ls + padi(k)), from_d2<V>(chk));
     }
     return;
   }
+  // natural order in and out: the forward rows (DIF) leave the spectrum in
+  // bit-reversed order, which the inverse rows (DIT) take
   for (int i = threadIdx.x; i < tot; i += kBlock) {
     const int r = i / nx, x = i - r * nx;
-    c.st(r * ls + padi(MODE == 1 ? x : dev::bitrev(x, a.lognx)), in[i]);
+    c.st(r * ls + padi(x), in[i]);
   }
-  const double2* twx = lds_twiddles(smem, fft_tw_offset(sizeof(V), rows * ls), a.Wx, nx, kBlock);
   if (MODE == 1) {
-    fft_lds<V, false, true, false>(c, twx, nx, a.lognx, rows, ls, 1, kBlock);
+    dit_passes<V, true, false>(c, a.Wx, nx, a.lognx, 0, rows, ls, 1, kBlock);
+    __syncthreads();
   } else if (MODE == 0) {
-    fft_lds<V, true, false, false>(c, twx, nx, a.lognx, rows, ls, 1, kBlock);
+    dif_passes<V, false, false>(c, a.Wx, nx, a.lognx, 0, rows, ls, 1, kBlock);
+    __syncthreads();
   } else {
     const double2 sh = a.shift[s];
     fft_mul_ifft<V, false>(c, a.Wx, nx, a.lognx, rows, ls, 1, kBlock,
@@ -288,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(FftArgs a) {
   }
   for (int i = threadIdx.x; i < tot; i += kBlock) {
     const int r = i / nx, x = i - r * nx;
-    out[i] = c.ld(r * ls + padi(MODE == 0 ? x : dev::bitrev(x, a.lognx)));
+    out[i] = c.ld(r * ls + padi(x));
   }
 }
 
@@ -310,51 +320,56 @@ __global__ __launch_bounds__(1024) void k_fft_cols(FftArgs a) {
   const int tot = ny * cols;
   if (BLUE) {
     const BlueDim& d = a.by;
-    const int P = d.P, logP = d.logP;
+    const int P = d.P;
     const double invP = 1.0 / P;
     for (int i = threadIdx.x; i < P * cols; i += CB) {
       const int j = i / cols, col = i - j * cols;
-      c.st(padi(dev::bitrev(j, logP)) * cols + col,
+      c.st(padi(j) * cols + col,
            j < ny ? vmul(base[(size_t)j * nx + col], from_d2<V>(d.ch[j])) : vzero<V>());
     }
     blue_conv<V, true>(c, d, d.Bf, cols, 1, cols, CB);
     const double2 sh = a.shift[s];
     for (int i = threadIdx.x; i < P * cols; i += CB) {
       const int k = i / cols, col = i - k * cols;
-      const int o = padi(dev::bitrev(k, logP)) * cols + col;
-      c.st(o, k < ny ? vmul(c.ld(o), from_d2<V>(cscale(inv_symbol(a, sh, x0 + col, k), invP))) : vzero<V>());
+      const int o = padi(k) * cols + col;
+      c.st(o, k < ny ? vmul(c.ld(o), from_d2<V>(cscale(inv_symbol(a, sh, kx_of(a, x0 + col), k), invP)))
+                     : vzero<V>());
     }
     blue_conv<V, true>(c, d, d.Bi, cols, 1, cols, CB);
     for (int i = threadIdx.x; i < tot; i += CB) {
       const int k = i / cols, col = i - k * cols;
       base[(size_t)k * nx + col] =
-          vmul(c.ld(padi(dev::bitrev(k, logP)) * cols + col), from_d2<V>(cscale(cconj(d.ch[k]), invP)));
+          vmul(c.ld(padi(k) * cols + col), from_d2<V>(cscale(cconj(d.ch[k]), invP)));
     }
     return;
   }
+  // forward (DIF) leaves row y of the tile at frequency ky = bitrev(y); the
+  // inverse (DIT) takes that order back to natural
   for (int i = threadIdx.x; i < tot; i += CB) {
     const int y = i / cols, col = i - y * cols;
-    c.st(padi(dev::bitrev(y, a.logny)) * cols + col, base[(size_t)y * nx + col]);
+    c.st(padi(y) * cols + col, base[(size_t)y * nx + col]);
   }
-  const double2* twy = lds_twiddles(smem, fft_tw_offset(sizeof(V), padi(ny) * cols), a.Wy, ny, CB);
   const double2 sh = a.shift[s];
-  // forward, divide, inverse; the divide in a pass of its own (in the last
-  // forward pass it would hold the group's registers through the symbol
-  // evaluation).  When the block size is a multiple of cols every trip of a
-  // thread is on the same column: its x part is summed once.
-  fft_lds<V, true, false, true>(c, twy, ny, a.logny, cols, 1, cols, CB);
+  dif_passes<V, false, true>(c, a.Wy, ny, a.logny, 0, cols, 1, cols, CB);
+  __syncthreads();
+  // the divide in a pass of its own (in the last forward pass it would hold
+  // the group's registers through the symbol evaluation).  When the block
+  // size is a multiple of cols every trip of a thread is on the same column:
+  // its x part is summed once.
   const bool same_col = (CB % cols) == 0;
-  const double2 lx = sym_x(a, x0 + threadIdx.x % cols);
+  const double2 lx = sym_x(a, kx_of(a, x0 + threadIdx.x % cols));
   for (int i = threadIdx.x; i < tot; i += CB) {
     const int y = i / cols, col = i - y * cols;
     const int o = padi(y) * cols + col;
-    const double2 f = inv_den(a, sh, cadd(same_col ? lx : sym_x(a, x0 + col), sym_rest(a, x0 + col, y)));
+    const int kx = kx_of(a, x0 + col);
+    const double2 f = inv_den(a, sh, cadd(same_col ? lx : sym_x(a, kx), sym_rest(a, kx, bitrev(y, a.logny))));
     c.st(o, vmul(c.ld(o), from_d2<V>(f)));
   }
-  fft_lds<V, false, true, true>(c, twy, ny, a.logny, cols, 1, cols, CB);
+  dit_passes<V, true, true>(c, a.Wy, ny, a.logny, 0, cols, 1, cols, CB);
+  __syncthreads();
   for (int i = threadIdx.x; i < tot; i += CB) {
     const int y = i / cols, col = i - y * cols;
-    base[(size_t)y * nx + col] = c.ld(padi(dev::bitrev(y, a.logny)) * cols + col);
+    base[(size_t)y * nx + col] = c.ld(padi(y) * cols + col);
   }
 }
 
@@ -384,9 +399,7 @@ hipError_t launch_fft_solve(bool f32, const FftArgs& a, int nsys, hipStream_t st
   }
   if (a.rows < 1 || a.cols < 1 || a.ny % a.rows != 0 || a.nx % a.cols != 0) return hipErrorInvalidValue;
   dim3 grow(a.ny / a.rows, nsys), gcol(a.nx / a.cols, nsys);
-  // non-Bluestein lines also hold their twiddle table in LDS
-  const size_t lrow = bx ? lbytes(a.rows * lx) : fft_tw_offset(f32 ? 8 : 16, a.rows * lx) + (size_t)(a.nx / 2) * 16;
-  const size_t lcol = by ? lbytes(a.cols * ly) : fft_tw_offset(f32 ? 8 : 16, a.cols * ly) + (size_t)(a.ny / 2) * 16;
+  const size_t lrow = lbytes(a.rows * lx), lcol = lbytes(a.cols * ly);
   int cthreads = 64;  // one thread per group of eight tile elements, a multiple of 64
   while (cthreads < 1024 && cthreads * 8 < a.cols * (by ? a.by.P : a.ny)) cthreads *= 2;
   if (f32) {

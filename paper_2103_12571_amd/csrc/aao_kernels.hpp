@@ -247,14 +247,6 @@ hipError_t launch_bicg_wg(bool f32, const KrylovArgs& a, int nsys, hipStream_t s
 hipError_t launch_fft_solve(bool f32, const FftArgs& a, int nsys, hipStream_t st);
 // LDS slots of one transform line of n elements (one pad slot per eight).
 inline int fft_pad_line(int n) { return n + (n >> 3); }
-// Byte offset of the twiddle table after `slots` complex LDS slots of
-// esize (16: two planes of doubles, each padded as LdsCplx does; 8:
-// interleaved floats), 16-byte aligned.
-__host__ __device__ inline size_t fft_tw_offset(int esize, int slots) {
-  const size_t stride = (esize == 16 && 2 * ((size_t)slots + 8) * 8 <= 65536) ? (size_t)slots + 8 : (size_t)slots;
-  const size_t b = esize == 16 ? 2 * stride * 8 : (size_t)slots * 8;
-  return (b + 15) & ~(size_t)15;
-}
 hipError_t launch_compact_active(const SysState* st, int n, int* list, int* count_tag, int tag, hipStream_t s);
 hipError_t launch_copy_c128_in(void* dst, bool f32, const double* src, int64_t n, hipStream_t st);
 hipError_t launch_copy_c128_out(double* dst, const void* src, bool f32, int64_t n,
