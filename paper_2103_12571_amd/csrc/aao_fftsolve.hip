@@ -38,6 +38,9 @@ template <> struct scal<float2> { using type = float; };
 // lines that sit a power of two apart) fall into different banks.
 __device__ __forceinline__ int padi(int i) { return i + (i >> 3); }
 
+// a / b for a >= 0, b > 0 (unsigned: a power-of-two constant b is a shift)
+__device__ __forceinline__ int udiv(int a, int b) { return (int)((unsigned)a / (unsigned)b); }
+
 // v e^{2 pi i e / 8} for e in 0 .. 3 (the roots of unity that separate the
 // twiddles of one group).
 __device__ __forceinline__ double2 root8_mul(double2 v, int e) {
@@ -112,8 +115,8 @@ __device__ __forceinline__ void fft_pass(const LdsCplx<V>& c, const double2* W, 
   const int wstride = n >> (slo + K);
   __syncthreads();
   for (int idx = threadIdx.x; idx < (nb << lng); idx += nth) {
-    const int b = FASTB ? idx % nb : idx >> lng;
-    const int g = FASTB ? idx / nb : idx & ((1 << lng) - 1);
+    const int g = FASTB ? udiv(idx, nb) : idx & ((1 << lng) - 1);
+    const int b = FASTB ? idx - g * nb : idx >> lng;
     const int pos0 = g & (span - 1);
     const int i0 = ((g >> slo) << (slo + K)) + pos0;
     const int base = b * sb;
@@ -305,13 +308,14 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(FftArgs a) {
 // Columns: forward along y, divide, inverse along y, in place on R.
 // grid (nx / cols, nsys); column col, row y at col + padi(y) cols in LDS (a
 // cache line of cols consecutive elements per row).  BLUE: ny through
-// length-P convolutions.
-template <typename V, bool BLUE>
+// length-P convolutions.  CL > 0: cols = CL at compile time (the index
+// splits i / cols, i % cols and the LDS strides are shifts), else a.cols.
+template <typename V, bool BLUE, int CL>
 __global__ __launch_bounds__(1024) void k_fft_cols(FftArgs a) {
   const int CB = blockDim.x;
   extern __shared__ char smem[];
   const int s = blockIdx.y;
-  const int nx = a.nx, ny = a.ny, cols = a.cols;
+  const int nx = a.nx, ny = a.ny, cols = CL > 0 ? CL : a.cols;
   const LdsCplx<V> c(smem, padi(BLUE ? a.by.P : ny) * cols);
   int grp = blockIdx.x;  // XCD-banded: neighbouring column groups share cache lines
   if ((gridDim.x & 7) == 0) grp = (grp & 7) * (gridDim.x >> 3) + (grp >> 3);
@@ -323,21 +327,21 @@ __global__ __launch_bounds__(1024) void k_fft_cols(FftArgs a) {
     const int P = d.P;
     const double invP = 1.0 / P;
     for (int i = threadIdx.x; i < P * cols; i += CB) {
-      const int j = i / cols, col = i - j * cols;
+      const int j = udiv(i, cols), col = i - j * cols;
       c.st(padi(j) * cols + col,
            j < ny ? vmul(base[(size_t)j * nx + col], from_d2<V>(d.ch[j])) : vzero<V>());
     }
     blue_conv<V, true>(c, d, d.Bf, cols, 1, cols, CB);
     const double2 sh = a.shift[s];
     for (int i = threadIdx.x; i < P * cols; i += CB) {
-      const int k = i / cols, col = i - k * cols;
+      const int k = udiv(i, cols), col = i - k * cols;
       const int o = padi(k) * cols + col;
       c.st(o, k < ny ? vmul(c.ld(o), from_d2<V>(cscale(inv_symbol(a, sh, kx_of(a, x0 + col), k), invP)))
                      : vzero<V>());
     }
     blue_conv<V, true>(c, d, d.Bi, cols, 1, cols, CB);
     for (int i = threadIdx.x; i < tot; i += CB) {
-      const int k = i / cols, col = i - k * cols;
+      const int k = udiv(i, cols), col = i - k * cols;
       base[(size_t)k * nx + col] =
           vmul(c.ld(padi(k) * cols + col), from_d2<V>(cscale(cconj(d.ch[k]), invP)));
     }
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(FftArgs a) {
   // forward (DIF) leaves row y of the tile at frequency ky = bitrev(y); the
   // inverse (DIT) takes that order back to natural
   for (int i = threadIdx.x; i < tot; i += CB) {
-    const int y = i / cols, col = i - y * cols;
+    const int y = udiv(i, cols), col = i - y * cols;
     c.st(padi(y) * cols + col, base[(size_t)y * nx + col]);
   }
   const double2 sh = a.shift[s];
@@ -359,7 +363,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(FftArgs a) {
   const bool same_col = (CB % cols) == 0;
   const double2 lx = sym_x(a, kx_of(a, x0 + threadIdx.x % cols));
   for (int i = threadIdx.x; i < tot; i += CB) {
-    const int y = i / cols, col = i - y * cols;
+    const int y = udiv(i, cols), col = i - y * cols;
     const int o = padi(y) * cols + col;
     const int kx = kx_of(a, x0 + col);
     const double2 f = inv_den(a, sh, cadd(same_col ? lx : sym_x(a, kx), sym_rest(a, kx, bitrev(y, a.logny))));
@@ -368,7 +372,7 @@ __global__ __launch_bounds__(1024) void k_fft_cols(FftArgs a) {
   dit_passes<V, true, true>(c, a.Wy, ny, a.logny, 0, cols, 1, cols, CB);
   __syncthreads();
   for (int i = threadIdx.x; i < tot; i += CB) {
-    const int y = i / cols, col = i - y * cols;
+    const int y = udiv(i, cols), col = i - y * cols;
     base[(size_t)y * nx + col] = c.ld(padi(y) * cols + col);
   }
 }
@@ -385,10 +389,20 @@ hipError_t launch_fft_solve(bool f32, const FftArgs& a, int nsys, hipStream_t st
     if (bx) hipLaunchKernelGGL((k_fft_rows<V, MODE, true>), grid, dim3(kBlock), lds, st, a);   \
     else hipLaunchKernelGGL((k_fft_rows<V, MODE, false>), grid, dim3(kBlock), lds, st, a);     \
   } while (0)
-#define AAO_COLS(V, grid, lds)                                                              \
-  do {                                                                                       \
-    if (by) hipLaunchKernelGGL((k_fft_cols<V, true>), grid, dim3(cthreads), lds, st, a);    \
-    else hipLaunchKernelGGL((k_fft_cols<V, false>), grid, dim3(cthreads), lds, st, a);      \
+#define AAO_COLS1(V, BL, grid, lds)                                                                  \
+  do {                                                                                               \
+    switch (a.cols) {                                                                                \
+      case 2: hipLaunchKernelGGL((k_fft_cols<V, BL, 2>), grid, dim3(cthreads), lds, st, a); break;   \
+      case 4: hipLaunchKernelGGL((k_fft_cols<V, BL, 4>), grid, dim3(cthreads), lds, st, a); break;   \
+      case 8: hipLaunchKernelGGL((k_fft_cols<V, BL, 8>), grid, dim3(cthreads), lds, st, a); break;   \
+      case 16: hipLaunchKernelGGL((k_fft_cols<V, BL, 16>), grid, dim3(cthreads), lds, st, a); break; \
+      default: hipLaunchKernelGGL((k_fft_cols<V, BL, 0>), grid, dim3(cthreads), lds, st, a);         \
+    }                                                                                                \
+  } while (0)
+#define AAO_COLS(V, grid, lds)                 \
+  do {                                         \
+    if (by) AAO_COLS1(V, true, grid, lds);     \
+    else AAO_COLS1(V, false, grid, lds);       \
   } while (0)
   if (a.ny == 1) {
     dim3 grid(1, nsys);
@@ -413,6 +427,7 @@ hipError_t launch_fft_solve(bool f32, const FftArgs& a, int nsys, hipStream_t st
   }
 #undef AAO_ROWS
 #undef AAO_COLS
+#undef AAO_COLS1
   return hipGetLastError();
 }
 
