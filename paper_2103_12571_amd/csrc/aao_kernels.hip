@@ -34,6 +34,26 @@ using namespace dev;
 // operation for operation.
 constexpr int kStageRows = 4;  // rows l per thread: L TN <= kStageRows kBlock
 
+// The per-frequency node transforms [Lh][M][M] are copied to LDS (at double
+// offset mixo, real and imaginary parts side by side) where they fit
+// kMixLdsBytes: read from global memory, the M^2 coefficients of every
+// output item miss L1 once the tile data streams through it.
+constexpr size_t kMixLdsBytes = 8192;
+template <int M>
+__device__ __forceinline__ void stage_mix(const double2* mix, int Lh, int mixo) {
+  extern __shared__ double lds[];
+  if (mixo < 0) return;
+  for (int i = threadIdx.x; i < Lh * M * M; i += kBlock) {
+    const double2 v = mix[i];
+    lds[mixo + 2 * i] = v.x;
+    lds[mixo + 2 * i + 1] = v.y;
+  }
+}
+__device__ __forceinline__ double2 mix_lds(int mixo, int i) {
+  extern __shared__ double lds[];
+  return mk(lds[mixo + 2 * i], lds[mixo + 2 * i + 1]);
+}
+
 template <int M, bool ADJ, int NT>
 __device__ __forceinline__ void stage_residual(const FwdArgs& a, int b, int n0, int nl, int x, int y,
                                                const int* nbs, int cim_off, int hal_off, double& res2) {
@@ -211,6 +231,7 @@ void k_fwd(FwdArgs a) {
     twr[i] = a.tw[i].x;
     twi[i] = a.tw[i].y;
   }
+  stage_mix<M>(a.mix, a.Lh, a.mixo);
 
   // TN divides kBlock, so the spatial point of a thread is the same in every
   // row l it visits: its coordinates and the unrolled taps' neighbour offsets
@@ -306,7 +327,7 @@ void k_fwd(FwdArgs a) {
   const int logP = a.logTN - 1;
   // frequencies 0 and L/2 (both self-conjugate) share an item, so that the
   // (L/2) P items fill the block once (L TN = 1024 within the LDS budget)
-  auto emit = [&](int j, int p) {
+  auto emit = [&](int j, int p, auto&& mixw) __attribute__((always_inline)) {
     const int jm = (L - j) & (L - 1);
     double2 A[M], Bv[M];
 #pragma unroll
@@ -321,14 +342,13 @@ void k_fwd(FwdArgs a) {
         Bv[m].y = -Bv[m].y;
       }
     }
-    const double2* mx = a.mix + (size_t)j * M * M;
     const int n = n0 + 2 * p;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       double2 xa = mk(0, 0), xb = mk(0, 0);
 #pragma unroll
       for (int k = 0; k < M; ++k) {
-        const double2 w = mx[m * M + k];
+        const double2 w = mixw(j, m * M + k);
         xa = cadd(xa, cmul(w, A[k]));
         xb = cadd(xb, cmul(w, Bv[k]));
       }
@@ -337,12 +357,16 @@ void k_fwd(FwdArgs a) {
       if (n + 1 < N) out[o + 1] = from_d2<OutV>(xb);
     }
   };
-  for (int idx = threadIdx.x; idx < max(L >> 1, 1) * P; idx += kBlock) {
-    const int j = idx >> logP;
-    const int p = idx & (P - 1);
-    emit(j, p);
-    if (j == 0 && L > 1) emit(L >> 1, p);
-  }
+  auto emit_all = [&](auto&& mixw) __attribute__((always_inline)) {
+    for (int idx = threadIdx.x; idx < max(L >> 1, 1) * P; idx += kBlock) {
+      const int j = idx >> logP;
+      const int p = idx & (P - 1);
+      emit(j, p, mixw);
+      if (j == 0 && L > 1) emit(L >> 1, p, mixw);
+    }
+  };
+  if (a.mixo >= 0) emit_all([&](int j, int i) { return mix_lds(a.mixo + 2 * j * M * M, i); });
+  else emit_all([&](int j, int i) { return (a.mix + (size_t)j * M * M)[i]; });
   if (MODE == 0) {
     double v[1] = {res2};
     block_sum<1>(v, sh);
@@ -1261,6 +1285,20 @@ size_t xform_lds_bytes(int M, int L, int TN) {
   return (2 * ((size_t)L * M * (TN / 2) + kPlanePad) + (size_t)L) * sizeof(double);
 }
 
+// LDS offset (doubles, even) of the node transforms staged after `used`
+// bytes, or -1 where they do not fit kMixLdsBytes or would lower the number of
+// workgroups a CU holds (at most five: the transform's register budget);
+// *bytes receives the launch's LDS size.
+int mix_offset(int M, int Lh, size_t used, size_t* bytes) {
+  constexpr size_t kLdsPerCU = 160 * 1024;
+  const size_t mb = (size_t)Lh * M * M * sizeof(double2);
+  const size_t off = (used + 15) / 16 * 16;
+  *bytes = used;
+  if (mb > kMixLdsBytes || kLdsPerCU / (off + mb) < std::min<size_t>(kLdsPerCU / used, 5)) return -1;
+  *bytes = off + mb;
+  return (int)(off / sizeof(double));
+}
+
 // Halo width of the staged residual (the largest |dx| of the taps with dy = 0;
 // none when a tile is a whole row), or -1 where it is not used: a tile must
 // lie inside one grid row, a thread hold at most kStageRows rows l, and the
@@ -1286,7 +1324,8 @@ hipError_t fwd_m(bool adj, bool from_r, bool out_f32, const FwdArgs& a0, int B, 
   FwdArgs a = a0;
   const int hx = (from_r || M > 4) ? -1 : stage_halo(a0, B);
   a.hx = hx > 0 ? hx : 0;
-  const size_t lds = xform_lds_bytes(M, a.L, a.TN) + (size_t)a.L * M * 2 * a.hx * sizeof(double);
+  size_t lds = xform_lds_bytes(M, a.L, a.TN) + (size_t)a.L * M * 2 * a.hx * sizeof(double);
+  a.mixo = mix_offset(M, a.Lh, lds, &lds);
   const int nt = (a.taps.n == 3 || a.taps.n == 5) ? a.taps.n : 0;
 #define AAO_FWD(ADJ, MODE, OV, NT, STG) \
   hipLaunchKernelGGL((k_fwd<M, ADJ, MODE, OV, NT, STG>), grid, dim3(kBlock), lds, st, a)

@@ -115,6 +115,8 @@ struct FwdArgs {
   double dt;
   int L, logL, Lh, TN, logTN;
   int hx;               // halo width of the staged residual (set by the launcher)
+  int mixo;             // LDS offset (doubles) of the staged node transforms, -1: read
+                        // from global memory (set by the launcher)
 };
 
 // Inverse transform + update (row a4).
