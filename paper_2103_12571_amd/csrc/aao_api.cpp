@@ -80,6 +80,25 @@ int ilog2(int64_t v) {
 #ifndef AAO_XCD_BANDS
 #define AAO_XCD_BANDS 1
 #endif
+// Active-system checks of the COCG passes: every AAO_CG_CHECK_EARLY passes up
+// to pass AAO_CG_CHECK_SWITCH, then every AAO_CG_CHECK_LATE, and every
+// AAO_CG_CHECK_SMALL once the small tiles are in use.  A check reads the
+// snapshot the previous one requested, so passes launched after the last
+// system stopped run (exiting at once) until the second check after it:
+// short intervals save those launches, but an interval of one pass makes the
+// host wait on the pass it has just queued and the queue drains.
+#ifndef AAO_CG_CHECK_EARLY
+#define AAO_CG_CHECK_EARLY 2
+#endif
+#ifndef AAO_CG_CHECK_SWITCH
+#define AAO_CG_CHECK_SWITCH 16
+#endif
+#ifndef AAO_CG_CHECK_LATE
+#define AAO_CG_CHECK_LATE 4
+#endif
+#ifndef AAO_CG_CHECK_SMALL
+#define AAO_CG_CHECK_SMALL 2
+#endif
 // LDS budgets (KiB) of the transform over l and of the spatial FFT passes.
 #ifndef AAO_XFORM_LDS_KB
 #define AAO_XFORM_LDS_KB 24
@@ -608,7 +627,7 @@ aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
   LagCheck c;
   aao_status ls = lag_begin(p, c, nsys);
   if (ls != AAO_OK) return ls;
-  int next_check = 4;
+  int next_check = AAO_CG_CHECK_EARLY;
   bool small = false;
   // fused: pass k advances the scalars from pass k-1's sums (pass inner_maxit
   // only records the iteration cap); else a scalar kernel follows each pass
@@ -630,7 +649,6 @@ aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
     if (!a.fused)
       HIPCHK(timed(p, aao::KC_MISC, [&] { return aao::launch_cg_scalars(a, k, nact, p->stream); }));
     if (k + 1 == next_check) {
-      next_check += (k < 16) ? 4 : 8;
       int n;
       aao_status s = lag_check(c, nact, a.sys_list, n, false, a.fused != 0);
       if (s != AAO_OK) return s;
@@ -641,6 +659,7 @@ aao_status inner_solve_cg(aao_plan* p, int adj, int nsys) {
         cg_tiling(a, p, true);
         small = true;
       }
+      next_check += small ? AAO_CG_CHECK_SMALL : (k < AAO_CG_CHECK_SWITCH ? AAO_CG_CHECK_EARLY : AAO_CG_CHECK_LATE);
     }
   }
   if (c.deferred >= 0) {  // requested after the last pass: no pass takes it
