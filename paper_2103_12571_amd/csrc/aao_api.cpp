@@ -99,6 +99,15 @@ int ilog2(int64_t v) {
 #ifndef AAO_CG_CHECK_SMALL
 #define AAO_CG_CHECK_SMALL 2
 #endif
+// The same for the chunked BiCGStab (three launches per iteration): every
+// AAO_BICG_CHECK_EARLY iterations up to iteration AAO_CG_CHECK_SWITCH, then
+// every AAO_BICG_CHECK_LATE.
+#ifndef AAO_BICG_CHECK_EARLY
+#define AAO_BICG_CHECK_EARLY 2
+#endif
+#ifndef AAO_BICG_CHECK_LATE
+#define AAO_BICG_CHECK_LATE 4
+#endif
 // LDS budgets (KiB) of the transform over l and of the spatial FFT passes.
 #ifndef AAO_XFORM_LDS_KB
 #define AAO_XFORM_LDS_KB 24
@@ -752,7 +761,7 @@ aao_status inner_solve(aao_plan* p, int adj, int nsys) {
   LagCheck c;
   aao_status ls = lag_begin(p, c, nsys);
   if (ls != AAO_OK) return ls;
-  int next_check = 4;
+  int next_check = AAO_BICG_CHECK_EARLY;
   for (int k = 0; k <= p->inner_maxit; ++k) {
     HIPCHK(timed(p, aao::KC_BICG_1, [&] { return phase(1, k, nact); }));
     if (k < p->inner_maxit) {
@@ -761,7 +770,7 @@ aao_status inner_solve(aao_plan* p, int adj, int nsys) {
       a.wps_rho = a.wps;  // rho_{k+1} and ||r_{k+1}||^2 were written by a.wps chunks
     }
     if (k + 1 == next_check) {
-      next_check += (k < 16) ? 4 : 8;
+      next_check += (k < AAO_CG_CHECK_SWITCH) ? AAO_BICG_CHECK_EARLY : AAO_BICG_CHECK_LATE;
       int n;
       aao_status s = lag_check(c, nact, a.sys_list, n, false);
       if (s != AAO_OK) return s;
