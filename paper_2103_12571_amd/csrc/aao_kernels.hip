@@ -508,7 +508,13 @@ __global__ __launch_bounds__(kBlock) void k_bwd(BwdArgs a) {
   }
   lds_fft<true>(cre, cim, twr, twi, L, a.logL, ncol);
 
-  // as in k_fwd every row lm this thread visits is at the same spatial point
+  // as in k_fwd every row lm this thread visits is at the same spatial point.
+  // Its rows are taken in batches of kUpdRows, each read whole before any of
+  // it is written: row by row, each load of u would wait for the previous
+  // row's store (the compiler cannot tell the rows apart), one memory round
+  // trip per row.  (A thread has at most 12 rows, L M TN <= 3072, unless TN
+  // is at its minimum of 2; eight rows per batch keep the register count of
+  // the transform.)
   const int lmon = ADJ ? 0 : L - 1;
   double dmax = 0.0;
   const int nl = threadIdx.x & (TN - 1);
@@ -516,13 +522,36 @@ __global__ __launch_bounds__(kBlock) void k_bwd(BwdArgs a) {
   if (n < N) {
     const double* src = ((nl & 1) ? cim : cre) + (nl >> 1);
     double* ub = a.u + (size_t)b * L * M * N + n;  // this instance's u at point n
-    for (int lm = threadIdx.x >> a.logTN; lm < L * M; lm += (kBlock >> a.logTN)) {
-      const int l = lm / M;
-      const double d = src[lm * P] * a.scale[l];
-      double* o = ub + (size_t)lm * N;
-      if (MODE == 0) *o += d;
-      else *o = d;
-      if (l == lmon) dmax = fmax(dmax, fabs(d));
+    const int step = kBlock >> a.logTN;
+    constexpr int kUpdRows = 8;
+    for (int lm0 = threadIdx.x >> a.logTN; lm0 < L * M; lm0 += kUpdRows * step) {
+      // the scales first, then u (loads complete in order: waiting for a
+      // scale then leaves every u load in flight)
+      double d[kUpdRows], uo[kUpdRows];
+#pragma unroll
+      for (int i = 0; i < kUpdRows; ++i) {
+        const int lm = lm0 + i * step;
+        d[i] = (lm < L * M) ? a.scale[lm / M] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < kUpdRows; ++i) {
+        const int lm = lm0 + i * step;
+        uo[i] = (MODE == 0 && lm < L * M) ? ub[(size_t)lm * N] : 0.0;
+      }
+      // all results before the first store (each guarded store would
+      // otherwise wait for every memory operation issued before it)
+#pragma unroll
+      for (int i = 0; i < kUpdRows; ++i) {
+        const int lm = lm0 + i * step;
+        d[i] = (lm < L * M) ? src[lm * P] * d[i] : 0.0;
+        if (lm < L * M && lm / M == lmon) dmax = fmax(dmax, fabs(d[i]));
+        uo[i] = (MODE == 0) ? uo[i] + d[i] : d[i];
+      }
+#pragma unroll
+      for (int i = 0; i < kUpdRows; ++i) {
+        const int lm = lm0 + i * step;
+        if (lm < L * M) ub[(size_t)lm * N] = uo[i];
+      }
     }
   }
   dmax = block_max(dmax, sh);
