@@ -543,9 +543,10 @@ __global__ __launch_bounds__(kBlock) void k_bwd(BwdArgs a) {
 #pragma unroll
       for (int i = 0; i < kUpdRows; ++i) {
         const int lm = lm0 + i * step;
-        d[i] = (lm < L * M) ? src[lm * P] * d[i] : 0.0;
-        if (lm < L * M && lm / M == lmon) dmax = fmax(dmax, fabs(d[i]));
-        uo[i] = (MODE == 0) ? uo[i] + d[i] : d[i];
+        const double sv = (lm < L * M) ? src[lm * P] : 0.0;
+        const double dd = sv * d[i];  // delta (d holds the scale here)
+        if (lm < L * M && lm / M == lmon) dmax = fmax(dmax, fabs(dd));
+        uo[i] = (MODE == 0) ? fma(sv, d[i], uo[i]) : dd;  // u + delta in one rounding
       }
 #pragma unroll
       for (int i = 0; i < kUpdRows; ++i) {
