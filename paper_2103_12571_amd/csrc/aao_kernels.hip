@@ -33,6 +33,9 @@ using namespace dev;
 // planes with the scaled rows.  The arithmetic is that of the unstaged loop,
 // operation for operation.
 constexpr int kStageRows = 4;  // rows l per thread: L TN <= kStageRows kBlock
+#ifndef AAO_FWD_STG_WAVES
+#define AAO_FWD_STG_WAVES 5  // waves per SIMD asked for the staged forward transform
+#endif
 
 // The per-frequency node transforms [Lh][M][M] are copied to LDS (at double
 // offset mixo, real and imaginary parts side by side) where they fit
@@ -68,15 +71,23 @@ __device__ __forceinline__ void stage_residual(const FwdArgs& a, int b, int n0, 
   const int own = ((nl & 1) ? cim_off : 0) + (nl >> 1);
   const double* ub = a.u + (size_t)b * L * M * N;
 
-  // phase 1: the tile and its halo
+  // phase 1: the tile and its halo (the tile's loads all issued before the
+  // first LDS store: row by row each row's loads waited for the previous
+  // row's stores)
+  double cv[kStageRows][M];
+#pragma unroll
+  for (int i = 0; i < kStageRows; ++i) {
+    const int l = l0 + i * step;
+#pragma unroll
+    for (int m = 0; m < M; ++m) cv[i][m] = (l < L) ? ub[((size_t)l * M + m) * N + n] : 0.0;
+  }
 #pragma unroll
   for (int i = 0; i < kStageRows; ++i) {
     const int l = l0 + i * step;
     if (l < L) {
       const int lr = bitrev(l, a.logL);
-      const double* ul = ub + (size_t)l * M * N + n;
 #pragma unroll
-      for (int m = 0; m < M; ++m) lds[own + (lr * M + m) * P] = ul[(size_t)m * N];
+      for (int m = 0; m < M; ++m) lds[own + (lr * M + m) * P] = cv[i][m];
     }
   }
   const int hw = 2 * hx;
@@ -209,7 +220,7 @@ __device__ __forceinline__ void stage_residual(const FwdArgs& a, int b, int n0, 
 template <int M, bool ADJ, int MODE, typename OutV, int NT, bool STG>
 // The staged form asks for five waves per SIMD (at most 96 VGPRs; the
 // unstaged form is left to the compiler, which takes about 100).
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(STG ? 5 : 1)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(STG ? AAO_FWD_STG_WAVES : 1)))
 void k_fwd(FwdArgs a) {
   extern __shared__ double lds[];
   const int TN = a.TN, P = TN >> 1, L = a.L, N = a.g.N;
