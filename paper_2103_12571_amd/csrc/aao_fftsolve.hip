@@ -41,6 +41,28 @@ __device__ __forceinline__ int padi(int i) { return i + (i >> 3); }
 // a / b for a >= 0, b > 0 (unsigned: a power-of-two constant b is a shift)
 __device__ __forceinline__ int udiv(int a, int b) { return (int)((unsigned)a / (unsigned)b); }
 
+// Copy elements i = threadIdx.x + nth j (i < tot) of global memory into LDS,
+// kLdBatch per thread at a time: every load of a batch is issued before the
+// first LDS store (a loop of load-then-store waits out one memory round trip
+// per element).  get(i) loads element i, put(i, v) stores it.
+constexpr int kLdBatch = 8;
+template <typename V, typename Get, typename Put>
+__device__ __forceinline__ void load_to_lds(int tot, int nth, const Get& get, const Put& put) {
+  for (int i0 = threadIdx.x; i0 < tot; i0 += kLdBatch * nth) {
+    V v[kLdBatch];
+#pragma unroll
+    for (int j = 0; j < kLdBatch; ++j) {
+      const int i = i0 + j * nth;
+      v[j] = (i < tot) ? get(i) : vzero<V>();
+    }
+#pragma unroll
+    for (int j = 0; j < kLdBatch; ++j) {
+      const int i = i0 + j * nth;
+      if (i < tot) put(i, v[j]);
+    }
+  }
+}
+
 // v e^{2 pi i e / 8} for e in 0 .. 3 (the roots of unity that separate the
 // twiddles of one group).
 __device__ __forceinline__ double2 root8_mul(double2 v, int e) {
@@ -284,10 +306,10 @@ __global__ __launch_bounds__(kBlock) void k_fft_rows(FftArgs a) {
   }
   // natural order in and out: the forward rows (DIF) leave the spectrum in
   // bit-reversed order, which the inverse rows (DIT) take
-  for (int i = threadIdx.x; i < tot; i += kBlock) {
+  load_to_lds<V>(tot, kBlock, [&](int i) { return in[i]; }, [&](int i, V v) {
     const int r = i / nx, x = i - r * nx;
-    c.st(r * ls + padi(x), in[i]);
-  }
+    c.st(r * ls + padi(x), v);
+  });
   if (MODE == 1) {
     dit_passes<V, true, false>(c, a.Wx, nx, a.lognx, 0, rows, ls, 1, kBlock);
     __syncthreads();
@@ -349,10 +371,13 @@ __global__ __launch_bounds__(1024) void k_fft_cols(FftArgs a) {
   }
   // forward (DIF) leaves row y of the tile at frequency ky = bitrev(y); the
   // inverse (DIT) takes that order back to natural
-  for (int i = threadIdx.x; i < tot; i += CB) {
+  load_to_lds<V>(tot, CB, [&](int i) {
     const int y = udiv(i, cols), col = i - y * cols;
-    c.st(padi(y) * cols + col, base[(size_t)y * nx + col]);
-  }
+    return base[(size_t)y * nx + col];
+  }, [&](int i, V v) {
+    const int y = udiv(i, cols), col = i - y * cols;
+    c.st(padi(y) * cols + col, v);
+  });
   const double2 sh = a.shift[s];
   dif_passes<V, false, true>(c, a.Wy, ny, a.logny, 0, cols, 1, cols, CB);
   __syncthreads();
