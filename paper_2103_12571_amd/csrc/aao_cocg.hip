@@ -246,21 +246,31 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
   const TileGeo G = tile_geo(a, tile);
   const V* Rb = reinterpret_cast<const V*>(a.R[0]) + (size_t)s * a.g.N;
   const LdsCplx<V> Bt(smem, G.PW * G.PH);
-  V bi[NI];
+  // every value of the tile and its ring formed before the first LDS store
+  // (point by point each point's loads waited for the previous point's
+  // store); ring indices are always in range, so their loads need no guard
+  V bi[NI], bh[NH > 0 ? NH : 1];
+  int bl[NI], hl[NH > 0 ? NH : 1];
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
-    int g, l, q;
+    int g, q;
     bool own;
-    tile_slot(a, G, t, j, g, l, q, own);
+    tile_slot(a, G, t, j, g, bl[j], q, own);
     bi[j] = Rb[g];
-    if (l >= 0) Bt.st(l, bi[j]);
   }
 #pragma unroll
   for (int j = 0; j < NH; ++j) {
     int g, l, q;
     ring_slot(a, G, t, j, g, l, q);
-    if (q >= 0) Bt.st(l, Rb[g]);  // the one-hop ring is enough for one stencil
+    bh[j] = Rb[g];
+    hl[j] = (q >= 0) ? l : -1;  // the one-hop ring is enough for one stencil
   }
+#pragma unroll
+  for (int j = 0; j < NI; ++j)
+    if (bl[j] >= 0) Bt.st(bl[j], bi[j]);
+#pragma unroll
+  for (int j = 0; j < NH; ++j)
+    if (hl[j] >= 0) Bt.st(hl[j], bh[j]);
   __syncthreads();
   const V sft = from_d2<V>(a.shift[s]);
   double v[kQ] = {0, 0, 0, 0, 0};
@@ -644,25 +654,44 @@ __global__ __launch_bounds__(kBlock) void k_bicg_t1(CgArgs g, KrylovArgs a, int 
     bt = from_d2<V>(cmul(cdiv(rho, st->rho), cdiv(st->alpha, st->omega)));
     om = from_d2<V>(st->omega);
   }
-  // p at a point (k = 0: r)
-  auto pval = [&](int i) { return k == 0 ? R[i] : vadd(R[i], vmul(bt, vsub(Po[i], vmul(om, Vo[i])))); };
+  // p at a point (k = 0: r) from its r, p_{k-1}, v_{k-1}; the three loads are
+  // made whatever k is (the buffers always exist), so that every point's
+  // loads can be in flight together
+  struct Prv { V r, po, vo; };
+  auto pload = [&](int i) { return Prv{R[i], Po[i], Vo[i]}; };
+  auto pform = [&](const Prv& x) { return k == 0 ? x.r : vadd(x.r, vmul(bt, vsub(x.po, vmul(om, x.vo)))); };
   const TileGeo G = tile_geo(g, tile);
   const LdsCplx<V> Pt(smem, G.PW * G.PH);
-  V pv[NI];
+  // every value of the tile and its ring formed before the first LDS store
+  // (point by point each point's loads waited for the previous point's
+  // store); ring indices are always in range, so their loads need no guard
+  Prv xi[NI], xh[NH > 0 ? NH : 1];
+  int pl[NI], hl[NH > 0 ? NH : 1];
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
-    int gi, l, q;
+    int gi, q;
     bool own;
-    tile_slot(g, G, t, j, gi, l, q, own);
-    pv[j] = pval(gi);
-    if (l >= 0) Pt.st(l, pv[j]);
+    tile_slot(g, G, t, j, gi, pl[j], q, own);
+    xi[j] = pload(gi);
   }
 #pragma unroll
   for (int j = 0; j < NH; ++j) {
     int gi, l, q;
     ring_slot(g, G, t, j, gi, l, q);
-    if (q >= 0) Pt.st(l, pval(gi));  // one stencil: the one-hop ring is enough
+    xh[j] = pload(gi);
+    hl[j] = (q >= 0) ? l : -1;  // one stencil: the one-hop ring is enough
   }
+  V pv[NI], ph[NH > 0 ? NH : 1];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) pv[j] = pform(xi[j]);
+#pragma unroll
+  for (int j = 0; j < NH; ++j) ph[j] = pform(xh[j]);
+#pragma unroll
+  for (int j = 0; j < NI; ++j)
+    if (pl[j] >= 0) Pt.st(pl[j], pv[j]);
+#pragma unroll
+  for (int j = 0; j < NH; ++j)
+    if (hl[j] >= 0) Pt.st(hl[j], ph[j]);
   __syncthreads();
   double hv_re = 0, hv_im = 0, bb = 0;
 #pragma unroll
@@ -741,21 +770,31 @@ __global__ __launch_bounds__(kBlock) void k_bicg_t2(CgArgs g, KrylovArgs a, int 
   auto sval = [&](int i) { return vsub(R[i], vmul(av, Vc[i])); };
   const TileGeo G = tile_geo(g, tile);
   const LdsCplx<V> St(smem, G.PW * G.PH);
-  V sv[NI];
+  // every value of the tile and its ring formed before the first LDS store
+  // (point by point each point's loads waited for the previous point's
+  // store); ring indices are always in range, so their loads need no guard
+  V sv[NI], sh2[NH > 0 ? NH : 1];
+  int sl[NI], hl[NH > 0 ? NH : 1];
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
-    int gi, l, q;
+    int gi, q;
     bool own;
-    tile_slot(g, G, t, j, gi, l, q, own);
+    tile_slot(g, G, t, j, gi, sl[j], q, own);
     sv[j] = sval(gi);
-    if (l >= 0) St.st(l, sv[j]);
   }
 #pragma unroll
   for (int j = 0; j < NH; ++j) {
     int gi, l, q;
     ring_slot(g, G, t, j, gi, l, q);
-    if (q >= 0) St.st(l, sval(gi));
+    sh2[j] = sval(gi);
+    hl[j] = (q >= 0) ? l : -1;
   }
+#pragma unroll
+  for (int j = 0; j < NI; ++j)
+    if (sl[j] >= 0) St.st(sl[j], sv[j]);
+#pragma unroll
+  for (int j = 0; j < NH; ++j)
+    if (hl[j] >= 0) St.st(hl[j], sh2[j]);
   __syncthreads();
   double ts_re = 0, ts_im = 0, tt = 0;
 #pragma unroll
