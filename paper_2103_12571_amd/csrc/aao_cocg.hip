@@ -248,21 +248,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
   const LdsCplx<V> Bt(smem, G.PW * G.PH);
   // every value of the tile and its ring formed before the first LDS store
   // (point by point each point's loads waited for the previous point's
-  // store); ring indices are always in range, so their loads need no guard
+  // store); a ring slot outside the one-hop ring loads the thread's first
+  // tile point instead (a cache hit), so no load needs a guard
   V bi[NI], bh[NH > 0 ? NH : 1];
-  int bl[NI], hl[NH > 0 ? NH : 1];
+  int bl[NI], hl[NH > 0 ? NH : 1], g0 = 0;
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
     int g, q;
     bool own;
     tile_slot(a, G, t, j, g, bl[j], q, own);
     bi[j] = Rb[g];
+    if (j == 0) g0 = g;
   }
 #pragma unroll
   for (int j = 0; j < NH; ++j) {
     int g, l, q;
     ring_slot(a, G, t, j, g, l, q);
-    bh[j] = Rb[g];
+    bh[j] = Rb[q >= 0 ? g : g0];
     hl[j] = (q >= 0) ? l : -1;  // the one-hop ring is enough for one stencil
   }
 #pragma unroll
@@ -664,21 +666,23 @@ __global__ __launch_bounds__(kBlock) void k_bicg_t1(CgArgs g, KrylovArgs a, int 
   const LdsCplx<V> Pt(smem, G.PW * G.PH);
   // every value of the tile and its ring formed before the first LDS store
   // (point by point each point's loads waited for the previous point's
-  // store); ring indices are always in range, so their loads need no guard
+  // store); a ring slot outside the one-hop ring loads the thread's first
+  // tile point instead (a cache hit), so no load needs a guard
   Prv xi[NI], xh[NH > 0 ? NH : 1];
-  int pl[NI], hl[NH > 0 ? NH : 1];
+  int pl[NI], hl[NH > 0 ? NH : 1], g0 = 0;
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
     int gi, q;
     bool own;
     tile_slot(g, G, t, j, gi, pl[j], q, own);
     xi[j] = pload(gi);
+    if (j == 0) g0 = gi;
   }
 #pragma unroll
   for (int j = 0; j < NH; ++j) {
     int gi, l, q;
     ring_slot(g, G, t, j, gi, l, q);
-    xh[j] = pload(gi);
+    xh[j] = pload(q >= 0 ? gi : g0);
     hl[j] = (q >= 0) ? l : -1;  // one stencil: the one-hop ring is enough
   }
   V pv[NI], ph[NH > 0 ? NH : 1];
@@ -772,21 +776,23 @@ __global__ __launch_bounds__(kBlock) void k_bicg_t2(CgArgs g, KrylovArgs a, int 
   const LdsCplx<V> St(smem, G.PW * G.PH);
   // every value of the tile and its ring formed before the first LDS store
   // (point by point each point's loads waited for the previous point's
-  // store); ring indices are always in range, so their loads need no guard
+  // store); a ring slot outside the one-hop ring loads the thread's first
+  // tile point instead (a cache hit), so no load needs a guard
   V sv[NI], sh2[NH > 0 ? NH : 1];
-  int sl[NI], hl[NH > 0 ? NH : 1];
+  int sl[NI], hl[NH > 0 ? NH : 1], g0 = 0;
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
     int gi, q;
     bool own;
     tile_slot(g, G, t, j, gi, sl[j], q, own);
     sv[j] = sval(gi);
+    if (j == 0) g0 = gi;
   }
 #pragma unroll
   for (int j = 0; j < NH; ++j) {
     int gi, l, q;
     ring_slot(g, G, t, j, gi, l, q);
-    sh2[j] = sval(gi);
+    sh2[j] = sval(q >= 0 ? gi : g0);
     hl[j] = (q >= 0) ? l : -1;
   }
 #pragma unroll
